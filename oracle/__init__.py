@@ -1,0 +1,298 @@
+"""CPU oracle for the wavefront path-guiding hot path (test infrastructure).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The GPU library never calls it and shares no code with it.
+The arithmetic lives in ``oracle.c`` (plain C, FP64 values, exact integer
+traversal, FP32 only where an integer decision is taken in the paper's FP32);
+this module only marshals numpy arrays through ctypes.
+
+Parity unpinned: none of the functions below. Every function is pinned by a
+test in ``tests/test_oracle_*.py`` against closed forms, brute force or
+invariants that do not reuse this code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+FMT_FP32, FMT_FP16, FMT_BF16 = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (FP contraction off)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
+            _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        vp, i32, i64, u32, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
+        sig = {
+            "orc_build": (vp, [vp, i64, i32, vp]),
+            "orc_free": (None, [vp]),
+            "orc_depth": (i32, [vp]),
+            "orc_level_size": (i64, [vp, i32]),
+            "orc_level_keys": (None, [vp, i32, vp]),
+            "orc_level_normals": (None, [vp, i32, vp]),
+            "orc_level_exitance": (None, [vp, i32, vp, vp]),
+            "orc_leaf_info": (None, [vp, vp, vp]),
+            "orc_leaf_accum": (None, [vp, vp, vp, vp]),
+            "orc_dropped": (i64, [vp]),
+            "orc_set_uniform_exitance": (None, [vp, f32]),
+            "orc_accumulate": (i64, [vp, vp, vp, vp, i64]),
+            "orc_propagate": (None, [vp, i32]),
+            "orc_morton": (u32, [u32, u32, u32]),
+            "orc_oct_decode": (None, [C.c_double, C.c_double, vp]),
+            "orc_oct_encode": (None, [C.c_double, C.c_double, C.c_double, vp]),
+            "orc_dir_table": (None, [i32, vp]),
+            "orc_philox": (None, [vp, vp, vp]),
+            "orc_debug_march": (None, [vp, vp, i64, i32, i32, i32, vp, vp]),
+            "orc_field": (None, [vp, vp, i64, i32, f32, vp, vp]),
+            "orc_guide_pdf": (None, [vp, vp, i64, i32, f32, vp, vp]),
+            "orc_guide_sample": (None, [vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp]),
+            "orc_pdf_eval": (None, [vp, vp, vp, i64, i32, f32, vp, vp, vp]),
+            "orc_march_one": (None, [vp, vp, vp, i32, i32, vp]),
+            "orc_quantize": (None, [vp, vp, vp, vp]),
+            "orc_round_fmt_array": (None, [vp, vp, i64, i32]),
+            "orc_eval_one": (None, [vp, vp, vp, i32, vp, vp]),
+            "orc_oct_encode_many": (None, [vp, i64, vp]),
+            "orc_oct_decode_many": (None, [vp, i64, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _soa(a, dtype=np.float32):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    assert a.ndim == 2 and a.shape[0] == 3
+    return a
+
+
+def morton(x: int, y: int, z: int) -> int:
+    return int(lib().orc_morton(x, y, z))
+
+
+def oct_decode(x: float, y: float) -> np.ndarray:
+    out = np.zeros(3)
+    lib().orc_oct_decode(x, y, _p(out))
+    return out
+
+
+def oct_encode(d) -> np.ndarray:
+    out = np.zeros(2)
+    lib().orc_oct_encode(float(d[0]), float(d[1]), float(d[2]), _p(out))
+    return out
+
+
+def oct_encode_many(d) -> np.ndarray:
+    """(3, n) directions -> (2, n) square coordinates."""
+    d = np.ascontiguousarray(d, np.float64)
+    out = np.zeros((2, d.shape[1]))
+    lib().orc_oct_encode_many(_p(d), d.shape[1], _p(out))
+    return out
+
+
+def oct_decode_many(xy) -> np.ndarray:
+    """(2, n) square coordinates -> (3, n) unit directions."""
+    xy = np.ascontiguousarray(xy, np.float64)
+    out = np.zeros((3, xy.shape[1]))
+    lib().orc_oct_decode_many(_p(xy), xy.shape[1], _p(out))
+    return out
+
+
+def dir_table(N: int) -> np.ndarray:
+    """(N*N, 3) float32 bin-centre directions, bin b = v*N + u."""
+    out = np.zeros((N * N, 3), np.float32)
+    lib().orc_dir_table(N, _p(out))
+    return out
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().orc_philox(_p(c), _p(k), _p(o))
+    return o
+
+
+def round_fmt(x, fmt: int) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32).ravel()
+    out = np.empty_like(x)
+    lib().orc_round_fmt_array(_p(x), _p(out), x.size, fmt)
+    return out
+
+
+def quantize(p, d):
+    p = np.ascontiguousarray(p, np.float32)
+    d = np.ascontiguousarray(d, np.float32)
+    O = np.zeros(3, np.int64)
+    q = np.zeros(3, np.int64)
+    lib().orc_quantize(_p(p), _p(d), _p(O), _p(q))
+    return O, q
+
+
+class SVO:
+    """Oracle sparse voxel octree built from axis-aligned rectangles."""
+
+    def __init__(self, rects: np.ndarray, depth: int):
+        self._rects = np.ascontiguousarray(rects)
+        assert self._rects.dtype.itemsize == 32
+        st = C.c_int32(0)
+        h = lib().orc_build(_p(self._rects), len(self._rects), depth, C.byref(st))
+        if not h:
+            raise ValueError(f"orc_build failed with status {st.value}")
+        self._h = h
+        self.depth = depth
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_free(h)
+            self._h = None
+
+    def level_size(self, l: int) -> int:
+        return int(lib().orc_level_size(self._h, l))
+
+    def level_sizes(self):
+        return [self.level_size(l) for l in range(self.depth + 1)]
+
+    def keys(self, l: int) -> np.ndarray:
+        out = np.zeros(self.level_size(l), np.uint32)
+        lib().orc_level_keys(self._h, l, _p(out))
+        return out
+
+    def normals(self, l: int) -> np.ndarray:
+        out = np.zeros((self.level_size(l), 3), np.float32)
+        lib().orc_level_normals(self._h, l, _p(out))
+        return out
+
+    def exitance(self, l: int):
+        n = self.level_size(l)
+        e32 = np.zeros((n, 2), np.float32)
+        e64 = np.zeros((n, 2), np.float64)
+        lib().orc_level_exitance(self._h, l, _p(e32), _p(e64))
+        return e32, e64
+
+    def leaf_info(self):
+        L = self.level_size(self.depth)
+        xyz = np.zeros((L, 3), np.int32)
+        em = np.zeros(L, np.uint8)
+        lib().orc_leaf_info(self._h, _p(xyz), _p(em))
+        return xyz, em
+
+    def leaf_accum(self):
+        L = self.level_size(self.depth)
+        s32 = np.zeros((L, 2), np.float32)
+        s64 = np.zeros((L, 2), np.float64)
+        cnt = np.zeros((L, 2), np.int64)
+        lib().orc_leaf_accum(self._h, _p(s32), _p(s64), _p(cnt))
+        return s32, s64, cnt
+
+    def dropped(self) -> int:
+        return int(lib().orc_dropped(self._h))
+
+    def set_uniform_exitance(self, v: float):
+        lib().orc_set_uniform_exitance(self._h, v)
+
+    def accumulate(self, pos, wo, rgb) -> int:
+        pos, wo, rgb = _soa(pos), _soa(wo), _soa(rgb)
+        return int(lib().orc_accumulate(self._h, _p(pos), _p(wo), _p(rgb), pos.shape[1]))
+
+    def propagate(self, fmt: int = FMT_FP32):
+        lib().orc_propagate(self._h, fmt)
+
+    def march_one(self, p, d, hier=False, lds_levels=5):
+        p = np.ascontiguousarray(p, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        out = np.zeros(5, np.int64)
+        lib().orc_march_one(self._h, _p(p), _p(d), int(hier), lds_levels, _p(out))
+        return dict(hit=int(out[0]), axis=int(out[1]), key=int(out[2]), delta=int(out[3]),
+                    visits=int(out[4]))
+
+    def eval_one(self, p, d, N: int):
+        p = np.ascontiguousarray(p, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        out = np.zeros(8, np.int64)
+        val = np.zeros(2)
+        lib().orc_eval_one(self._h, _p(p), _p(d), N, _p(out), _p(val))
+        keys = ("hit", "axis", "leaf", "delta", "k", "node", "node_index", "side")
+        rec = {k: int(v) for k, v in zip(keys, out)}
+        rec["value"], rec["r"] = float(val[0]), float(val[1])
+        return rec
+
+    def debug_march(self, pos, N: int, lds_levels: int = 5, hier: bool = False,
+                    visits: bool = False):
+        """(n, N*N, 8) int64 records {hit, axis, leaf, delta, k, node, node_index,
+        side} and optionally (n, N*N) node-test counts."""
+        pos = _soa(pos)
+        n = pos.shape[1]
+        out = np.zeros((n, N * N, 8), np.int64)
+        vis = np.zeros((n, N * N), np.int64) if visits else None
+        lib().orc_debug_march(self._h, _p(pos), n, N, lds_levels, int(hier), _p(out),
+                              _p(vis) if visits else None)
+        return (out, vis) if visits else out
+
+    def field(self, pos, N: int, eps: float = 0.01):
+        pos = _soa(pos)
+        n = pos.shape[1]
+        L = np.zeros((n, N * N))
+        Lt = np.zeros((n, N * N))
+        lib().orc_field(self._h, _p(pos), n, N, eps, _p(L), _p(Lt))
+        return L, Lt
+
+    def guide_pdf(self, pos, N: int, eps: float = 0.01, truth: bool = False):
+        pos = _soa(pos)
+        n = pos.shape[1]
+        pdf = np.zeros((n, N * N))
+        pt = np.zeros((n, N * N)) if truth else None
+        lib().orc_guide_pdf(self._h, _p(pos), n, N, eps, _p(pdf), _p(pt) if truth else None)
+        return (pdf, pt) if truth else pdf
+
+    def guide_sample(self, pos, N: int, seed: int, bounce: int, eps: float = 0.01):
+        pos = _soa(pos)
+        n = pos.shape[1]
+        d = np.zeros((3, n))
+        pdf = np.zeros(n)
+        b = np.zeros((n, 2), np.int32)
+        m = np.zeros((n, 2))
+        lib().orc_guide_sample(self._h, _p(pos), n, seed, bounce, N, eps, _p(d), _p(pdf),
+                               _p(b), _p(m))
+        return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+    def pdf_eval(self, pos, dirs, N: int, eps: float = 0.01):
+        pos = _soa(pos)
+        dirs = _soa(dirs)
+        n = pos.shape[1]
+        pdf = np.zeros(n)
+        b = np.zeros((n, 2), np.int32)
+        e = np.zeros(n)
+        lib().orc_pdf_eval(self._h, _p(pos), _p(dirs), n, N, eps, _p(pdf), _p(b), _p(e))
+        return dict(pdf=pdf, bin=b, edge=e)
