@@ -1,0 +1,249 @@
+/*
+ * wfpg.h -- C ABI of the wavefront path-guiding library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library implements the guiding hot path of Yalciner & Akyuz, "Path
+ * Guiding for Wavefront Path Tracing: A Memory Efficient Approach for GPU Path
+ * Tracers" (2024): a sparse voxel octree (SVO) caches radiant exitance
+ * (Sec. 3.2); at a path vertex an N x N field of equal solid-angle directions
+ * (Sec. 3.3) is traced through the SVO, turned into a piecewise-constant PDF
+ * and CDF (Sec. 3.5, Alg. 3) and sampled.
+ *
+ * Conventions shared by every entry point:
+ *  - World space is the unit cube [0,1]^3. Positions outside it are invalid
+ *    for guiding and are dropped by svo_accumulate.
+ *  - Device arrays are caller-owned, FP32, structure-of-arrays: a "3 x n"
+ *    array holds n x-values, then n y-values, then n z-values, contiguous.
+ *  - Every call validates its arguments synchronously and returns a negative
+ *    wfpg_status on error, without touching any device memory. Work is
+ *    enqueued asynchronously on the given HIP stream (NULL = default stream);
+ *    a device fault surfaces as WFPG_EDEVICE from a later call or from
+ *    svo_stats. n == 0 is a no-op that returns WFPG_OK. No C++ exception
+ *    crosses this interface. No function keeps a caller pointer after it
+ *    returns.
+ *  - Directions are unit vectors in world space: the field is omnidirectional
+ *    (Sec. 3.7 / Fig. 5 discussion), mapped to the square by the equal-area
+ *    concentric octahedral map (Sec. 4, "Radiance field projection"), square
+ *    centre = +z. Bin (u, v) covers x in [u/N, (u+1)/N), y in [v/N, (v+1)/N);
+ *    rows are v and the flat bin index is b = v*N + u.
+ *  - Returned pdfs are solid-angle densities in 1/sr (Eq. 2).
+ *  - Concurrency: guide_pdf, guide_sample, pdf_eval and wfpg_debug_march only
+ *    read the SVO and may run concurrently; svo_accumulate mutates it and must
+ *    be ordered by the caller (stream order).
+ */
+#ifndef WFPG_H
+#define WFPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wfpg_svo wfpg_svo; /* opaque; owns all of its device memory */
+typedef int32_t wfpg_status;
+
+enum {
+    WFPG_OK = 0,
+    WFPG_EINVAL = -1,      /* invalid argument */
+    WFPG_ENOMEM = -2,      /* device or host allocation failed */
+    WFPG_EDEVICE = -3,     /* HIP runtime error or device-side fault */
+    WFPG_ESTATE = -4,      /* call not valid in the object's current state */
+    WFPG_EUNSUPPORTED = -5 /* valid request this build does not support */
+};
+
+/* Storage format of the exitance and of the field bins (the CDF and pdf are
+ * always accumulated in FP32). */
+enum { WFPG_FP32 = 0, WFPG_FP16 = 1, WFPG_BF16 = 2 };
+
+/* Axis-aligned rectangle: the plane x[axis] == c, spanning [lo[k], hi[k]]
+ * along the other two axes taken in increasing order; normal sign * e_axis.
+ * emissive != 0 marks light sources (used only for statistics). */
+typedef struct {
+    int32_t axis;   /* 0, 1 or 2 */
+    float c;
+    float lo[2], hi[2];
+    int32_t sign;   /* +1 or -1 */
+    int32_t emissive;
+} wfpg_rect;
+
+/* Per-call guiding options.
+ *  N        -- bins per side of the direction field: 8, 16 or 32.
+ *  eps      -- value added to every bin (Sec. 4, "PDF domains": the field
+ *              starts at a nonzero value so the pdf is positive wherever
+ *              radiance may arrive); finite and > 0. Default 0.01.
+ *  mode     -- 0: SVO march. 1: learned model with march fallback
+ *              (requires guide_train first).
+ *  kl_bound -- fallback threshold in nats for mode 1 (default 0.05).
+ *  probe_stride -- every probe_stride-th vertex is also marched to judge the
+ *              learned model in mode 1 (default 256). */
+typedef struct {
+    int32_t N;
+    float eps;
+    int32_t mode;
+    float kl_bound;
+    int32_t probe_stride;
+} wfpg_opts;
+
+/* Default options {16, 0.01f, 0, 0.05f, 256}. */
+wfpg_opts wfpg_default_opts(void);
+
+const char *wfpg_status_string(wfpg_status s);
+
+/* ---------------------------------------------------------------------
+ * svo_build -- SVO generation (Sec. 3.2: conservative voxelization of the
+ * scene, a hierarchy from Morton-sorted voxel keys, and two normals per node
+ * from k-means with k = 2, Fig. 2).
+ *
+ * rects, n_rects: HOST array of rectangles (read during the call only).
+ * depth: leaf level D in [1, 10]; leaves are cells of size 2^-D.
+ * exitance_fmt: WFPG_FP32, WFPG_FP16 or WFPG_BF16 (storage of the exitance
+ *   read by the march and of the field bins).
+ * Voxelization is half-open: along an in-plane axis a rectangle covers the
+ *   cells whose [i, i+1) * 2^-D extent meets the open interval (lo, hi) (the
+ *   single cell holding lo when lo == hi); along its plane axis the cell
+ *   floor(c * 2^D), clamped to 2^D - 1.
+ * Leaf normal: k-means (k = 2) over the fragment normals of the cell in
+ *   rectangle order, seeded with the first fragment's normal and its
+ *   opposite; inner-node normal: the same over the occupied children's
+ *   normals in octant order. The node stores N and -N implicitly.
+ * Errors: EINVAL for depth out of range, n_rects < 0, rects == NULL with
+ *   n_rects > 0, axis not in {0,1,2}, sign not +-1, non-finite or lo > hi
+ *   coordinates, an unknown format, out == NULL. ENOMEM if the device
+ *   arrays cannot be allocated. On success *out owns the device memory;
+ *   the call synchronizes the stream before returning.
+ * ------------------------------------------------------------------- */
+wfpg_status svo_build(const wfpg_rect *rects, int64_t n_rects, int32_t depth,
+                      int32_t exitance_fmt, void *hip_stream, wfpg_svo **out);
+
+/* Frees the SVO and its device memory (synchronizes the device). NULL is a
+ * no-op. */
+void svo_destroy(wfpg_svo *svo);
+
+/* ---------------------------------------------------------------------
+ * svo_accumulate -- UpdateExitance (Alg. 1; Sec. 3.2 after Eq. 5): each
+ * path-vertex splat is mapped to its leaf and its local radiance estimate is
+ * accumulated; then the exitance is averaged bottom-up through the tree.
+ *
+ * pos, wo, rgb: DEVICE 3 x n FP32 (SoA). pos in [0,1]^3; wo the unit
+ *   direction the radiance leaves in (toward the previous path vertex); rgb
+ *   the local radiance estimate (e.g. T_n/T_k * L_e, Eq. 5).
+ * Per splat: y = Rec.709 luminance (0.2126 r + 0.7152 g) + 0.0722 b in FP32;
+ *   leaf = cell of pos; side 0 iff dot(N_leaf, wo) >= 0 else 1; the leaf
+ *   side's sum += y and count += 1 (FP32 / uint32 atomics, so sums of
+ *   several splats depend on arrival order within FP32 rounding). Splats
+ *   with a non-finite component, y < 0, or a position outside [0,1]^3 or in
+ *   an empty leaf are dropped and counted (svo_stats). Sums persist across
+ *   calls (progressive learning).
+ * Then every node is rewritten: leaf side value = sum/count (0 with no
+ *   splats); inner side value = mean, in octant order, over the occupied
+ *   children of the child side facing the same way (child sides swapped
+ *   when dot(N_child, N_parent) < 0), in FP32; stored rounded once (RNE) to
+ *   the SVO's exitance format.
+ * n == 0 still recomputes the averages.
+ * Errors: EINVAL for NULL svo, n < 0, or NULL arrays with n > 0.
+ * ------------------------------------------------------------------- */
+wfpg_status svo_accumulate(wfpg_svo *svo, const float *pos, const float *wo,
+                           const float *rgb, int64_t n, void *hip_stream);
+
+/* ---------------------------------------------------------------------
+ * guide_pdf -- the per-vertex guiding PDF (Alg. 3, ConeTrace for every
+ * direction patch, then GeneratePDF-CDF), written out in full.
+ *
+ * For vertex i (pos DEVICE 3 x n) and bin b with centre direction d_b:
+ *  - quantize: O = clamp(rint(p * 2^30), 0, 2^30 - 1), q = rint(d_b * 2^23);
+ *  - march: the first occupied leaf, other than the one holding p, met by
+ *    the exact 6-connected traversal of the ray (crossings compared exactly,
+ *    ties stepping the lowest axis first); leaving the cube is a miss;
+ *  - footprint (Eq. 7): r = distance to the hit leaf's entry point in leaf
+ *    units (FP32), A = r^2 * 4*pi/N^2, ascend k = #{j in 1..D : A >
+ *    2.5 * 4^(j-1)} levels to the node whose area is closest to A;
+ *  - value: side 0 iff dot(N_node, d_b) < 0 (FP32, fixed order), L_b =
+ *    E[node][side] + eps; a miss gives eps;
+ *  - pdf_b = L_b / sum_b' L_b' * N^2 / (4*pi).
+ * pdf_out: DEVICE n * N * N FP32, row-major [i][v][u].
+ * Errors: EINVAL for NULL svo/pos/opts/pdf_out with n > 0, n < 0, N not in
+ *   {8, 16, 32}, eps not finite and > 0, mode != 0.
+ * ------------------------------------------------------------------- */
+wfpg_status guide_pdf(const wfpg_svo *svo, const float *pos, int64_t n,
+                      const wfpg_opts *opts, float *pdf_out, void *hip_stream);
+
+/* ---------------------------------------------------------------------
+ * guide_sample -- one guided direction per vertex (Alg. 3 sampling step;
+ * inverse-CDF sampling of the piecewise-constant 2D field, Sec. 3.5).
+ *
+ * The field of vertex i is built as in guide_pdf (never written to memory);
+ * uniforms (u1..u4) come from Philox-4x32-10 with counter (i mod 2^32,
+ * i >> 32, bounce, 0) and key (seed mod 2^32, seed >> 32), u = (bits >> 8)
+ * * 2^-24. Row v: first with u1 * total < M_v (M: inclusive prefix of the
+ * row sums); column u: first with u2 * rowsum_v < R_v[u] (R_v: inclusive
+ * prefix of row v); both clamped to N - 1. Direction = octahedral decode of
+ * ((u + u3)/N, (v + u4)/N); its pdf = pdf_b of bin (u, v).
+ * nrm: DEVICE 3 x n surface normals; may be NULL unless opts->mode == 1.
+ * dir_out: DEVICE 3 x n FP32; pdf_out: DEVICE n FP32.
+ * Errors: as guide_pdf; mode 1 without a trained model is ESTATE.
+ * ------------------------------------------------------------------- */
+wfpg_status guide_sample(const wfpg_svo *svo, const float *pos, const float *nrm,
+                         int64_t n, uint64_t seed, uint32_t bounce,
+                         const wfpg_opts *opts, float *dir_out, float *pdf_out,
+                         void *hip_stream);
+
+/* ---------------------------------------------------------------------
+ * pdf_eval -- guiding pdf of given directions (needed to weight guided
+ * samples against BSDF and light samples with MIS, Sec. 4): the direction
+ * is encoded with the octahedral map, its bin taken, and pdf_b returned;
+ * the vertex's field is regenerated (nothing is stored between calls).
+ * pos, dir: DEVICE 3 x n; pdf_out: DEVICE n.
+ * Errors: as guide_pdf.
+ * ------------------------------------------------------------------- */
+wfpg_status pdf_eval(const wfpg_svo *svo, const float *pos, const float *dir,
+                     int64_t n, const wfpg_opts *opts, float *pdf_out,
+                     void *hip_stream);
+
+/* ------------------------------------------------------------ auxiliaries */
+
+/* Occupied leaves, all nodes and dropped splats so far; error_flags != 0
+ * means a kernel hit an internal limit (the last results are invalid).
+ * Any pointer may be NULL. Synchronizes the device. */
+wfpg_status svo_stats(const wfpg_svo *svo, int64_t *leaves, int64_t *nodes,
+                      int64_t *dropped_splats, int32_t *error_flags);
+
+/* Number of nodes at a level (0 = root .. depth = leaves); -1 on error. */
+int64_t svo_level_size(const wfpg_svo *svo, int32_t level);
+
+/* Copies one level to HOST arrays (any may be NULL): sorted Morton keys
+ * (x in bit 3i, y in 3i+1, z in 3i+2), normals (3 floats per node, AoS) and
+ * the exitance of side 0 and 1 (2 floats per node, FP32 values before the
+ * storage rounding). Synchronizes the stream. */
+wfpg_status svo_export_level(const wfpg_svo *svo, int32_t level, uint32_t *keys,
+                             float *normals, float *exitance, void *hip_stream);
+
+/* Copies the leaf accumulators to HOST arrays (either may be NULL): per leaf
+ * 2 FP32 sums and 2 uint32 counts (side 0, side 1). */
+wfpg_status svo_export_accum(const wfpg_svo *svo, float *sums, uint32_t *counts,
+                             void *hip_stream);
+
+/* Name and source location of the last failing HIP call seen by the library
+ * on this thread ("" if none); the string stays valid until the next failure
+ * on the thread. */
+const char *wfpg_last_error(void);
+
+/* Host copy of the FP32 bin-centre direction table the kernels use for
+ * resolution N (N*N*3 floats, AoS, bin b = v*N + u). */
+wfpg_status wfpg_dir_table(int32_t N, float *out);
+
+/* Test-only: the traversal record of every (vertex, bin) pair, for
+ * bit-exact comparison with an independent implementation.
+ * out: DEVICE n * N*N * 8 int32 = {hit, entry axis, leaf key, |B - O| of
+ * the entry crossing (2^-30 units), footprint ascent k, node key, node index
+ * within its level, side}; for a miss every field after hit is -1 except
+ * side (0). visits: DEVICE n * N*N int32 (may be NULL): occupancy tests at
+ * levels >= 5 of the traversal. */
+wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n,
+                             const wfpg_opts *opts, int32_t *out, int32_t *visits,
+                             void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WFPG_H */

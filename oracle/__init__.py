@@ -69,7 +69,7 @@ def lib():
             "orc_debug_march": (None, [vp, vp, i64, i32, i32, i32, vp, vp]),
             "orc_field": (None, [vp, vp, i64, i32, f32, vp, vp]),
             "orc_guide_pdf": (None, [vp, vp, i64, i32, f32, vp, vp]),
-            "orc_guide_sample": (None, [vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp]),
+            "orc_guide_sample": (None, [vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp, vp]),
             "orc_pdf_eval": (None, [vp, vp, vp, i64, i32, f32, vp, vp, vp]),
             "orc_march_one": (None, [vp, vp, vp, i32, i32, vp]),
             "orc_quantize": (None, [vp, vp, vp, vp]),
@@ -276,15 +276,18 @@ class SVO:
         lib().orc_guide_pdf(self._h, _p(pos), n, N, eps, _p(pdf), _p(pt) if truth else None)
         return (pdf, pt) if truth else pdf
 
-    def guide_sample(self, pos, N: int, seed: int, bounce: int, eps: float = 0.01):
+    def guide_sample(self, pos, N: int, seed: int, bounce: int, eps: float = 0.01, counter=None):
+        """counter: RNG counter per vertex (its index in the full queue);
+        defaults to 0..n-1."""
         pos = _soa(pos)
         n = pos.shape[1]
+        ctr = None if counter is None else np.ascontiguousarray(counter, np.int64)
         d = np.zeros((3, n))
         pdf = np.zeros(n)
         b = np.zeros((n, 2), np.int32)
         m = np.zeros((n, 2))
-        lib().orc_guide_sample(self._h, _p(pos), n, seed, bounce, N, eps, _p(d), _p(pdf),
-                               _p(b), _p(m))
+        lib().orc_guide_sample(self._h, _p(pos), n, seed, bounce, N, eps,
+                               _p(ctr) if ctr is not None else None, _p(d), _p(pdf), _p(b), _p(m))
         return dict(dir=d, pdf=pdf, bin=b, margin=m)
 
     def pdf_eval(self, pos, dirs, N: int, eps: float = 0.01):

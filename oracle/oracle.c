@@ -876,10 +876,11 @@ void orc_guide_pdf(const orc_svo *s, const float *pos, int64_t n, int32_t N, flo
  * the octahedral decode of ((u + u3)/N, (v + u4)/N); its pdf is pdf_b.
  * margin[2i], margin[2i+1]: distance of the row / column target to the
  * nearest CDF boundary, relative to the total / row sum (for the tolerance
- * band of the GPU comparison). */
+ * band of the GPU comparison). counter[i] (NULL: i) is the RNG counter of
+ * vertex i, i.e. its index in the caller's full queue. */
 void orc_guide_sample(const orc_svo *s, const float *pos, int64_t n, uint64_t seed,
-                      uint32_t bounce, int32_t N, float eps, double *dir, double *pdf,
-                      int32_t *bin, double *margin)
+                      uint32_t bounce, int32_t N, float eps, const int64_t *counter, double *dir,
+                      double *pdf, int32_t *bin, double *margin)
 {
     int NN = N * N;
     float *tab = malloc(sizeof(float) * 3 * (size_t)NN);
@@ -898,7 +899,7 @@ void orc_guide_sample(const orc_svo *s, const float *pos, int64_t n, uint64_t se
             M[v] = tot;
         }
         double u4[4];
-        uniforms(seed, bounce, i, u4);
+        uniforms(seed, bounce, counter ? counter[i] : i, u4);
         double tv = u4[0] * tot;
         int v = 0;
         while (v < N - 1 && !(tv < M[v])) v++;

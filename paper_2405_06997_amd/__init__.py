@@ -1,0 +1,262 @@
+"""Python binding of libwfpg.so, the MI355X wavefront path-guiding library.
+
+Argument marshalling only: every step of the guiding path runs in the HIP
+kernels behind the C ABI declared in ``include/wfpg.h``. PyTorch supplies
+device memory (tensors) and the current HIP stream. Device arrays are float32
+structure-of-arrays tensors of shape (3, n) (positions, directions, colours)
+or (n,) (pdfs). The entry points keep the C names: ``svo_build``,
+``svo_accumulate``, ``guide_pdf``, ``guide_sample``, ``pdf_eval``.
+
+Importing this module does not load the library; the first call does, and it
+raises ``WfpgLibraryMissing`` if ``libwfpg.so`` has not been built (there is
+no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwfpg.so")
+
+WFPG_FP32, WFPG_FP16, WFPG_BF16 = 0, 1, 2
+FORMATS = {"fp32": WFPG_FP32, "fp16": WFPG_FP16, "bf16": WFPG_BF16}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
+          -4: "invalid state", -5: "unsupported"}
+
+# exported symbols of include/wfpg.h (checked by the CPU test suite)
+EXPORTS = [
+    "wfpg_default_opts", "wfpg_status_string", "svo_build", "svo_destroy", "svo_accumulate",
+    "guide_pdf", "guide_sample", "pdf_eval", "svo_stats", "svo_level_size", "svo_export_level",
+    "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
+]
+
+
+class WfpgLibraryMissing(ImportError):
+    pass
+
+
+class WfpgError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str = ""):
+        msg = f"{fn} failed: {STATUS.get(status, status)} ({status})"
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
+        self.status = status
+
+
+class Opts(C.Structure):
+    _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("mode", C.c_int32),
+                ("kl_bound", C.c_float), ("probe_stride", C.c_int32)]
+
+
+def make_opts(N: int = 16, eps: float = 0.01, mode: int = 0, kl_bound: float = 0.05,
+              probe_stride: int = 256) -> Opts:
+    return Opts(N, eps, mode, kl_bound, probe_stride)
+
+
+_lib = None
+
+
+def lib():
+    """Load libwfpg.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WfpgLibraryMissing(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch ships its own HIP runtime under the same SONAME as /opt/rocm's; loading
+    # torch first makes the dynamic linker bind this library to that one runtime
+    # (two runtimes in one process do not share the device).
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+    sig = {
+        "wfpg_default_opts": (Opts, []),
+        "wfpg_status_string": (C.c_char_p, [i32]),
+        "svo_build": (i32, [vp, i64, i32, i32, vp, C.POINTER(vp)]),
+        "svo_destroy": (None, [vp]),
+        "svo_accumulate": (i32, [vp, vp, vp, vp, i64, vp]),
+        "guide_pdf": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
+        "guide_sample": (i32, [vp, vp, vp, i64, u64, u32, C.POINTER(Opts), vp, vp, vp]),
+        "pdf_eval": (i32, [vp, vp, vp, i64, C.POINTER(Opts), vp, vp]),
+        "svo_stats": (i32, [vp, vp, vp, vp, vp]),
+        "svo_level_size": (i64, [vp, i32]),
+        "svo_export_level": (i32, [vp, i32, vp, vp, vp, vp]),
+        "svo_export_accum": (i32, [vp, vp, vp, vp]),
+        "wfpg_dir_table": (i32, [i32, vp]),
+        "wfpg_last_error": (C.c_char_p, []),
+        "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(fn: str, st: int):
+    if st != 0:
+        detail = lib().wfpg_last_error().decode() if st == -3 or st == -2 else ""
+        raise WfpgError(fn, st, detail)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, shape0=None, name="tensor"):
+    """Device pointer of a contiguous float32/int32 CUDA tensor."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape0 is not None and (t.dim() != 2 or t.shape[0] != shape0):
+        raise ValueError(f"{name} must have shape ({shape0}, n)")
+    return C.c_void_p(t.data_ptr())
+
+
+def dir_table(N: int) -> np.ndarray:
+    """FP32 bin-centre directions used by the kernels, (N*N, 3)."""
+    out = np.zeros((N * N, 3), np.float32)
+    _check("wfpg_dir_table", lib().wfpg_dir_table(N, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+class SVO:
+    """Handle of a device-resident SVO (owns its device memory)."""
+
+    def __init__(self, handle, depth: int, fmt: int):
+        self._h = handle
+        self.depth = depth
+        self.fmt = fmt
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.svo_destroy(self._h)
+        self._h = None
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("SVO is closed")
+        return self._h
+
+    def level_size(self, l: int) -> int:
+        return int(lib().svo_level_size(self.handle, l))
+
+    def level_sizes(self):
+        return [self.level_size(l) for l in range(self.depth + 1)]
+
+    def stats(self):
+        v = [C.c_int64(0), C.c_int64(0), C.c_int64(0)]
+        e = C.c_int32(0)
+        _check("svo_stats", lib().svo_stats(self.handle, C.byref(v[0]), C.byref(v[1]),
+                                            C.byref(v[2]), C.byref(e)))
+        return dict(leaves=v[0].value, nodes=v[1].value, dropped=v[2].value, errors=e.value)
+
+    def export_level(self, l: int, stream=None):
+        m = self.level_size(l)
+        keys = np.zeros(m, np.uint32)
+        nrm = np.zeros((m, 3), np.float32)
+        ex = np.zeros((m, 2), np.float32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check("svo_export_level", lib().svo_export_level(self.handle, l, p(keys), p(nrm), p(ex),
+                                                          _stream(stream)))
+        return keys, nrm, ex
+
+    def export_accum(self, stream=None):
+        L = self.level_size(self.depth)
+        s = np.zeros((L, 2), np.float32)
+        c = np.zeros((L, 2), np.uint32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check("svo_export_accum", lib().svo_export_accum(self.handle, p(s), p(c), _stream(stream)))
+        return s, c
+
+
+def svo_build(rects: np.ndarray, depth: int, fmt: int = WFPG_FP32, stream=None) -> SVO:
+    """Build an SVO from a host array of rectangles (synth.RECT_DTYPE)."""
+    r = np.ascontiguousarray(rects)
+    if r.dtype.itemsize != 32:
+        raise ValueError("rects must use the 32-byte wfpg_rect layout")
+    h = C.c_void_p()
+    st = lib().svo_build(r.ctypes.data_as(C.c_void_p) if len(r) else None, len(r), depth, fmt,
+                         _stream(stream), C.byref(h))
+    _check("svo_build", st)
+    return SVO(h, depth, fmt)
+
+
+def svo_accumulate(svo: SVO, pos, wo, rgb, stream=None):
+    n = pos.shape[1]
+    for t, nm in ((wo, "wo"), (rgb, "rgb")):
+        if t.shape != pos.shape:
+            raise ValueError(f"{nm} must match pos")
+    _check("svo_accumulate", lib().svo_accumulate(svo.handle, _dptr(pos, 3, "pos"), _dptr(wo, 3, "wo"),
+                                                  _dptr(rgb, 3, "rgb"), n, _stream(stream)))
+
+
+def guide_pdf(svo: SVO, pos, opts: Opts, out=None, stream=None):
+    import torch
+    n = pos.shape[1]
+    NN = opts.N * opts.N
+    if out is None:
+        out = torch.empty((n, NN), dtype=torch.float32, device=pos.device)
+    if out.numel() != n * NN:
+        raise ValueError("out must hold n*N*N floats")
+    _check("guide_pdf", lib().guide_pdf(svo.handle, _dptr(pos, 3, "pos"), n, C.byref(opts),
+                                        _dptr(out, name="out"), _stream(stream)))
+    return out
+
+
+def guide_sample(svo: SVO, pos, opts: Opts, seed: int, bounce: int, nrm=None, dir_out=None,
+                 pdf_out=None, stream=None):
+    import torch
+    n = pos.shape[1]
+    if dir_out is None:
+        dir_out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+    if pdf_out is None:
+        pdf_out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    if dir_out.shape != (3, n) or pdf_out.numel() != n:
+        raise ValueError("output shapes must be (3, n) and (n,)")
+    _check("guide_sample", lib().guide_sample(
+        svo.handle, _dptr(pos, 3, "pos"), _dptr(nrm, 3, "nrm") if nrm is not None else None, n,
+        seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"), _dptr(pdf_out, name="pdf_out"),
+        _stream(stream)))
+    return dir_out, pdf_out
+
+
+def pdf_eval(svo: SVO, pos, dirs, opts: Opts, out=None, stream=None):
+    import torch
+    n = pos.shape[1]
+    if dirs.shape != pos.shape:
+        raise ValueError("dirs must match pos")
+    if out is None:
+        out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    _check("pdf_eval", lib().pdf_eval(svo.handle, _dptr(pos, 3, "pos"), _dptr(dirs, 3, "dirs"), n,
+                                      C.byref(opts), _dptr(out, name="out"), _stream(stream)))
+    return out
+
+
+def debug_march(svo: SVO, pos, opts: Opts, visits: bool = True, stream=None):
+    """Test-only traversal records, (n, N*N, 8) int32 and (n, N*N) visits."""
+    import torch
+    n = pos.shape[1]
+    NN = opts.N * opts.N
+    out = torch.empty((n, NN, 8), dtype=torch.int32, device=pos.device)
+    vis = torch.empty((n, NN), dtype=torch.int32, device=pos.device) if visits else None
+    _check("wfpg_debug_march", lib().wfpg_debug_march(
+        svo.handle, _dptr(pos, 3, "pos"), n, C.byref(opts), _dptr(out, name="out"),
+        _dptr(vis, name="visits") if visits else None, _stream(stream)))
+    return out, vis

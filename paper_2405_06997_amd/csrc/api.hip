@@ -1,0 +1,412 @@
+// C ABI of the path-guiding library: argument validation, device memory
+// ownership and kernel dispatch. Declarations and contracts: include/wfpg.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "wfpg_internal.h"
+
+using namespace wfpg;
+
+namespace wfpg {
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+
+hipError_t note_error(hipError_t e, const char *file, int line)
+{
+    if (e != hipSuccess) {
+        const char *base = std::strrchr(file, '/');
+        std::snprintf(g_last_error, sizeof g_last_error, "%s (%s:%d)", hipGetErrorName(e),
+                      base ? base + 1 : file, line);
+    }
+    return e;
+}
+
+int device_cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+            cu = 256;
+        cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+// Bin-centre directions of the N x N field: the equal-area concentric
+// octahedral map (Clarberg 2008, the projection named in Sec. 4) evaluated in
+// FP64 at ((u + 1/2)/N, (v + 1/2)/N) and rounded to FP32.
+void host_dir_table(int N, float *out)
+{
+    const double quarter_pi = std::atan(1.0);
+    for (int v = 0; v < N; ++v) {
+        for (int u = 0; u < N; ++u) {
+            const double a = 2.0 * ((u + 0.5) / N) - 1.0;
+            const double b = 2.0 * ((v + 0.5) / N) - 1.0;
+            const double aa = std::fabs(a), ab = std::fabs(b);
+            const double d = 1.0 - (aa + ab);
+            const double r = 1.0 - std::fabs(d);
+            const double phi = (r == 0.0) ? 0.0 : ((ab - aa) / r + 1.0) * quarter_pi;
+            const double s = r * std::sqrt(2.0 - r * r);
+            float *o = out + 3 * (v * N + u);
+            o[0] = (float)((a >= 0.0 ? 1.0 : -1.0) * std::cos(phi) * s);
+            o[1] = (float)((b >= 0.0 ? 1.0 : -1.0) * std::sin(phi) * s);
+            o[2] = (float)((d >= 0.0 ? 1.0 : -1.0) * (1.0 - r * r));
+        }
+    }
+}
+
+const float *device_dirtab(int N)
+{
+    static std::mutex mu;
+    static float *tabs[64][3] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    const int slot = N == 8 ? 0 : (N == 16 ? 1 : 2);
+    std::lock_guard<std::mutex> g(mu);
+    if (!tabs[dev][slot]) {
+        std::vector<float> h((size_t)N * N * 3);
+        host_dir_table(N, h.data());
+        float *d = nullptr;
+        if (hipMalloc((void **)&d, h.size() * sizeof(float)) != hipSuccess) return nullptr;
+        if (hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return nullptr;
+        }
+        tabs[dev][slot] = d;
+    }
+    return tabs[dev][slot];
+}
+
+}  // namespace wfpg
+
+namespace {
+
+wfpg_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return WFPG_OK;
+    if (!g_last_error[0]) note_error(e, "api", 0);
+    if (e == hipErrorOutOfMemory) return WFPG_ENOMEM;
+    return WFPG_EDEVICE;
+}
+
+// Cell range of [lo, hi] along one axis under the half-open rule.
+void cell_range(float lo, float hi, int D, int32_t &i0, int32_t &i1)
+{
+    const int R = 1 << D;
+    const float R_f = (float)R;
+    int32_t a = (int32_t)std::floor(lo * R_f);
+    int32_t b = (int32_t)std::ceil(hi * R_f) - 1;
+    if (b < a) b = a;
+    a = std::min(std::max(a, 0), R - 1);
+    b = std::min(std::max(b, 0), R - 1);
+    i0 = a;
+    i1 = b;
+}
+
+bool valid_opts(const wfpg_opts *o)
+{
+    if (!o) return false;
+    if (o->N != 8 && o->N != 16 && o->N != 32) return false;
+    if (!std::isfinite(o->eps) || !(o->eps > 0.f)) return false;
+    if (o->mode != 0 && o->mode != 1) return false;
+    return true;
+}
+
+TileConfig default_tile(const wfpg_svo *svo, int N)
+{
+    TileConfig t;
+    t.waves_per_block = 4;
+    t.lds_levels = std::min(7, svo->depth + 1);
+    t.blocks_per_cu = N == 32 ? 4 : 8;
+    return t;
+}
+
+GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o)
+{
+    GuideArgs a;
+    std::memset(&a, 0, sizeof a);
+    const double pi = 3.14159265358979323846;
+    a.eps = o->eps;
+    a.omega = (float)(4.0 * pi / (double)(o->N * o->N));
+    a.pdf_scale = (float)((double)(o->N * o->N) / (4.0 * pi));
+    a.dirtab = device_dirtab(o->N);
+    a.err = svo->d_err;
+    return a;
+}
+
+void free_svo(wfpg_svo *s)
+{
+    if (!s) return;
+    void *ptrs[] = {s->d_bits, s->d_rank, s->d_keys, s->d_nrm, s->d_e32, s->d_e16,
+                    s->d_sum, s->d_cnt, s->d_dropped, s->d_err};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+wfpg_opts wfpg_default_opts(void)
+{
+    wfpg_opts o;
+    o.N = 16;
+    o.eps = 0.01f;
+    o.mode = 0;
+    o.kl_bound = 0.05f;
+    o.probe_stride = 256;
+    return o;
+}
+
+const char *wfpg_status_string(wfpg_status s)
+{
+    switch (s) {
+    case WFPG_OK: return "ok";
+    case WFPG_EINVAL: return "invalid argument";
+    case WFPG_ENOMEM: return "out of memory";
+    case WFPG_EDEVICE: return "device error";
+    case WFPG_ESTATE: return "invalid state";
+    case WFPG_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+wfpg_status svo_build(const wfpg_rect *rects, int64_t n_rects, int32_t depth, int32_t exitance_fmt,
+                      void *hip_stream, wfpg_svo **out)
+{
+    if (!out) return WFPG_EINVAL;
+    *out = nullptr;
+    if (depth < 1 || depth > WFPG_MAXD || n_rects < 0 || (n_rects > 0 && !rects)) return WFPG_EINVAL;
+    if (exitance_fmt != WFPG_FP32 && exitance_fmt != WFPG_FP16 && exitance_fmt != WFPG_BF16)
+        return WFPG_EINVAL;
+    if (n_rects >= (1ll << 29)) return WFPG_EINVAL;
+    std::vector<RectCells> rc((size_t)n_rects);
+    std::vector<int64_t> foff((size_t)n_rects + 1, 0);
+    for (int64_t i = 0; i < n_rects; ++i) {
+        const wfpg_rect &r = rects[i];
+        if (r.axis < 0 || r.axis > 2 || (r.sign != 1 && r.sign != -1)) return WFPG_EINVAL;
+        const float v[5] = {r.c, r.lo[0], r.lo[1], r.hi[0], r.hi[1]};
+        for (float x : v)
+            if (!std::isfinite(x)) return WFPG_EINVAL;
+        if (r.lo[0] > r.hi[0] || r.lo[1] > r.hi[1]) return WFPG_EINVAL;
+        RectCells &c = rc[(size_t)i];
+        int32_t dummy;
+        c.axis = r.axis;
+        cell_range(r.c, r.c, depth, c.ca, dummy);
+        cell_range(r.lo[0], r.hi[0], depth, c.a0, c.a1);
+        cell_range(r.lo[1], r.hi[1], depth, c.b0, c.b1);
+        c.cls = r.axis * 2 + (r.sign > 0 ? 1 : 0);
+        c.emissive = r.emissive;
+        foff[(size_t)i + 1] = foff[(size_t)i] + (int64_t)(c.a1 - c.a0 + 1) * (c.b1 - c.b0 + 1);
+    }
+    const int64_t n_frag = foff[(size_t)n_rects];
+    hipStream_t s = (hipStream_t)hip_stream;
+    wfpg_svo *svo = new (std::nothrow) wfpg_svo();
+    if (!svo) return WFPG_ENOMEM;
+    svo->depth = depth;
+    svo->fmt = exitance_fmt;
+    (void)hipGetDevice(&svo->device);
+    svo->total_words = level_woff(depth + 1);
+#define NOTE(x) note_error((x), __FILE__, __LINE__)
+    hipError_t e = NOTE(hipMalloc((void **)&svo->d_bits, svo->total_words * sizeof(uint64_t)));
+    if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_rank, svo->total_words * sizeof(uint32_t)));
+    if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_dropped, 2 * sizeof(unsigned long long)));
+    if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_err, sizeof(int32_t)));
+    if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_bits, 0, svo->total_words * sizeof(uint64_t), s));
+    if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_dropped, 0, 2 * sizeof(unsigned long long), s));
+    if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_err, 0, sizeof(int32_t), s));
+    RectCells *d_rc = nullptr;
+    int64_t *d_foff = nullptr;
+    if (e == hipSuccess && n_rects > 0) {
+        e = hipMalloc((void **)&d_rc, rc.size() * sizeof(RectCells));
+        if (e == hipSuccess) e = hipMalloc((void **)&d_foff, foff.size() * sizeof(int64_t));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_rc, rc.data(), rc.size() * sizeof(RectCells), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_foff, foff.data(), foff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = launch_build(svo, d_rc, d_foff, n_rects, n_frag, s);
+    if (e == hipSuccess) e = NOTE(hipStreamSynchronize(s));
+#undef NOTE
+    if (d_rc) (void)hipFree(d_rc);
+    if (d_foff) (void)hipFree(d_foff);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_svo(svo);
+        return from_hip(e);
+    }
+    *out = svo;
+    return WFPG_OK;
+}
+
+void svo_destroy(wfpg_svo *svo)
+{
+    if (!svo) return;
+    (void)hipDeviceSynchronize();
+    free_svo(svo);
+}
+
+wfpg_status svo_accumulate(wfpg_svo *svo, const float *pos, const float *wo, const float *rgb,
+                           int64_t n, void *hip_stream)
+{
+    if (!svo || n < 0 || (n > 0 && (!pos || !wo || !rgb))) return WFPG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_accumulate(svo, pos, wo, rgb, n, s);
+    if (e == hipSuccess) e = launch_propagate(svo, s);
+    return from_hip(e);
+}
+
+static wfpg_status guide_common(const wfpg_svo *svo, int mode, const wfpg_opts *o, GuideArgs &a,
+                                void *hip_stream)
+{
+    if (!a.dirtab) return WFPG_ENOMEM;
+    return from_hip(launch_guide(svo, o->N, mode, a, default_tile(svo, o->N), (hipStream_t)hip_stream));
+}
+
+wfpg_status guide_pdf(const wfpg_svo *svo, const float *pos, int64_t n, const wfpg_opts *opts,
+                      float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !pdf_out))) return WFPG_EINVAL;
+    if (opts->mode != 0) return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.n = n;
+    a.pdf_out = pdf_out;
+    return guide_common(svo, MODE_PDF, opts, a, hip_stream);
+}
+
+wfpg_status guide_sample(const wfpg_svo *svo, const float *pos, const float *nrm, int64_t n,
+                         uint64_t seed, uint32_t bounce, const wfpg_opts *opts, float *dir_out,
+                         float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !dir_out || !pdf_out)))
+        return WFPG_EINVAL;
+    if (opts->mode == 1) return WFPG_ESTATE;   // no learned model attached
+    (void)nrm;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.n = n;
+    a.seed = seed;
+    a.bounce = bounce;
+    a.dir_out = dir_out;
+    a.pdf_out = pdf_out;
+    return guide_common(svo, MODE_SAMPLE, opts, a, hip_stream);
+}
+
+wfpg_status pdf_eval(const wfpg_svo *svo, const float *pos, const float *dir, int64_t n,
+                     const wfpg_opts *opts, float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !dir || !pdf_out))) return WFPG_EINVAL;
+    if (opts->mode != 0) return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.dir_in = dir;
+    a.n = n;
+    a.pdf_out = pdf_out;
+    return guide_common(svo, MODE_EVAL, opts, a, hip_stream);
+}
+
+wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n, const wfpg_opts *opts,
+                             int32_t *out, int32_t *visits, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !out))) return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.n = n;
+    a.dbg_out = out;
+    a.dbg_visits = visits;
+    return guide_common(svo, MODE_DEBUG, opts, a, hip_stream);
+}
+
+wfpg_status svo_stats(const wfpg_svo *svo, int64_t *leaves, int64_t *nodes, int64_t *dropped_splats,
+                      int32_t *error_flags)
+{
+    if (!svo) return WFPG_EINVAL;
+    hipError_t e = hipDeviceSynchronize();
+    unsigned long long d[2] = {0, 0};
+    int32_t err = 0;
+    if (e == hipSuccess) e = hipMemcpy(d, svo->d_dropped, sizeof d, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&err, svo->d_err, sizeof err, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    if (leaves) *leaves = svo->n[svo->depth];
+    if (nodes) *nodes = svo->total_nodes;
+    if (dropped_splats) *dropped_splats = (int64_t)(d[0] + d[1]);
+    if (error_flags) *error_flags = err;
+    return WFPG_OK;
+}
+
+int64_t svo_level_size(const wfpg_svo *svo, int32_t level)
+{
+    if (!svo || level < 0 || level > svo->depth) return -1;
+    return svo->n[level];
+}
+
+wfpg_status svo_export_level(const wfpg_svo *svo, int32_t level, uint32_t *keys, float *normals,
+                             float *exitance, void *hip_stream)
+{
+    if (!svo || level < 0 || level > svo->depth) return WFPG_EINVAL;
+    const int64_t m = svo->n[level], off = svo->noff[level];
+    if (m == 0) return WFPG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+    if (keys) e = hipMemcpyAsync(keys, svo->d_keys + off, m * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    std::vector<float4> nb;
+    if (e == hipSuccess && normals) {
+        nb.resize((size_t)m);
+        e = hipMemcpyAsync(nb.data(), svo->d_nrm + off, m * sizeof(float4), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess && exitance)
+        e = hipMemcpyAsync(exitance, svo->d_e32 + off, m * sizeof(float2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && normals)
+        for (int64_t i = 0; i < m; ++i) {
+            normals[3 * i] = nb[(size_t)i].x;
+            normals[3 * i + 1] = nb[(size_t)i].y;
+            normals[3 * i + 2] = nb[(size_t)i].z;
+        }
+    return from_hip(e);
+}
+
+wfpg_status svo_export_accum(const wfpg_svo *svo, float *sums, uint32_t *counts, void *hip_stream)
+{
+    if (!svo) return WFPG_EINVAL;
+    const int64_t L = svo->n[svo->depth];
+    if (L == 0) return WFPG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+    if (sums) e = hipMemcpyAsync(sums, svo->d_sum, L * sizeof(float2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && counts)
+        e = hipMemcpyAsync(counts, svo->d_cnt, L * sizeof(uint2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return from_hip(e);
+}
+
+const char *wfpg_last_error(void)
+{
+    return g_last_error;
+}
+
+wfpg_status wfpg_dir_table(int32_t N, float *out)
+{
+    if (!out || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
+    host_dir_table(N, out);
+    return WFPG_OK;
+}
+
+}  // extern "C"

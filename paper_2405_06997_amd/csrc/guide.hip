@@ -1,0 +1,283 @@
+// Per-vertex guiding on gfx950 (Alg. 3: ConeTrace for every direction patch,
+// GeneratePDF-CDF, sampling; Sec. 3.3-3.5).
+//
+// One wave64 owns one query vertex; lane l marches bins b = j*64 + l
+// (j < N*N/64) with the exact SVO march of march_core.h. Rows of the N x N
+// field are runs of N consecutive lanes, so the row CDFs are segmented wave
+// scans and the marginal CDF is one more scan over N lanes; sampling is a
+// ballot + find-first-set over the CDF.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "march_core.h"
+#include "wfpg_internal.h"
+
+namespace wfpg {
+namespace {
+
+using core::Hit;
+using core::Ray;
+using core::woff;
+
+__device__ __forceinline__ float round16(float f, int fmt)
+{
+    if (fmt == WFPG_FP16) return __half2float(__float2half_rn(f));
+    uint32_t u = __float_as_uint(f);
+    return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
+}
+__device__ __forceinline__ float unpack16(uint32_t v, int side, int fmt)
+{
+    uint32_t h = side ? (v >> 16) : (v & 0xffffu);
+    if (fmt == WFPG_FP16) return __half2float(__ushort_as_half((unsigned short)h));
+    return __uint_as_float(h << 16);
+}
+
+// Philox-4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// Equal-area concentric octahedral map (Clarberg 2008), FP32.
+__device__ __forceinline__ void oct_decode(float x, float y, float &dx, float &dy, float &dz)
+{
+    const float a = 2.f * x - 1.f, b = 2.f * y - 1.f;
+    const float aa = fabsf(a), ab = fabsf(b);
+    const float d = 1.f - (aa + ab);
+    const float r = 1.f - fabsf(d);
+    const float phi = r == 0.f ? 0.f : ((ab - aa) / r + 1.f) * 0.78539816339744831f;
+    const float z = (d >= 0.f ? 1.f : -1.f) * (1.f - r * r);
+    const float s = r * sqrtf(2.f - r * r);
+    float sn, cs;
+    sincosf(phi, &sn, &cs);
+    dx = (a >= 0.f ? cs : -cs) * s;
+    dy = (b >= 0.f ? sn : -sn) * s;
+    dz = z;
+}
+__device__ __forceinline__ void oct_encode(float dx, float dy, float dz, float &x, float &y)
+{
+    const float r = sqrtf(fmaxf(1.f - fabsf(dz), 0.f));
+    const float phi = atan2f(fabsf(dy), fabsf(dx));
+    const float t = r * phi * 0.63661977236758134f;
+    float aa = r - t, ab = t;
+    if (dz < 0.f) {
+        const float na = 1.f - ab, nb = 1.f - aa;
+        aa = na;
+        ab = nb;
+    }
+    x = ((dx >= 0.f ? aa : -aa) + 1.f) * 0.5f;
+    y = ((dy >= 0.f ? ab : -ab) + 1.f) * 0.5f;
+}
+
+template <int N>
+__device__ __forceinline__ float seg_scan(float v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < N; d <<= 1) {
+        const float t = __shfl_up(v, d, N);
+        if ((lane & (N - 1)) >= d) v += t;
+    }
+    return v;
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(512) k_guide(SvoView sv, GuideArgs a, int lds_levels)
+{
+    constexpr int NN = N * N;
+    constexpr int BPL = NN / 64;  // bins per lane
+    constexpr int G = 64 / N;     // rows per 64-bin pass
+    extern __shared__ uint64_t lbits[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const int D = sv.depth;
+    const int fmt = sv.fmt;
+    const uint32_t nlw = woff(lds_levels);
+    for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
+    __syncthreads();
+
+    const int64_t n = a.n_dev ? *a.n_dev : a.n;
+    // per-lane bin directions (FP32 table) and their quantization
+    float dx[BPL], dy[BPL], dz[BPL];
+    int qq[BPL][3];
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const int b = j * 64 + lane;
+        dx[j] = a.dirtab[3 * b];
+        dy[j] = a.dirtab[3 * b + 1];
+        dz[j] = a.dirtab[3 * b + 2];
+        qq[j][0] = core::quantize_dir(dx[j]);
+        qq[j][1] = core::quantize_dir(dy[j]);
+        qq[j][2] = core::quantize_dir(dz[j]);
+    }
+    auto bits = [&](int lvl, uint32_t wi) -> uint64_t {
+        return lvl < lds_levels ? lbits[wi] : sv.bits[wi];
+    };
+
+    for (int64_t i = (int64_t)blockIdx.x * W + wave; i < n; i += (int64_t)gridDim.x * W) {
+        uint32_t O[3], oc[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            O[k] = core::quantize_pos(a.pos[k * n + i]);
+            oc[k] = O[k] >> (WFPG_FINE - D);
+        }
+        const uint32_t origin_key = core::morton3(oc[0], oc[1], oc[2]);
+        float L[BPL];
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            Ray ray;
+            core::make_ray(O, qq[j][0], qq[j][1], qq[j][2], ray);
+            int vis = 0;
+            Hit h = {-1, 0u, 0u};
+            const int res = core::march(ray, D, origin_key, bits, 5, vis, h);
+            if (res < 0) atomicOr(a.err, 1);
+            float val = a.eps;
+            int k = -1, side = 0;
+            uint32_t node = 0;
+            int64_t nidx = -1;
+            if (res > 0) {
+                const float dsel = h.axis == 0 ? dx[j] : (h.axis == 1 ? dy[j] : dz[j]);
+                k = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
+                const int lf = D - k;
+                node = h.key >> (3 * k);
+                const uint32_t wi = woff(lf) + (node >> 6);
+                const uint64_t w = sv.bits[wi];
+                const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
+                const int64_t g = (int64_t)sv.rank[wi] + __popcll(msk);
+                nidx = g - sv.noff[lf];
+                const float4 Nn = sv.nrm[g];
+                side = core::dot3(Nn.x, Nn.y, Nn.z, dx[j], dy[j], dz[j]) < 0.f ? 0 : 1;
+                if (fmt == WFPG_FP32) {
+                    const float2 e = sv.e32[g];
+                    val = (side ? e.y : e.x) + a.eps;
+                } else {
+                    val = round16(unpack16(sv.e16[g], side, fmt) + a.eps, fmt);
+                }
+            } else if (fmt != WFPG_FP32) {
+                val = round16(a.eps, fmt);
+            }
+            L[j] = val;
+            if constexpr (MODE == MODE_DEBUG) {
+                int32_t *o = a.dbg_out + ((size_t)i * NN + j * 64 + lane) * 8;
+                o[0] = res > 0;
+                o[1] = res > 0 ? h.axis : -1;
+                o[2] = res > 0 ? (int32_t)h.key : -1;
+                o[3] = res > 0 ? (int32_t)h.delta : -1;
+                o[4] = k;
+                o[5] = res > 0 ? (int32_t)node : -1;
+                o[6] = (int32_t)nidx;
+                o[7] = side;
+                if (a.dbg_visits) a.dbg_visits[(size_t)i * NN + j * 64 + lane] = vis;
+            }
+        }
+        if constexpr (MODE == MODE_DEBUG) continue;
+
+        // row CDFs (segmented inclusive scans), marginal CDF over the row sums
+        float S[BPL];
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) S[j] = seg_scan<N>(L[j], lane);
+        float rs = 0.f;
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            const float t = __shfl(S[j], (lane % G) * N + N - 1);
+            if (lane / G == j) rs = t;
+        }
+        if (lane >= N) rs = 0.f;
+        const float M = seg_scan<N>(rs, lane);
+        const float total = __shfl(M, N - 1);
+
+        if constexpr (MODE == MODE_PDF) {
+#pragma unroll
+            for (int j = 0; j < BPL; ++j)
+                a.pdf_out[(size_t)i * NN + j * 64 + lane] =
+                    __fmul_rn(__fdiv_rn(L[j], total), a.pdf_scale);
+        } else if constexpr (MODE == MODE_SAMPLE) {
+            uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
+            philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
+            const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
+            const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
+            const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
+            const float tv = u1 * total;
+            const uint64_t bv = __ballot(lane < N && tv < M);
+            const int v = bv ? (__ffsll((unsigned long long)bv) - 1) : N - 1;
+            const int jv = v / G, gv = v % G;
+            float Sj = S[0], Lj = L[0];
+#pragma unroll
+            for (int j = 1; j < BPL; ++j)
+                if (j == jv) { Sj = S[j]; Lj = L[j]; }
+            const float rowsum = __shfl(Sj, gv * N + N - 1);
+            const float tu = u2 * rowsum;
+            const bool in_row = (lane / N) == gv;
+            const uint64_t bu = __ballot(in_row && tu < Sj);
+            const int u = bu ? (__ffsll((unsigned long long)bu) - 1 - gv * N) : N - 1;
+            const float Lb = __shfl(Lj, gv * N + u);
+            if (lane == 0) {
+                const float inv = 1.f / (float)N;
+                float ox, oy, oz;
+                oct_decode(__fadd_rn((float)u * inv, u3 * inv), __fadd_rn((float)v * inv, u4 * inv),
+                           ox, oy, oz);
+                a.dir_out[i] = ox;
+                a.dir_out[n + i] = oy;
+                a.dir_out[2 * n + i] = oz;
+                a.pdf_out[i] = __fmul_rn(__fdiv_rn(Lb, total), a.pdf_scale);
+            }
+        } else if constexpr (MODE == MODE_EVAL) {
+            float ex, ey;
+            oct_encode(a.dir_in[i], a.dir_in[n + i], a.dir_in[2 * n + i], ex, ey);
+            const int u = min(max((int)floorf(ex * (float)N), 0), N - 1);
+            const int v = min(max((int)floorf(ey * (float)N), 0), N - 1);
+            const int jv = v / G, gv = v % G;
+            float Lj = L[0];
+#pragma unroll
+            for (int j = 1; j < BPL; ++j)
+                if (j == jv) Lj = L[j];
+            const float Lb = __shfl(Lj, gv * N + u);
+            if (lane == 0) a.pdf_out[i] = __fmul_rn(__fdiv_rn(Lb, total), a.pdf_scale);
+        }
+    }
+}
+
+template <int N>
+hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a, const TileConfig &tc,
+                    hipStream_t s)
+{
+    const int W = tc.waves_per_block;
+    const int64_t want = a.n_dev ? INT64_MAX : (a.n + W - 1) / W;
+    const int64_t cap = (int64_t)device_cu_count() * tc.blocks_per_cu;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+    const size_t lds = (size_t)level_woff(tc.lds_levels) * sizeof(uint64_t);
+    const dim3 blk(64 * W);
+    const wfpg::SvoView v = svo->view();
+    switch (mode) {
+    case MODE_SAMPLE: hipLaunchKernelGGL((k_guide<N, MODE_SAMPLE>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    case MODE_PDF: hipLaunchKernelGGL((k_guide<N, MODE_PDF>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    case MODE_EVAL: hipLaunchKernelGGL((k_guide<N, MODE_EVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    default: hipLaunchKernelGGL((k_guide<N, MODE_DEBUG>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_guide(const wfpg_svo *svo, int N, int mode, const GuideArgs &a,
+                        const TileConfig &tc, hipStream_t s)
+{
+    switch (N) {
+    case 8: return launch_n<8>(svo, mode, a, tc, s);
+    case 16: return launch_n<16>(svo, mode, a, tc, s);
+    case 32: return launch_n<32>(svo, mode, a, tc, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace wfpg

@@ -1,0 +1,135 @@
+// Internal declarations of the wavefront path-guiding library (gfx950).
+//
+// SVO layout in device memory (depth D <= 10):
+//  * occupancy: one dense bitmap per level l, 8^l bits in Morton order, packed
+//    into 64-bit words (a word is one 4x4x4 brick of level l, i.e. two levels
+//    of the tree below one level-(l-2) node). Level l starts at word
+//    woff(l) of one shared array; levels 0..2 take one word each.
+//  * rank: per word, the global index of the first node stored in that word
+//    (level node offset + popcount of all earlier words of the level). The
+//    index of node `key` at level l is rank[woff(l) + key/64] +
+//    popcount(word & ((1 << key%64) - 1)). Nodes of all levels share one
+//    index space, level 0 first.
+//  * per node: keys (uint32 Morton), normal (float4, w unused), exitance
+//    (float2, FP32 value of side 0 / side 1) and, for 16-bit storage, the two
+//    sides packed into one uint32 (side 0 in the low half).
+//  * per leaf: splat sums (float2) and counts (uint2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wfpg.h"
+
+#define WFPG_MAXD 10
+#define WFPG_FINE 30
+
+namespace wfpg {
+
+// Word offset of level l in the shared bitmap/rank arrays.
+__host__ __device__ constexpr uint64_t level_words(int l)
+{
+    return l <= 2 ? 1ull : (1ull << (3 * l - 6));
+}
+__host__ __device__ constexpr uint64_t level_woff(int l)
+{
+    uint64_t o = 0;
+    for (int m = 0; m < l; ++m) o += level_words(m);
+    return o;
+}
+
+// Read-only view of an SVO handed to kernels by value.
+struct SvoView {
+    const uint64_t *bits;
+    const uint32_t *rank;
+    const uint32_t *keys;
+    const float4 *nrm;
+    const float2 *e32;
+    const uint32_t *e16;
+    int64_t noff[WFPG_MAXD + 2];  // first node index of each level
+    int depth;
+    int fmt;
+};
+
+struct RectCells {   // voxelized extent of one rectangle (host computed)
+    int32_t axis, ca;       // plane axis and its cell index
+    int32_t a0, a1, b0, b1; // inclusive cell ranges along the two other axes
+    int32_t cls;            // normal class: axis * 2 + (sign > 0)
+    int32_t emissive;
+};
+
+// Launchers (one translation unit each, enqueued on `s`).
+hipError_t launch_build(struct ::wfpg_svo *svo, const RectCells *d_rects, const int64_t *d_foff,
+                        int64_t n_rects, int64_t n_frag, hipStream_t s);
+hipError_t launch_accumulate(struct ::wfpg_svo *svo, const float *pos, const float *wo,
+                             const float *rgb, int64_t n, hipStream_t s);
+hipError_t launch_propagate(struct ::wfpg_svo *svo, hipStream_t s);
+
+enum GuideMode { MODE_SAMPLE = 0, MODE_PDF = 1, MODE_EVAL = 2, MODE_DEBUG = 3 };
+
+struct GuideArgs {
+    const float *pos;
+    const float *dir_in;      // MODE_EVAL
+    int64_t n;                // queue length (ignored when n_dev != NULL)
+    const int64_t *n_dev;     // optional device-resident queue length
+    float eps;
+    float omega;              // fp32(4*pi/N^2)
+    float pdf_scale;          // fp32(N^2/(4*pi))
+    uint64_t seed;
+    uint32_t bounce;
+    float *dir_out;
+    float *pdf_out;
+    int32_t *dbg_out;
+    int32_t *dbg_visits;
+    const float *dirtab;      // N*N*3 FP32 bin centres
+    int32_t *err;             // device error flags
+};
+
+struct TileConfig {          // launch shape chosen by the autotuner
+    int waves_per_block;     // 1, 2, 4, 8
+    int lds_levels;          // top levels held in LDS: 5, 6 or 7
+    int blocks_per_cu;       // persistent grid size factor
+};
+
+hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const GuideArgs &a,
+                        const TileConfig &tc, hipStream_t s);
+
+int device_cu_count();
+// Records a failing HIP call (thread-local) for wfpg_last_error().
+hipError_t note_error(hipError_t e, const char *file, int line);
+#define WFPG_HIP_TRY(x)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) return ::wfpg::note_error(e_, __FILE__, __LINE__);             \
+    } while (0)
+const float *device_dirtab(int N);   // uploaded once per N per device
+void host_dir_table(int N, float *out);
+
+}  // namespace wfpg
+
+// Host-side object behind the opaque handle.
+struct wfpg_svo {
+    int depth = 0, fmt = 0, device = 0;
+    int64_t n[WFPG_MAXD + 1] = {};
+    int64_t noff[WFPG_MAXD + 2] = {};
+    int64_t total_nodes = 0;
+    uint64_t total_words = 0;
+    uint64_t *d_bits = nullptr;
+    uint32_t *d_rank = nullptr;
+    uint32_t *d_keys = nullptr;
+    float4 *d_nrm = nullptr;
+    float2 *d_e32 = nullptr;
+    uint32_t *d_e16 = nullptr;
+    float2 *d_sum = nullptr;
+    uint2 *d_cnt = nullptr;
+    unsigned long long *d_dropped = nullptr;
+    int32_t *d_err = nullptr;
+    wfpg::SvoView view() const
+    {
+        wfpg::SvoView v;
+        v.bits = d_bits; v.rank = d_rank; v.keys = d_keys; v.nrm = d_nrm;
+        v.e32 = d_e32; v.e16 = d_e16; v.depth = depth; v.fmt = fmt;
+        for (int i = 0; i < WFPG_MAXD + 2; ++i) v.noff[i] = noff[i];
+        return v;
+    }
+};

@@ -1,0 +1,56 @@
+// Host build of the library's traversal core (paper_2405_06997_amd/csrc/
+// march_core.h) for the CPU test suite: the same source the gfx950 kernels
+// run, driven here over arrays the test builds from the oracle's SVO.
+#include <stdint.h>
+
+#include "../../paper_2405_06997_amd/csrc/march_core.h"
+
+using namespace wfpg::core;
+
+extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, const int64_t *noff,
+                                 const float *nrm, int D, const float *pos, int64_t n,
+                                 const float *dirtab, int N, float omega, int32_t *out,
+                                 int32_t *visits)
+{
+    const int NN = N * N;
+    auto load = [&](int, uint32_t wi) -> uint64_t { return bits[wi]; };
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t O[3], oc[3];
+        for (int k = 0; k < 3; ++k) {
+            O[k] = quantize_pos(pos[k * n + i]);
+            oc[k] = O[k] >> (kFine - D);
+        }
+        const uint32_t origin = morton3(oc[0], oc[1], oc[2]);
+        for (int b = 0; b < NN; ++b) {
+            const float *d = dirtab + 3 * b;
+            Ray r;
+            make_ray(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), r);
+            int vis = 0;
+            Hit h = {-1, 0u, 0u};
+            const int res = march(r, D, origin, load, 5, vis, h);
+            int32_t *o = out + ((int64_t)i * NN + b) * 8;
+            o[0] = res > 0;
+            o[1] = res > 0 ? h.axis : -1;
+            o[2] = res > 0 ? (int32_t)h.key : -1;
+            o[3] = res > 0 ? (int32_t)h.delta : -1;
+            o[4] = -1; o[5] = -1; o[6] = -1; o[7] = 0;
+            if (res > 0) {
+                const float da = d[h.axis] < 0 ? -d[h.axis] : d[h.axis];
+                const int k = footprint_levels(h.delta, da, D, omega);
+                const int lf = D - k;
+                const uint32_t node = h.key >> (3 * k);
+                const uint32_t wi = woff(lf) + (node >> 6);
+                const uint64_t w = bits[wi];
+                const uint64_t m = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
+                const int64_t g = (int64_t)rank[wi] + __builtin_popcountll(m);
+                const float *nn = nrm + 3 * g;
+                o[4] = k;
+                o[5] = (int32_t)node;
+                o[6] = (int32_t)(g - noff[lf]);
+                o[7] = dot3(nn[0], nn[1], nn[2], d[0], d[1], d[2]) < 0.f ? 0 : 1;
+            }
+            visits[(int64_t)i * NN + b] = res < 0 ? -1 : vis;
+        }
+    }
+}

@@ -1,0 +1,408 @@
+"""GPU-vs-oracle parity of the HIP path, called through the C ABI.
+
+Bars: SVO build arrays, traversal records and bin choices bit-exact; PDFs
+within 1e-5 relative (FP32 field, FP32 CDF); sampled bins equal except inside
+the FP32 scan band at CDF boundaries (several answers are then correct);
+sampled directions within 4e-6 rad of the oracle's FP64 decode.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+BAND = 1e-5        # relative CDF margin inside which FP32 scan order may pick a neighbour
+EDGE = 1e-4        # distance to a bin edge (in bin units) inside which FP32 encode may differ
+DIR_TOL = 4e-6     # radians
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def w():
+    import paper_2405_06997_amd as w
+    w.lib()
+    return w
+
+
+def to_dev(torch_dev, *arrs):
+    torch, dev = torch_dev
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in arrs]
+
+
+@pytest.fixture(scope="module")
+def c1(orc, w, torch_dev):
+    """Tiny Cornell box, depth 6, one splat per (leaf, side)."""
+    box = synth.cornell_box()
+    o = orc.SVO(box, 6)
+    xyz, em = o.leaf_info()
+    sp = synth.leaf_splats(xyz, o.normals(6), em, 6, seed=2)
+    assert o.accumulate(*sp) == 0
+    o.propagate()
+    g = w.svo_build(box, 6)
+    w.svo_accumulate(g, *to_dev(torch_dev, *sp))
+    pos, nrm, _ = synth.area_points(box, 4096, 3)
+    return dict(rects=box, o=o, g=g, pos=pos, nrm=nrm, D=6, splats=sp)
+
+
+@pytest.fixture(scope="module")
+def c2(orc, w, torch_dev):
+    """Room, depth 10 (~8M leaves), 2M splats."""
+    room = synth.room()
+    o = orc.SVO(room, 10)
+    sp = synth.room_splats(room, 2_000_000, 13)
+    dropped = o.accumulate(*sp)
+    o.propagate()
+    g = w.svo_build(room, 10)
+    w.svo_accumulate(g, *to_dev(torch_dev, *sp))
+    cam, cnrm, _ = synth.camera_queue(room)
+    rnd, rnrm, _ = synth.area_points(room, 2_073_600, 14)
+    return dict(rects=room, o=o, g=g, D=10, cam=cam, rnd=rnd, dropped=dropped, splats=sp)
+
+
+def sample_cols(a, k, seed=0):
+    idx = np.random.default_rng(seed).choice(a.shape[1], size=k, replace=False)
+    idx.sort()
+    return np.ascontiguousarray(a[:, idx]), idx
+
+
+# ------------------------------------------------------------------ build ----
+@pytest.mark.parametrize("case", ["c1", "c2"])
+def test_build_bitexact(case, request):
+    c = request.getfixturevalue(case)
+    o, g, D = c["o"], c["g"], c["D"]
+    assert g.level_sizes() == o.level_sizes()
+    for l in range(D + 1):
+        keys, nrm, _ = g.export_level(l)
+        assert np.array_equal(keys, o.keys(l)), l
+        assert np.array_equal(nrm.view(np.uint32), o.normals(l).view(np.uint32)), l
+    st = g.stats()
+    assert st["leaves"] == o.level_size(D) and st["errors"] == 0
+
+
+def test_build_other_depths(orc, w):
+    rng = np.random.default_rng(5)
+    for D in (1, 3, 5, 8):
+        rs = synth.room(n_boxes=8)
+        o = orc.SVO(rs, D)
+        g = w.svo_build(rs, D)
+        assert g.level_sizes() == o.level_sizes()
+        for l in range(D + 1):
+            k, n, _ = g.export_level(l)
+            assert np.array_equal(k, o.keys(l))
+            assert np.array_equal(n.view(np.uint32), o.normals(l).view(np.uint32))
+
+
+# ------------------------------------------------------------- accumulate ----
+def test_accumulate_one_splat_per_side_bitexact(c1):
+    o, g = c1["o"], c1["g"]
+    s, cnt = g.export_accum()
+    assert (cnt == 1).all()
+    for l in range(7):
+        _, _, ex = g.export_level(l)
+        e32, _ = o.exitance(l)
+        assert np.array_equal(ex.view(np.uint32), e32.view(np.uint32)), l
+
+
+def test_accumulate_room_counts_and_sums(c2):
+    o, g = c2["o"], c2["g"]
+    s, cnt = g.export_accum()
+    s32, s64, ocnt = o.leaf_accum()
+    assert np.array_equal(cnt.astype(np.int64), ocnt)
+    assert g.stats()["dropped"] == c2["dropped"] == o.dropped()
+    # FP32 atomics: |sum - exact| <= (count - 1) * u * sum
+    u = 2.0 ** -24
+    bound = np.maximum(ocnt - 1, 0) * u * s64 + 1e-30
+    assert (np.abs(s.astype(np.float64) - s64) <= bound * 1.0001).all()
+    for l in range(11):
+        _, _, ex = g.export_level(l)
+        e32, _ = o.exitance(l)
+        denom = np.maximum(np.abs(e32), 1e-30)
+        assert (np.abs(ex - e32) / denom).max() < 1e-5, l
+
+
+# ------------------------------------------------------------------ march ----
+def _march_compare(o, g, w, torch_dev, pos, N):
+    (dpos,) = to_dev(torch_dev, pos)
+    rec, vis = w.debug_march(g, dpos, w.make_opts(N=N))
+    rec = rec.cpu().numpy().astype(np.int64)
+    vis = vis.cpu().numpy().astype(np.int64)
+    want, wvis = o.debug_march(pos, N, lds_levels=5, hier=False, visits=True)
+    hit = want[..., 0] == 1
+    assert np.array_equal(rec[..., 0], want[..., 0])
+    assert np.array_equal(rec[hit], want[hit])
+    assert np.array_equal(vis, wvis)
+    assert g.stats()["errors"] == 0
+    return hit.mean()
+
+
+def test_march_bitexact_c1(c1, w, torch_dev):
+    for N in (8, 16):
+        hr = _march_compare(c1["o"], c1["g"], w, torch_dev, c1["pos"], N)
+        assert hr > 0.3
+
+
+@pytest.mark.parametrize("N,k", [(16, 384), (8, 256), (32, 48)])
+def test_march_bitexact_c2(c2, w, torch_dev, N, k):
+    cam, _ = sample_cols(c2["cam"], k // 2, 1)
+    rnd, _ = sample_cols(c2["rnd"], k // 2, 2)
+    _march_compare(c2["o"], c2["g"], w, torch_dev, np.concatenate([cam, rnd], 1), N)
+
+
+# -------------------------------------------------------------- guide_pdf ----
+def _pdf_compare(o, g, w, torch_dev, pos, N, tol=1e-5):
+    (dpos,) = to_dev(torch_dev, pos)
+    got = w.guide_pdf(g, dpos, w.make_opts(N=N)).cpu().numpy().astype(np.float64)
+    want = o.guide_pdf(pos, N)
+    rel = np.abs(got - want) / want
+    assert rel.max() <= tol, rel.max()
+    np.testing.assert_allclose(got.sum(1) * 4 * math.pi / N ** 2, 1.0, rtol=1e-5)
+    return rel.max()
+
+
+def test_guide_pdf_c1(c1, w, torch_dev):
+    for N in (8, 16, 32):
+        _pdf_compare(c1["o"], c1["g"], w, torch_dev, c1["pos"][:, :1024], N)
+
+
+def test_guide_pdf_c2(c2, w, torch_dev):
+    cam, _ = sample_cols(c2["cam"], 256, 3)
+    rnd, _ = sample_cols(c2["rnd"], 128, 4)
+    _pdf_compare(c2["o"], c2["g"], w, torch_dev, np.concatenate([cam, rnd], 1), 16)
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_guide_pdf_16bit_storage(orc, w, torch_dev, c1, fmt):
+    """16-bit exitance and bins: within 2e-3 of the oracle fed the same
+    quantized values (the oracle rounds exactly as the kernels store, so the
+    FP32-path bar of 1e-5 is kept), and the error against the FP64 field is
+    reported."""
+    box = c1["rects"]
+    o = orc.SVO(box, 6)
+    o.accumulate(*c1["splats"])
+    o.propagate(fmt)
+    g = w.svo_build(box, 6, fmt)
+    w.svo_accumulate(g, *to_dev(torch_dev, *c1["splats"]))
+    pos = c1["pos"][:, :1024]
+    (dpos,) = to_dev(torch_dev, pos)
+    got = w.guide_pdf(g, dpos, w.make_opts(N=8)).cpu().numpy().astype(np.float64)
+    want, truth = o.guide_pdf(pos, 8, truth=True)
+    rel = np.abs(got - want) / want
+    assert rel.max() <= 1e-5
+    err_truth = np.abs(got - truth) / truth
+    print(f"fmt {fmt}: max rel err vs FP64 field {err_truth.max():.3e}, mean {err_truth.mean():.3e}")
+    assert err_truth.max() < 2e-2
+
+
+# ----------------------------------------------------------- guide_sample ----
+def _sample_compare(orc, o, g, w, torch_dev, pos, N, seed, bounce):
+    (dpos,) = to_dev(torch_dev, pos)
+    d, p = w.guide_sample(g, dpos, w.make_opts(N=N), seed=seed, bounce=bounce)
+    d = d.cpu().numpy().astype(np.float64)
+    p = p.cpu().numpy().astype(np.float64)
+    ref = o.guide_sample(pos, N, seed=seed, bounce=bounce)
+    xy = orc.oct_encode_many(d)
+    gb = np.stack([np.minimum((xy[0] * N).astype(int), N - 1),
+                   np.minimum((xy[1] * N).astype(int), N - 1)], 1)
+    fx, fy = xy[0] * N, xy[1] * N
+    edge = np.minimum(np.abs(fx - np.rint(fx)), np.abs(fy - np.rint(fy)))
+    same = (gb == ref["bin"]).all(1)
+    band = ref["margin"].min(1) < BAND
+    bad = ~same & ~band & (edge > EDGE)
+    assert not bad.any(), np.nonzero(bad)[0][:10]
+    assert same.mean() > 0.99
+    ok = same & (edge > EDGE)
+    a_ = d[:, ok] / np.linalg.norm(d[:, ok], axis=0)
+    b_ = ref["dir"][:, ok]
+    ang = 2 * np.arcsin(np.minimum(np.linalg.norm(a_ - b_, axis=0) / 2, 1.0))
+    assert ang.max() < DIR_TOL, ang.max()
+    rel = np.abs(p[same] - ref["pdf"][same]) / ref["pdf"][same]
+    assert rel.max() <= 1e-5
+    np.testing.assert_allclose(np.linalg.norm(d, axis=0), 1.0, atol=2e-6)
+    return (~same).sum()
+
+
+def test_guide_sample_c1(orc, c1, w, torch_dev):
+    for N in (8, 16, 32):
+        _sample_compare(orc, c1["o"], c1["g"], w, torch_dev, c1["pos"], N, seed=11 + N, bounce=2)
+
+
+def test_guide_sample_c2(orc, c2, w, torch_dev):
+    cam, _ = sample_cols(c2["cam"], 512, 5)
+    _sample_compare(orc, c2["o"], c2["g"], w, torch_dev, cam, 16, seed=123, bounce=0)
+
+
+def test_sample_chi2_gpu(orc, c1, w, torch_dev):
+    from scipy import stats
+    torch, dev = torch_dev
+    N = 8
+    n = 1 << 20
+    o, g = c1["o"], c1["g"]
+    for vi in (0, 1):
+        pos = np.repeat(c1["pos"][:, vi:vi + 1], n, 1)
+        (dpos,) = to_dev(torch_dev, pos)
+        d, _ = w.guide_sample(g, dpos, w.make_opts(N=N), seed=77 + vi, bounce=1)
+        xy = orc.oct_encode_many(d.cpu().numpy().astype(np.float64))
+        b = np.minimum((xy[1] * N).astype(int), N - 1) * N + np.minimum((xy[0] * N).astype(int), N - 1)
+        h = np.bincount(b, minlength=N * N).astype(float)
+        prob = o.guide_pdf(c1["pos"][:, vi:vi + 1], N)[0] * 4 * math.pi / N ** 2
+        e = prob * n
+        keep = e >= 5
+        hs = np.append(h[keep], h[~keep].sum())
+        es = np.append(e[keep], e[~keep].sum())
+        if es[-1] == 0:
+            hs, es = hs[:-1], es[:-1]
+        assert stats.chisquare(hs, es).pvalue > 1e-3
+
+
+# --------------------------------------------------------------- pdf_eval ----
+def test_pdf_eval_c1(orc, c1, w, torch_dev):
+    o, g = c1["o"], c1["g"]
+    pos = c1["pos"][:, :2048]
+    rng = np.random.default_rng(8)
+    v = rng.normal(size=(3, pos.shape[1]))
+    v = (v / np.linalg.norm(v, axis=0)).astype(np.float32)
+    for N in (8, 16):
+        dpos, dv = to_dev(torch_dev, pos, v)
+        got = w.pdf_eval(g, dpos, dv, w.make_opts(N=N)).cpu().numpy().astype(np.float64)
+        ref = o.pdf_eval(pos, v, N)
+        ok = ref["edge"] > EDGE
+        assert ok.mean() > 0.99
+        rel = np.abs(got[ok] - ref["pdf"][ok]) / ref["pdf"][ok]
+        assert rel.max() <= 1e-5
+
+
+def test_pdf_eval_of_samples_matches_sample_pdf(c2, w, torch_dev):
+    torch, dev = torch_dev
+    cam, _ = sample_cols(c2["cam"], 4096, 9)
+    (dpos,) = to_dev(torch_dev, cam)
+    opts = w.make_opts(N=16)
+    d, p = w.guide_sample(c2["g"], dpos, opts, seed=5, bounce=1)
+    q = w.pdf_eval(c2["g"], dpos, d, opts)
+    agree = (torch.abs(p - q) <= 1e-6 * p).float().mean().item()
+    assert agree > 0.999
+
+
+# -------------------------------------------------------------- edge cases ---
+def test_edge_cases(orc, w, torch_dev, c1):
+    torch, dev = torch_dev
+    g = c1["g"]
+    opts = w.make_opts(N=8)
+    empty = torch.empty((3, 0), device=dev)
+    w.guide_sample(g, empty, opts, 1, 0)
+    w.guide_pdf(g, empty, opts)
+    w.svo_accumulate(g, empty, empty, empty)  # recomputes averages only
+    # ragged queue lengths (not multiples of the waves of a block)
+    for n in (1, 3, 63, 65, 1001):
+        pos = c1["pos"][:, :n]
+        (dpos,) = to_dev(torch_dev, pos)
+        got = w.guide_pdf(g, dpos, opts).cpu().numpy()
+        want = c1["o"].guide_pdf(pos, 8)
+        assert (np.abs(got - want) / want).max() <= 1e-5
+    # invalid arguments
+    bad = w.make_opts(N=12)
+    with pytest.raises(w.WfpgError):
+        w.guide_pdf(g, to_dev(torch_dev, c1["pos"][:, :4])[0], bad)
+    with pytest.raises(w.WfpgError) as ei:
+        w.guide_sample(g, to_dev(torch_dev, c1["pos"][:, :4])[0], w.make_opts(N=8, mode=1), 1, 0)
+    assert ei.value.status == -4
+    with pytest.raises(w.WfpgError):
+        w.guide_pdf(g, to_dev(torch_dev, c1["pos"][:, :4])[0], w.make_opts(N=8, eps=0.0))
+
+
+def test_empty_svo_all_miss(w, torch_dev):
+    torch, dev = torch_dev
+    g = w.svo_build(np.zeros(0, synth.RECT_DTYPE), 5)
+    assert g.level_sizes() == [0] * 6
+    pos = torch.rand((3, 100), device=dev)
+    pdf = w.guide_pdf(g, pos, w.make_opts(N=16))
+    assert torch.allclose(pdf, torch.full_like(pdf, 1 / (4 * math.pi)), rtol=1e-6)
+    sp = torch.rand((3, 10), device=dev)
+    w.svo_accumulate(g, sp, sp, sp)
+    assert g.stats()["dropped"] == 10
+
+
+def test_invalid_splats_dropped(orc, w, torch_dev):
+    torch, dev = torch_dev
+    box = synth.cornell_box()
+    o = orc.SVO(box, 6)
+    g = w.svo_build(box, 6)
+    pos, nrm, _ = synth.area_points(box, 1000, 4)
+    rgb = np.ones((3, 1000), np.float32)
+    pos[0, 0] = np.nan
+    pos[1, 1] = 1.5
+    rgb[2, 2] = np.inf
+    rgb[:, 3] = -1.0
+    pos[:, 5] = 0.5
+    nd = o.accumulate(pos, nrm, rgb)
+    w.svo_accumulate(g, *to_dev(torch_dev, pos, nrm, rgb))
+    assert g.stats()["dropped"] == nd == 5
+    s, c = g.export_accum()
+    _, _, oc = o.leaf_accum()
+    assert np.array_equal(c.astype(np.int64), oc)
+
+
+def test_uniform_enclosure_gpu(w, torch_dev):
+    """Closed box, every splat 1.0 on both sides: every inner node averages
+    to 1.0 and an interior point sees the uniform pdf 1/(4 pi)."""
+    torch, dev = torch_dev
+    rs = []
+    for a in range(3):
+        rs.append(synth.make_rect(a, 0.0, (0, 0), (1, 1), +1))
+        rs.append(synth.make_rect(a, 1.0, (0, 0), (1, 1), -1))
+    rs = np.array(rs, synth.RECT_DTYPE)
+    g = w.svo_build(rs, 5)
+    keys, nrm, _ = g.export_level(5)
+    xyz = np.stack([np.array([sum(((int(k) >> (3 * i + a)) & 1) << i for i in range(5)) for k in keys])
+                    for a in range(3)], 1)
+    sp = synth.leaf_splats(xyz, nrm, np.zeros(len(keys)), 5)
+    ones = np.ones_like(sp[2])
+    w.svo_accumulate(g, *to_dev(torch_dev, sp[0], sp[1], ones))
+    for l in range(6):
+        _, _, ex = g.export_level(l)
+        assert (ex == 1.0).all()
+    pos = torch.rand((3, 64), device=dev) * 0.8 + 0.1
+    pdf = w.guide_pdf(g, pos, w.make_opts(N=16))
+    assert torch.allclose(pdf, torch.full_like(pdf, 1 / (4 * math.pi)), rtol=1e-6)
+
+
+# ------------------------------------------------- full size, bench launch ---
+def test_full_size_headline_queue(orc, c2, w, torch_dev):
+    """guide_sample over the whole 1920x1080 camera queue in the benchmark's
+    launch configuration; every 1013th vertex checked against the oracle."""
+    torch, dev = torch_dev
+    cam = c2["cam"]
+    (dpos,) = to_dev(torch_dev, cam)
+    opts = w.make_opts(N=16)
+    d, p = w.guide_sample(c2["g"], dpos, opts, seed=2024, bounce=0)
+    d2, p2 = w.guide_sample(c2["g"], dpos, opts, seed=2024, bounce=0)
+    assert torch.equal(d, d2) and torch.equal(p, p2)   # deterministic
+    assert torch.isfinite(p).all() and (p > 0).all()
+    assert torch.allclose(torch.linalg.norm(d, dim=0), torch.ones_like(p), atol=2e-6)
+    idx = np.arange(0, cam.shape[1], 1013)
+    sub = np.ascontiguousarray(cam[:, idx])
+    ref = c2["o"].guide_sample(sub, 16, seed=2024, bounce=0, counter=idx)
+    gd = d.cpu().numpy()[:, idx].astype(np.float64)
+    gp = p.cpu().numpy()[idx].astype(np.float64)
+    xy = orc.oct_encode_many(gd)
+    gb = np.stack([np.minimum((xy[0] * 16).astype(int), 15), np.minimum((xy[1] * 16).astype(int), 15)], 1)
+    same = (gb == ref["bin"]).all(1)
+    fx, fy = xy[0] * 16, xy[1] * 16
+    edge = np.minimum(np.abs(fx - np.rint(fx)), np.abs(fy - np.rint(fy)))
+    assert not (~same & (ref["margin"].min(1) >= BAND) & (edge > EDGE)).any()
+    rel = np.abs(gp[same] - ref["pdf"][same]) / ref["pdf"][same]
+    assert same.mean() > 0.99 and rel.max() <= 1e-5
+    assert g_stats_ok(c2["g"])
+
+
+def g_stats_ok(g):
+    return g.stats()["errors"] == 0

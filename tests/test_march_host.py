@@ -1,0 +1,107 @@
+"""The library's traversal core (march_core.h), compiled for the host with
+g++, against the oracle: every (vertex, bin) record bit-exact. This checks
+the exact logic the gfx950 kernels run without needing a GPU."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("host") / "march_host.so"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
+                           "-ffp-contract=off", os.path.join(HERE, "host", "march_host.cpp"),
+                           "-o", str(out)])
+    L = C.CDLL(str(out))
+    L.host_debug_march.restype = None
+    L.host_debug_march.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_int64,
+                                                       C.c_void_p, C.c_int, C.c_float,
+                                                       C.c_void_p, C.c_void_p]
+    return L
+
+
+def level_words(l):
+    return 1 if l <= 2 else 1 << (3 * l - 6)
+
+
+def bitmaps_from_oracle(o, D):
+    """Dense per-level bitmaps + per-word ranks (global node index), built
+    from the oracle's sorted level keys."""
+    woff = np.cumsum([0] + [level_words(l) for l in range(D + 1)])
+    bits = np.zeros(woff[-1], np.uint64)
+    rank = np.zeros(woff[-1], np.uint32)
+    noff = np.zeros(12, np.int64)
+    nrm = []
+    base = 0
+    for l in range(D + 1):
+        k = o.keys(l).astype(np.int64)
+        noff[l] = base
+        np.bitwise_or.at(bits, woff[l] + (k >> 6), (np.uint64(1) << (k & 63).astype(np.uint64)))
+        words = bits[woff[l]:woff[l + 1]]
+        pc = np.array([bin(int(x)).count("1") for x in words], np.int64) if len(words) < 5000 else \
+            np.unpackbits(words.view(np.uint8)).reshape(-1, 64).sum(1)
+        rank[woff[l]:woff[l + 1]] = (base + np.concatenate([[0], np.cumsum(pc)[:-1]])).astype(np.uint32)
+        base += len(k)
+        nrm.append(o.normals(l))
+    noff[D + 1:] = base
+    return bits, rank, noff, np.ascontiguousarray(np.concatenate(nrm, 0))
+
+
+def run_host(L, o, D, pos, N):
+    import paper_2405_06997_amd as w   # host table only (no device work)
+    bits, rank, noff, nrm = bitmaps_from_oracle(o, D)
+    pos = np.ascontiguousarray(pos, np.float32)
+    n = pos.shape[1]
+    tab = np.ascontiguousarray(w.dir_table(N))
+    out = np.zeros((n, N * N, 8), np.int32)
+    vis = np.zeros((n, N * N), np.int32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    L.host_debug_march(p(bits), p(rank), p(noff), p(nrm), D, p(pos), n, p(tab), N,
+                       float(np.float32(4 * np.pi / (N * N))), p(out), p(vis))
+    return out.astype(np.int64), vis.astype(np.int64)
+
+
+def compare(orc_svo, got, gvis, pos, N):
+    want, wvis = orc_svo.debug_march(pos, N, lds_levels=5, hier=False, visits=True)
+    hit = want[..., 0] == 1
+    assert np.array_equal(got[..., 0], want[..., 0])
+    assert np.array_equal(got[hit], want[hit])
+    assert np.array_equal(gvis, wvis)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_host_core_cornell(orc, host_lib, N):
+    box = synth.cornell_box()
+    o = orc.SVO(box, 6)
+    pos, _, _ = synth.area_points(box, 2048, 3)
+    got, vis = run_host(host_lib, o, 6, pos, N)
+    compare(o, got, vis, pos, N)
+
+
+def test_host_core_boundaries(orc, host_lib):
+    """Query points on cell corners, faces and the cube's faces (p = 0, 1)."""
+    box = synth.cornell_box()
+    o = orc.SVO(box, 5)
+    rng = np.random.default_rng(3)
+    pos = (rng.integers(0, 33, (3, 1500)) / 32.0).astype(np.float32)
+    pos[:, :500] = np.where(rng.random((3, 500)) < 0.5, pos[:, :500], rng.random((3, 500)))
+    got, vis = run_host(host_lib, o, 5, pos, 8)
+    compare(o, got, vis, pos, 8)
+
+
+def test_host_core_room(orc, host_lib):
+    room = synth.room()
+    o = orc.SVO(room, 10)
+    cam, _, _ = synth.camera_queue(room)
+    idx = np.random.default_rng(0).choice(cam.shape[1], 96, replace=False)
+    rnd, _, _ = synth.area_points(room, 96, 14)
+    pos = np.concatenate([cam[:, idx], rnd], 1)
+    got, vis = run_host(host_lib, o, 10, pos, 16)
+    compare(o, got, vis, pos, 16)
