@@ -243,6 +243,40 @@ wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n,
                              const wfpg_opts *opts, int32_t *out, int32_t *visits,
                              void *hip_stream);
 
+/* ---------------------------------------------------------------------
+ * Launch shape of the guide kernels and its autotuner. A tile is the number
+ * of waves per workgroup (one wave per vertex), the number of top SVO levels
+ * staged in LDS (levels 0..lds_levels-1) and the persistent grid size in
+ * workgroups per compute unit. Tiles are cached per (device, N, SVO depth,
+ * exitance format); guide_pdf, guide_sample, pdf_eval use the cached tile or
+ * a default. Results never depend on the tile.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t waves_per_block;
+    int32_t lds_levels;
+    int32_t blocks_per_cu;
+} wfpg_tile;
+
+/* Current tile for resolution N. EINVAL for bad arguments. */
+wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out);
+
+/* Force a tile for resolution N (EINVAL if it exceeds the kernel's limits:
+ * 1..16 waves, 1..depth+1 levels, 1..64 blocks per CU, 64 KiB of LDS). */
+wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile);
+
+/* Sweep candidate tiles for resolution N on the given DEVICE queue pos
+ * (3 x n), time guide_sample with HIP events (median of reps), cache and
+ * return the fastest (best_out, best_ms may be NULL). Allocates its own
+ * scratch outputs; synchronizes the stream. */
+wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N, int32_t reps,
+                          void *hip_stream, wfpg_tile *best_out, float *best_ms);
+
+/* Per-vertex work counts of the march, for measurement: counts (DEVICE
+ * n x 2 int32) = {occupancy tests at levels >= 5 summed over the vertex's
+ * N*N bins, number of bins that hit}. The same traversal as guide_sample. */
+wfpg_status wfpg_march_counts(const wfpg_svo *svo, const float *pos, int64_t n,
+                              const wfpg_opts *opts, int32_t *counts, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,7 @@ def lib():
             "orc_eval_one": (None, [vp, vp, vp, i32, vp, vp]),
             "orc_oct_encode_many": (None, [vp, i64, vp]),
             "orc_oct_decode_many": (None, [vp, i64, vp]),
+            "orc_num_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -94,6 +95,10 @@ def _soa(a, dtype=np.float32):
     a = np.ascontiguousarray(a, dtype=dtype)
     assert a.ndim == 2 and a.shape[0] == 3
     return a
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def morton(x: int, y: int, z: int) -> int:

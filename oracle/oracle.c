@@ -21,6 +21,7 @@
  * exitance per leaf, side-aligned bottom-up averaging, Philox-4x32-10 uniforms.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1009,4 +1010,16 @@ void orc_oct_decode_many(const double *xy, int64_t n, double *d)
         orc_oct_decode(xy[i], xy[n + i], o);
         d[i] = o[0]; d[n + i] = o[1]; d[2 * n + i] = o[2];
     }
+}
+
+/* Number of OpenMP threads the parallel loops above use. */
+int32_t orc_num_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
 }

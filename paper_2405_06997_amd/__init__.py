@@ -32,6 +32,7 @@ EXPORTS = [
     "wfpg_default_opts", "wfpg_status_string", "svo_build", "svo_destroy", "svo_accumulate",
     "guide_pdf", "guide_sample", "pdf_eval", "svo_stats", "svo_level_size", "svo_export_level",
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
+    "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
 ]
 
 
@@ -46,6 +47,11 @@ class WfpgError(RuntimeError):
             msg += f" [{detail}]"
         super().__init__(msg)
         self.status = status
+
+
+class Tile(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("lds_levels", C.c_int32),
+                ("blocks_per_cu", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -90,6 +96,10 @@ def lib():
         "svo_export_accum": (i32, [vp, vp, vp, vp]),
         "wfpg_dir_table": (i32, [i32, vp]),
         "wfpg_last_error": (C.c_char_p, []),
+        "wfpg_march_counts": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
+        "wfpg_get_tile": (i32, [vp, i32, C.POINTER(Tile)]),
+        "wfpg_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
+        "wfpg_autotune": (i32, [vp, vp, i64, i32, i32, vp, C.POINTER(Tile), C.POINTER(C.c_float)]),
         "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -260,3 +270,36 @@ def debug_march(svo: SVO, pos, opts: Opts, visits: bool = True, stream=None):
         svo.handle, _dptr(pos, 3, "pos"), n, C.byref(opts), _dptr(out, name="out"),
         _dptr(vis, name="visits") if visits else None, _stream(stream)))
     return out, vis
+
+
+def march_counts(svo: SVO, pos, opts: Opts, stream=None):
+    """Per-vertex (occupancy tests at levels >= 5, hit bins), (n, 2) int32."""
+    import torch
+    n = pos.shape[1]
+    out = torch.empty((n, 2), dtype=torch.int32, device=pos.device)
+    _check("wfpg_march_counts", lib().wfpg_march_counts(svo.handle, _dptr(pos, 3, "pos"), n,
+                                                        C.byref(opts), _dptr(out, name="counts"),
+                                                        _stream(stream)))
+    return out
+
+
+def get_tile(svo: SVO, N: int) -> dict:
+    t = Tile()
+    _check("wfpg_get_tile", lib().wfpg_get_tile(svo.handle, N, C.byref(t)))
+    return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
+                blocks_per_cu=t.blocks_per_cu)
+
+
+def set_tile(svo: SVO, N: int, waves_per_block: int, lds_levels: int, blocks_per_cu: int):
+    t = Tile(waves_per_block, lds_levels, blocks_per_cu)
+    _check("wfpg_set_tile", lib().wfpg_set_tile(svo.handle, N, C.byref(t)))
+
+
+def autotune(svo: SVO, pos, N: int, reps: int = 3, stream=None) -> dict:
+    """Sweep launch shapes on a device queue; caches and returns the best."""
+    t = Tile()
+    ms = C.c_float(0)
+    _check("wfpg_autotune", lib().wfpg_autotune(svo.handle, _dptr(pos, 3, "pos"), pos.shape[1], N,
+                                                reps, _stream(stream), C.byref(t), C.byref(ms)))
+    return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
+                blocks_per_cu=t.blocks_per_cu, ms=ms.value)

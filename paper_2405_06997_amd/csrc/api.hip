@@ -123,15 +123,6 @@ bool valid_opts(const wfpg_opts *o)
     return true;
 }
 
-TileConfig default_tile(const wfpg_svo *svo, int N)
-{
-    TileConfig t;
-    t.waves_per_block = 4;
-    t.lds_levels = std::min(7, svo->depth + 1);
-    t.blocks_per_cu = N == 32 ? 4 : 8;
-    return t;
-}
-
 GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o)
 {
     GuideArgs a;
@@ -272,7 +263,7 @@ static wfpg_status guide_common(const wfpg_svo *svo, int mode, const wfpg_opts *
                                 void *hip_stream)
 {
     if (!a.dirtab) return WFPG_ENOMEM;
-    return from_hip(launch_guide(svo, o->N, mode, a, default_tile(svo, o->N), (hipStream_t)hip_stream));
+    return from_hip(launch_guide(svo, o->N, mode, a, choose_tile(svo, o->N), (hipStream_t)hip_stream));
 }
 
 wfpg_status guide_pdf(const wfpg_svo *svo, const float *pos, int64_t n, const wfpg_opts *opts,
@@ -332,6 +323,18 @@ wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n, c
     a.dbg_out = out;
     a.dbg_visits = visits;
     return guide_common(svo, MODE_DEBUG, opts, a, hip_stream);
+}
+
+wfpg_status wfpg_march_counts(const wfpg_svo *svo, const float *pos, int64_t n, const wfpg_opts *opts,
+                              int32_t *counts, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !counts))) return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.n = n;
+    a.dbg_out = counts;
+    return guide_common(svo, MODE_COUNT, opts, a, hip_stream);
 }
 
 wfpg_status svo_stats(const wfpg_svo *svo, int64_t *leaves, int64_t *nodes, int64_t *dropped_splats,

@@ -18,7 +18,6 @@ namespace wfpg {
 namespace {
 
 using core::Hit;
-using core::Ray;
 using core::woff;
 
 __device__ __forceinline__ float round16(float f, int fmt)
@@ -89,99 +88,159 @@ __device__ __forceinline__ float seg_scan(float v, int lane)
     return v;
 }
 
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+constexpr uint32_t kMissRec = 0xffffffffu;
+
+// LDS layout of a block: [top-level bitmap words][N*N*3 bin directions]
+// [per wave: N*N hit records {key | axis << 30, delta}].
 template <int N, int MODE>
-__global__ void __launch_bounds__(512) k_guide(SvoView sv, GuideArgs a, int lds_levels)
+__global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds_levels)
 {
     constexpr int NN = N * N;
-    constexpr int BPL = NN / 64;  // bins per lane
+    constexpr int BPL = NN / 64;  // bins per lane in the value pass
     constexpr int G = 64 / N;     // rows per 64-bin pass
-    extern __shared__ uint64_t lbits[];
+    extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
     const int D = sv.depth;
     const int fmt = sv.fmt;
     const uint32_t nlw = woff(lds_levels);
+    uint64_t *lbits = smem;
+    float *ldir = reinterpret_cast<float *>(smem + nlw);
+    uint32_t *lrec = reinterpret_cast<uint32_t *>(ldir + 3 * NN) + (size_t)wave * 2 * NN;
     for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
+    for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) ldir[t] = a.dirtab[t];
     __syncthreads();
 
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
-    // per-lane bin directions (FP32 table) and their quantization
-    float dx[BPL], dy[BPL], dz[BPL];
-    int qq[BPL][3];
-#pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-        const int b = j * 64 + lane;
-        dx[j] = a.dirtab[3 * b];
-        dy[j] = a.dirtab[3 * b + 1];
-        dz[j] = a.dirtab[3 * b + 2];
-        qq[j][0] = core::quantize_dir(dx[j]);
-        qq[j][1] = core::quantize_dir(dy[j]);
-        qq[j][2] = core::quantize_dir(dz[j]);
-    }
-    auto bits = [&](int lvl, uint32_t wi) -> uint64_t {
-        return lvl < lds_levels ? lbits[wi] : sv.bits[wi];
+    const uint64_t *gbits = sv.bits;
+    auto bits = [gbits, lbits, lds_levels](int lvl, uint32_t wi) -> uint64_t {
+        return lvl < lds_levels ? lbits[wi] : gbits[wi];
     };
 
     for (int64_t i = (int64_t)blockIdx.x * W + wave; i < n; i += (int64_t)gridDim.x * W) {
-        uint32_t O[3], oc[3];
+        uint32_t O[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            O[k] = core::quantize_pos(a.pos[k * n + i]);
-            oc[k] = O[k] >> (WFPG_FINE - D);
+        for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(a.pos[k * n + i]);
+
+        // ---- march every bin; lanes that finish take the next unmarched bin
+        int bin = lane;          // N*N >= 64
+        int next = 64;
+        int vis = 0, vis_tot = 0, iters = 0;
+        core::MarchState st;
+        core::march_begin(st, O, core::quantize_dir(ldir[3 * bin]), core::quantize_dir(ldir[3 * bin + 1]),
+                          core::quantize_dir(ldir[3 * bin + 2]), D);
+        while (true) {
+            const bool act = bin >= 0;
+            if (__ballot(act) == 0ull) break;
+            int res = core::STEP_CONTINUE;
+            Hit h = {-1, 0u, 0u};
+            if (act) {
+                res = core::march_step(st, D, bits, 5, vis, h);
+                if (res == core::STEP_CONTINUE && ++iters >= core::kMaxIt) {
+                    atomicOr(a.err, 1);
+                    res = core::STEP_MISS;
+                }
+            }
+            const bool fin = act && res != core::STEP_CONTINUE;
+            if (fin) {
+                lrec[2 * bin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
+                lrec[2 * bin + 1] = h.delta;
+                if constexpr (MODE == MODE_DEBUG) {
+                    if (a.dbg_visits) a.dbg_visits[(size_t)i * NN + bin] = vis;
+                }
+                vis_tot += vis;
+            }
+            const uint64_t fm = __ballot(fin);
+            if (fm) {
+                if (fin) {
+                    const int nb = next + lanes_below(fm);
+                    bin = nb < NN ? nb : -1;
+                    if (bin >= 0) {
+                        core::march_begin(st, O, core::quantize_dir(ldir[3 * bin]),
+                                          core::quantize_dir(ldir[3 * bin + 1]),
+                                          core::quantize_dir(ldir[3 * bin + 2]), D);
+                        vis = 0;
+                        iters = 0;
+                    }
+                }
+                next += __popcll(fm);
+            }
         }
-        const uint32_t origin_key = core::morton3(oc[0], oc[1], oc[2]);
+        wave_lds_fence();
+
+        // ---- field values: footprint level, node, side, exitance + eps
         float L[BPL];
+        int hit_sum = 0;
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            Ray ray;
-            core::make_ray(O, qq[j][0], qq[j][1], qq[j][2], ray);
-            int vis = 0;
-            Hit h = {-1, 0u, 0u};
-            const int res = core::march(ray, D, origin_key, bits, 5, vis, h);
-            if (res < 0) atomicOr(a.err, 1);
-            float val = a.eps;
+            const int b = j * 64 + lane;
+            const uint32_t rec = lrec[2 * b];
+            float val = fmt == WFPG_FP32 ? a.eps : round16(a.eps, fmt);
             int k = -1, side = 0;
             uint32_t node = 0;
             int64_t nidx = -1;
-            if (res > 0) {
-                const float dsel = h.axis == 0 ? dx[j] : (h.axis == 1 ? dy[j] : dz[j]);
-                k = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
+            if (rec != kMissRec) {
+                const int axis = (int)(rec >> 30);
+                const uint32_t key = rec & 0x3fffffffu;
+                const float dx = ldir[3 * b], dy = ldir[3 * b + 1], dz = ldir[3 * b + 2];
+                const float dsel = axis == 0 ? dx : (axis == 1 ? dy : dz);
+                k = core::footprint_levels(lrec[2 * b + 1], fabsf(dsel), D, a.omega);
                 const int lf = D - k;
-                node = h.key >> (3 * k);
+                node = key >> (3 * k);
                 const uint32_t wi = woff(lf) + (node >> 6);
                 const uint64_t w = sv.bits[wi];
                 const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
                 const int64_t g = (int64_t)sv.rank[wi] + __popcll(msk);
                 nidx = g - sv.noff[lf];
                 const float4 Nn = sv.nrm[g];
-                side = core::dot3(Nn.x, Nn.y, Nn.z, dx[j], dy[j], dz[j]) < 0.f ? 0 : 1;
+                side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
                 if (fmt == WFPG_FP32) {
                     const float2 e = sv.e32[g];
                     val = (side ? e.y : e.x) + a.eps;
                 } else {
                     val = round16(unpack16(sv.e16[g], side, fmt) + a.eps, fmt);
                 }
-            } else if (fmt != WFPG_FP32) {
-                val = round16(a.eps, fmt);
+                ++hit_sum;
+                if constexpr (MODE == MODE_DEBUG) {
+                    int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
+                    o[0] = 1; o[1] = axis; o[2] = (int32_t)key; o[3] = (int32_t)lrec[2 * b + 1];
+                    o[4] = k; o[5] = (int32_t)node; o[6] = (int32_t)nidx; o[7] = side;
+                }
+            } else if constexpr (MODE == MODE_DEBUG) {
+                int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
+                o[0] = 0; o[1] = -1; o[2] = -1; o[3] = -1; o[4] = -1; o[5] = -1; o[6] = -1; o[7] = 0;
             }
             L[j] = val;
-            if constexpr (MODE == MODE_DEBUG) {
-                int32_t *o = a.dbg_out + ((size_t)i * NN + j * 64 + lane) * 8;
-                o[0] = res > 0;
-                o[1] = res > 0 ? h.axis : -1;
-                o[2] = res > 0 ? (int32_t)h.key : -1;
-                o[3] = res > 0 ? (int32_t)h.delta : -1;
-                o[4] = k;
-                o[5] = res > 0 ? (int32_t)node : -1;
-                o[6] = (int32_t)nidx;
-                o[7] = side;
-                if (a.dbg_visits) a.dbg_visits[(size_t)i * NN + j * 64 + lane] = vis;
-            }
         }
+        wave_lds_fence();
         if constexpr (MODE == MODE_DEBUG) continue;
+        if constexpr (MODE == MODE_COUNT) {
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                vis_tot += __shfl_xor(vis_tot, d);
+                hit_sum += __shfl_xor(hit_sum, d);
+            }
+            if (lane == 0) {
+                a.dbg_out[2 * i] = vis_tot;
+                a.dbg_out[2 * i + 1] = hit_sum;
+            }
+            continue;
+        }
 
-        // row CDFs (segmented inclusive scans), marginal CDF over the row sums
+        // ---- row CDFs (segmented inclusive scans), marginal CDF over row sums
         float S[BPL];
 #pragma unroll
         for (int j = 0; j < BPL; ++j) S[j] = seg_scan<N>(L[j], lane);
@@ -198,8 +257,7 @@ __global__ void __launch_bounds__(512) k_guide(SvoView sv, GuideArgs a, int lds_
         if constexpr (MODE == MODE_PDF) {
 #pragma unroll
             for (int j = 0; j < BPL; ++j)
-                a.pdf_out[(size_t)i * NN + j * 64 + lane] =
-                    __fmul_rn(__fdiv_rn(L[j], total), a.pdf_scale);
+                a.pdf_out[(size_t)i * NN + j * 64 + lane] = (L[j] / total) * a.pdf_scale;
         } else if constexpr (MODE == MODE_SAMPLE) {
             uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
             philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
@@ -224,12 +282,11 @@ __global__ void __launch_bounds__(512) k_guide(SvoView sv, GuideArgs a, int lds_
             if (lane == 0) {
                 const float inv = 1.f / (float)N;
                 float ox, oy, oz;
-                oct_decode(__fadd_rn((float)u * inv, u3 * inv), __fadd_rn((float)v * inv, u4 * inv),
-                           ox, oy, oz);
+                oct_decode((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
                 a.dir_out[i] = ox;
                 a.dir_out[n + i] = oy;
                 a.dir_out[2 * n + i] = oz;
-                a.pdf_out[i] = __fmul_rn(__fdiv_rn(Lb, total), a.pdf_scale);
+                a.pdf_out[i] = (Lb / total) * a.pdf_scale;
             }
         } else if constexpr (MODE == MODE_EVAL) {
             float ex, ey;
@@ -242,7 +299,7 @@ __global__ void __launch_bounds__(512) k_guide(SvoView sv, GuideArgs a, int lds_
             for (int j = 1; j < BPL; ++j)
                 if (j == jv) Lj = L[j];
             const float Lb = __shfl(Lj, gv * N + u);
-            if (lane == 0) a.pdf_out[i] = __fmul_rn(__fdiv_rn(Lb, total), a.pdf_scale);
+            if (lane == 0) a.pdf_out[i] = (Lb / total) * a.pdf_scale;
         }
     }
 }
@@ -255,13 +312,14 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a, const Til
     const int64_t want = a.n_dev ? INT64_MAX : (a.n + W - 1) / W;
     const int64_t cap = (int64_t)device_cu_count() * tc.blocks_per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    const size_t lds = (size_t)level_woff(tc.lds_levels) * sizeof(uint64_t);
+    const size_t lds = guide_lds_bytes(N, tc);
     const dim3 blk(64 * W);
     const wfpg::SvoView v = svo->view();
     switch (mode) {
     case MODE_SAMPLE: hipLaunchKernelGGL((k_guide<N, MODE_SAMPLE>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     case MODE_PDF: hipLaunchKernelGGL((k_guide<N, MODE_PDF>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     case MODE_EVAL: hipLaunchKernelGGL((k_guide<N, MODE_EVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    case MODE_COUNT: hipLaunchKernelGGL((k_guide<N, MODE_COUNT>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     default: hipLaunchKernelGGL((k_guide<N, MODE_DEBUG>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     }
     return hipGetLastError();

@@ -22,8 +22,10 @@
 
 #if defined(__HIPCC__)
 #define WFPG_HD __host__ __device__ __forceinline__
+#define WFPG_UNROLL _Pragma("unroll")
 #else
 #define WFPG_HD inline
+#define WFPG_UNROLL
 #endif
 
 namespace wfpg {
@@ -67,114 +69,152 @@ WFPG_HD int quantize_dir(float d)
     return (int)__builtin_rintf(d * 8388608.0f);   // exact scaling, |q| <= 2^23
 }
 
-struct Ray {
-    uint32_t O[3];    // origin, 2^-30 units
-    uint32_t aq[3];   // |q|
-    int sg[3];        // sign(q)
-};
-
-WFPG_HD void make_ray(const uint32_t O[3], int q0, int q1, int q2, Ray &r)
-{
-    const int q[3] = {q0, q1, q2};
-    for (int k = 0; k < 3; ++k) {
-        r.O[k] = O[k];
-        r.aq[k] = (uint32_t)(q[k] < 0 ? -q[k] : q[k]);
-        r.sg[k] = (q[k] > 0) - (q[k] < 0);
-    }
-}
-
 struct Hit {
     int axis;          // axis of the crossing that entered the hit leaf
     uint32_t key;      // hit leaf key
     uint32_t delta;    // |B - O| of that crossing, 2^-30 units
 };
 
-// Bits(level, word_index) -> uint64 occupancy word. Returns 1 on a hit, 0 on
-// a miss and -1 if the iteration bound is exceeded (never expected).
-template <class Bits>
-WFPG_HD int march(const Ray &r, int D, uint32_t origin_key, const Bits &bits, int count_from,
-                  int &vis, Hit &h)
+// Resumable march state: the ray, the current cell (level, key, lower
+// corner), the last crossing (parameter tn/td on axis ta; ta = -1 at the
+// start) and the cell entered by that crossing (tlvl, tkey) while its
+// ancestors are retested. Plain scalars only, so that the state lives in
+// registers.
+struct MarchState {
+    uint32_t O0, O1, O2;      // origin, 2^-30 units
+    uint32_t aq0, aq1, aq2;   // |q|
+    int sg0, sg1, sg2;        // sign(q)
+    uint32_t origin_key;
+    int lvl, tlvl, ta;
+    uint32_t key, tkey, tn, td;
+    uint32_t lo0, lo1, lo2;
+};
+
+WFPG_HD void march_begin(MarchState &s, const uint32_t O[3], int q0, int q1, int q2, int D)
 {
-    int lvl = 0;
-    uint32_t key = 0;
-    uint32_t lo0 = 0, lo1 = 0, lo2 = 0;
-    int tlvl = 0;
-    uint32_t tkey = 0;
-    uint32_t tn = 0, td = 1;
-    int ta = -1;
-    for (int it = 0; it < kMaxIt; ++it) {
-        const uint64_t w = bits(lvl, woff(lvl) + (key >> 6));
-        vis += (lvl >= count_from);
-        if ((w >> (key & 63)) & 1ull) {
-            if (lvl == D) {
-                if (key != origin_key) {
-                    h.axis = ta;
-                    h.key = key;
-                    h.delta = tn;
-                    return 1;
-                }
-            } else {
-                const uint32_t half = 1u << (29 - lvl);
-                uint32_t oct;
-                if (lvl < tlvl) {
-                    oct = (tkey >> (3 * (tlvl - lvl - 1))) & 7u;
-                } else {
-                    oct = 0;
-                    const uint32_t lo[3] = {lo0, lo1, lo2};
-                    for (int j = 0; j < 3; ++j) {
-                        const uint32_t M = lo[j] + half;
-                        bool up;
-                        if (r.sg[j] == 0) {
-                            up = r.O[j] >= M;
-                        } else {
-                            int32_t dl = (int32_t)(M - r.O[j]);
-                            if (r.sg[j] < 0) dl = -dl;
-                            const int64_t lhs = (int64_t)dl * (int64_t)td -
-                                                (int64_t)((uint64_t)tn * r.aq[j]);
-                            const bool crossed =
-                                lhs < (int64_t)(j <= ta) || (r.sg[j] > 0 && dl == 0);
-                            up = crossed != (r.sg[j] < 0);
-                        }
-                        oct |= (uint32_t)up << j;
-                    }
-                }
-                key = (key << 3) | oct;
-                lo0 += (oct & 1u) ? half : 0u;
-                lo1 += (oct & 2u) ? half : 0u;
-                lo2 += (oct & 4u) ? half : 0u;
-                ++lvl;
-                continue;
+    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
+    s.aq0 = (uint32_t)(q0 < 0 ? -q0 : q0);
+    s.aq1 = (uint32_t)(q1 < 0 ? -q1 : q1);
+    s.aq2 = (uint32_t)(q2 < 0 ? -q2 : q2);
+    s.sg0 = (q0 > 0) - (q0 < 0);
+    s.sg1 = (q1 > 0) - (q1 < 0);
+    s.sg2 = (q2 > 0) - (q2 < 0);
+    s.origin_key = morton3(O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D));
+    s.lvl = 0; s.tlvl = 0; s.ta = -1;
+    s.key = 0; s.tkey = 0; s.tn = 0; s.td = 1;
+    s.lo0 = 0; s.lo1 = 0; s.lo2 = 0;
+}
+
+enum { STEP_CONTINUE = 0, STEP_HIT = 1, STEP_MISS = 2 };
+
+// Which half of a cell the ray is in along one axis just after the current
+// crossing (tn/td, ta): the mid-plane M counts as crossed iff its crossing
+// parameter is smaller, or equal with an axis not above ta.
+WFPG_HD uint32_t upper_half(uint32_t M, uint32_t O, uint32_t aq, int sg, int j, uint32_t tn,
+                            uint32_t td, int ta)
+{
+    if (sg == 0) return O >= M ? 1u : 0u;
+    int32_t dl = (int32_t)(M - O);
+    if (sg < 0) dl = -dl;
+    const int64_t lhs = (int64_t)dl * (int64_t)td - (int64_t)((uint64_t)tn * aq);
+    const bool crossed = lhs < (int64_t)(j <= ta) || (sg > 0 && dl == 0);
+    return (crossed != (sg < 0)) ? 1u : 0u;
+}
+
+// Distance (2^-30 units) from O to the far face of [lo, lo + size) along
+// the ray's direction on one axis (1 when the axis is not crossed).
+WFPG_HD uint32_t far_face(uint32_t lo, uint32_t size, uint32_t O, int sg)
+{
+    return sg > 0 ? lo + size - O : (sg < 0 ? O - lo : 1u);
+}
+
+// One occupancy test followed by a descent or an exit step.
+// Bits(level, word_index) -> uint64 occupancy word.
+template <class Bits>
+WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
+{
+    const uint64_t w = bits(s.lvl, woff(s.lvl) + (s.key >> 6));
+    vis += (s.lvl >= count_from);
+    if ((w >> (s.key & 63)) & 1ull) {
+        if (s.lvl == D) {
+            if (s.key != s.origin_key) {
+                h.axis = s.ta;
+                h.key = s.key;
+                h.delta = s.tn;
+                return STEP_HIT;
             }
+        } else {
+            const uint32_t half = 1u << (29 - s.lvl);
+            uint32_t oct;
+            if (s.lvl < s.tlvl) {
+                oct = (s.tkey >> (3 * (s.tlvl - s.lvl - 1))) & 7u;
+            } else {
+                oct = upper_half(s.lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
+                      (upper_half(s.lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
+                      (upper_half(s.lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
+            }
+            s.key = (s.key << 3) | oct;
+            s.lo0 += (oct & 1u) ? half : 0u;
+            s.lo1 += (oct & 2u) ? half : 0u;
+            s.lo2 += (oct & 4u) ? half : 0u;
+            ++s.lvl;
+            return STEP_CONTINUE;
         }
-        // leave the current cell (empty, or the origin's leaf)
-        const uint32_t size = 1u << (kFine - lvl);
-        const uint32_t dl0 = r.sg[0] > 0 ? lo0 + size - r.O[0] : (r.sg[0] < 0 ? r.O[0] - lo0 : 1u);
-        const uint32_t dl1 = r.sg[1] > 0 ? lo1 + size - r.O[1] : (r.sg[1] < 0 ? r.O[1] - lo1 : 1u);
-        const uint32_t dl2 = r.sg[2] > 0 ? lo2 + size - r.O[2] : (r.sg[2] < 0 ? r.O[2] - lo2 : 1u);
-        int e = 0;
-        uint32_t De = dl0, Qe = r.aq[0];
-        if ((uint64_t)dl1 * Qe < (uint64_t)De * r.aq[1]) { e = 1; De = dl1; Qe = r.aq[1]; }
-        if ((uint64_t)dl2 * Qe < (uint64_t)De * r.aq[2]) { e = 2; De = dl2; Qe = r.aq[2]; }
-        const int s = e == 0 ? r.sg[0] : (e == 1 ? r.sg[1] : r.sg[2]);
-        const uint32_t le = e == 0 ? lo0 : (e == 1 ? lo1 : lo2);
-        const int64_t nl = (int64_t)le + (int64_t)s * (int64_t)size;
-        if (nl < 0 || nl >= (1ll << kFine)) return 0;
-        const uint32_t oldc = le >> (kFine - lvl), newc = (uint32_t)nl >> (kFine - lvl);
-        if (e == 0) lo0 = (uint32_t)nl; else if (e == 1) lo1 = (uint32_t)nl; else lo2 = (uint32_t)nl;
-        const uint32_t m = 0x09249249u << e;
-        key = s > 0 ? ((((key | ~m) + 1u) & m) | (key & ~m)) : ((((key & m) - 1u) & m) | (key & ~m));
-        tn = De;
-        td = Qe;
-        ta = e;
-        tlvl = lvl;
-        tkey = key;
-        const int p = 31 - __builtin_clz(oldc ^ newc);
-        lvl -= p;
-        key >>= 3 * p;
-        const uint32_t mk = ~((1u << (kFine - lvl)) - 1u);
-        lo0 &= mk;
-        lo1 &= mk;
-        lo2 &= mk;
+    }
+    // leave the current cell (empty, or the origin's leaf)
+    const uint32_t size = 1u << (kFine - s.lvl);
+    const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
+    const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
+    const uint32_t dl2 = far_face(s.lo2, size, s.O2, s.sg2);
+    // lowest-parameter exit axis, ties to the lower axis; the per-axis values
+    // are picked with masks (a select between struct fields would be turned
+    // into a private-memory table by the compiler)
+    const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
+    const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
+    const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
+    const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
+    const int e = (int)((m1 & 1u) | (m2 & 2u));
+    const uint32_t De = (dl2 & m2) | (D01 & ~m2);
+    const uint32_t Qe = (s.aq2 & m2) | (Q01 & ~m2);
+    const int sgn = (int)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) | ((uint32_t)s.sg2 & m2));
+    const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
+    const int64_t nl = (int64_t)le + (int64_t)sgn * (int64_t)size;
+    if (nl < 0 || nl >= (1ll << kFine)) return STEP_MISS;
+    const uint32_t nlu = (uint32_t)nl;
+    const uint32_t oldc = le >> (kFine - s.lvl), newc = nlu >> (kFine - s.lvl);
+    s.lo0 = (nlu & m0) | (s.lo0 & ~m0);
+    s.lo1 = (nlu & m1) | (s.lo1 & ~m1);
+    s.lo2 = (nlu & m2) | (s.lo2 & ~m2);
+    const uint32_t m = 0x09249249u << e;
+    s.key = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m))
+                    : ((((s.key & m) - 1u) & m) | (s.key & ~m));
+    s.tn = De;
+    s.td = Qe;
+    s.ta = e;
+    s.tlvl = s.lvl;
+    s.tkey = s.key;
+    const int p = 31 - __builtin_clz(oldc ^ newc);
+    s.lvl -= p;
+    s.key >>= 3 * p;
+    const uint32_t mk = ~((1u << (kFine - s.lvl)) - 1u);
+    s.lo0 &= mk;
+    s.lo1 &= mk;
+    s.lo2 &= mk;
+    return STEP_CONTINUE;
+}
+
+// Whole march: 1 on a hit, 0 on a miss, -1 if the iteration bound is
+// exceeded (never expected).
+template <class Bits>
+WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits &bits,
+                  int count_from, int &vis, Hit &h)
+{
+    MarchState s;
+    march_begin(s, O, q0, q1, q2, D);
+    for (int it = 0; it < kMaxIt; ++it) {
+        const int st = march_step(s, D, bits, count_from, vis, h);
+        if (st == STEP_HIT) return 1;
+        if (st == STEP_MISS) return 0;
     }
     return -1;
 }
@@ -186,13 +226,17 @@ WFPG_HD int march(const Ray &r, int D, uint32_t origin_key, const Bits &bits, in
 WFPG_HD int footprint_levels(uint32_t delta, float dabs, int D, float omega)
 {
     float scale = 1.0f;
-    for (int i = 0; i < kFine - D; ++i) scale *= 0.5f;     // exact 2^-(30-D)
+    WFPG_UNROLL
+    for (int i = 0; i < kFine; ++i)                         // exact 2^-(30-D)
+        if (i < kFine - D) scale *= 0.5f;
     const float dist = ((float)delta * scale) / dabs;
     const float sq = dist * dist;
     const float A = sq * omega;
     int k = 0;
     float thr = 2.5f;
-    for (int j = 1; j <= D; ++j) {
+    WFPG_UNROLL
+    for (int j = 1; j <= 10; ++j) {
+        if (j > D) break;
         k += A > thr ? 1 : 0;
         thr *= 4.0f;
     }

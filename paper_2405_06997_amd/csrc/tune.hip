@@ -1,0 +1,177 @@
+// Autotuner of the guide kernel's launch shape (waves per block, SVO levels
+// staged in LDS, persistent grid size), cached per (device, N, depth, format).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "wfpg_internal.h"
+
+namespace wfpg {
+namespace {
+
+using Key = std::tuple<int, int, int, int>;   // device, N, depth, fmt
+std::mutex g_mu;
+std::map<Key, TileConfig> g_cache;
+
+Key key_of(const wfpg_svo *svo, int N)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return Key(dev, N, svo->depth, svo->fmt);
+}
+
+TileConfig default_tile(int N, int depth)
+{
+    TileConfig t;
+    t.waves_per_block = 4;
+    t.lds_levels = 6;
+    t.blocks_per_cu = N == 32 ? 4 : 8;
+    return legalize_tile(t, N, depth);
+}
+
+}  // namespace
+
+TileConfig legalize_tile(TileConfig t, int N, int depth)
+{
+    t.waves_per_block = std::min(std::max(t.waves_per_block, 1), 16);
+    t.blocks_per_cu = std::min(std::max(t.blocks_per_cu, 1), 64);
+    t.lds_levels = std::min(std::max(t.lds_levels, 1), std::min(7, depth + 1));
+    while (t.lds_levels > 1 && guide_lds_bytes(N, t) > kMaxGuideLds) --t.lds_levels;
+    while (t.waves_per_block > 1 && guide_lds_bytes(N, t) > kMaxGuideLds) --t.waves_per_block;
+    return t;
+}
+
+TileConfig choose_tile(const wfpg_svo *svo, int N)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_cache.find(key_of(svo, N));
+    if (it != g_cache.end()) return it->second;
+    return default_tile(N, svo->depth);
+}
+
+}  // namespace wfpg
+
+using namespace wfpg;
+
+extern "C" {
+
+wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out)
+{
+    if (!svo || !out || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
+    const TileConfig t = choose_tile(svo, N);
+    out->waves_per_block = t.waves_per_block;
+    out->lds_levels = t.lds_levels;
+    out->blocks_per_cu = t.blocks_per_cu;
+    return WFPG_OK;
+}
+
+wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile)
+{
+    if (!svo || !tile || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
+    TileConfig t;
+    t.waves_per_block = tile->waves_per_block;
+    t.lds_levels = tile->lds_levels;
+    t.blocks_per_cu = tile->blocks_per_cu;
+    if (t.waves_per_block < 1 || t.waves_per_block > 16 || t.blocks_per_cu < 1 ||
+        t.blocks_per_cu > 64 || t.lds_levels < 1 || t.lds_levels > svo->depth + 1 ||
+        guide_lds_bytes(N, t) > kMaxGuideLds)
+        return WFPG_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_cache[key_of(svo, N)] = t;
+    return WFPG_OK;
+}
+
+wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N, int32_t reps,
+                          void *hip_stream, wfpg_tile *best_out, float *best_ms)
+{
+    if (!svo || !pos || n <= 0 || reps < 1 || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    float *d_dir = nullptr, *d_pdf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc((void **)&d_dir, (size_t)n * 3 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_pdf, (size_t)n * sizeof(float));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const float *tab = device_dirtab(N);
+    TileConfig best = default_tile(N, svo->depth);
+    float best_t = 1e30f;
+    if (e == hipSuccess && tab) {
+        GuideArgs a;
+        std::memset(&a, 0, sizeof a);
+        const double pi = 3.14159265358979323846;
+        a.pos = pos;
+        a.n = n;
+        a.eps = 0.01f;
+        a.omega = (float)(4.0 * pi / (double)(N * N));
+        a.pdf_scale = (float)((double)(N * N) / (4.0 * pi));
+        a.dirtab = tab;
+        a.err = svo->d_err;
+        a.dir_out = d_dir;
+        a.pdf_out = d_pdf;
+        const int waves[] = {1, 2, 4, 8};
+        const int levels[] = {5, 6, 7};
+        const int bpcu[] = {2, 4, 8, 16};
+        std::vector<TileConfig> cand;
+        for (int w : waves)
+            for (int l : levels)
+                for (int b : bpcu) {
+                    TileConfig t;
+                    t.waves_per_block = w;
+                    t.lds_levels = std::min(l, svo->depth + 1);
+                    t.blocks_per_cu = b;
+                    if (guide_lds_bytes(N, t) > kMaxGuideLds) continue;
+                    bool dup = false;
+                    for (const TileConfig &c : cand)
+                        dup = dup || (c.waves_per_block == t.waves_per_block &&
+                                      c.lds_levels == t.lds_levels && c.blocks_per_cu == t.blocks_per_cu);
+                    if (!dup) cand.push_back(t);
+                }
+        for (const TileConfig &t : cand) {
+            e = launch_guide(svo, N, MODE_SAMPLE, a, t, s);   // warm-up
+            if (e != hipSuccess) break;
+            std::vector<float> ts;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = launch_guide(svo, N, MODE_SAMPLE, a, t, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                ts.push_back(ms);
+            }
+            if (e != hipSuccess) break;
+            std::sort(ts.begin(), ts.end());
+            const float med = ts[ts.size() / 2];
+            if (std::getenv("WFPG_TUNE_VERBOSE"))
+                std::fprintf(stderr, "tune N=%d waves=%d lds_levels=%d blocks/CU=%d: %.3f ms\n", N,
+                             t.waves_per_block, t.lds_levels, t.blocks_per_cu, med);
+            if (med < best_t) { best_t = med; best = t; }
+        }
+    }
+    if (d_dir) (void)hipFree(d_dir);
+    if (d_pdf) (void)hipFree(d_pdf);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return note_error(e, __FILE__, __LINE__) == hipErrorOutOfMemory ? WFPG_ENOMEM : WFPG_EDEVICE;
+    if (!tab) return WFPG_ENOMEM;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        g_cache[key_of(svo, N)] = best;
+    }
+    if (best_out) {
+        best_out->waves_per_block = best.waves_per_block;
+        best_out->lds_levels = best.lds_levels;
+        best_out->blocks_per_cu = best.blocks_per_cu;
+    }
+    if (best_ms) *best_ms = best_t;
+    return WFPG_OK;
+}
+
+}  // extern "C"

@@ -65,7 +65,7 @@ hipError_t launch_accumulate(struct ::wfpg_svo *svo, const float *pos, const flo
                              const float *rgb, int64_t n, hipStream_t s);
 hipError_t launch_propagate(struct ::wfpg_svo *svo, hipStream_t s);
 
-enum GuideMode { MODE_SAMPLE = 0, MODE_PDF = 1, MODE_EVAL = 2, MODE_DEBUG = 3 };
+enum GuideMode { MODE_SAMPLE = 0, MODE_PDF = 1, MODE_EVAL = 2, MODE_DEBUG = 3, MODE_COUNT = 4 };
 
 struct GuideArgs {
     const float *pos;
@@ -93,6 +93,19 @@ struct TileConfig {          // launch shape chosen by the autotuner
 
 hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const GuideArgs &a,
                         const TileConfig &tc, hipStream_t s);
+
+// LDS bytes of one guide block: staged bitmap levels, bin directions and the
+// per-wave hit records.
+inline size_t guide_lds_bytes(int N, const TileConfig &tc)
+{
+    return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 +
+           (size_t)tc.waves_per_block * N * N * 2 * 4;
+}
+constexpr size_t kMaxGuideLds = 64 * 1024;
+
+// Tile chosen for (device, N, depth, format): the autotuned one if present.
+TileConfig choose_tile(const struct ::wfpg_svo *svo, int N);
+TileConfig legalize_tile(TileConfig t, int N, int depth);
 
 int device_cu_count();
 // Records a failing HIP call (thread-local) for wfpg_last_error().

@@ -16,19 +16,14 @@ extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, con
     auto load = [&](int, uint32_t wi) -> uint64_t { return bits[wi]; };
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t i = 0; i < n; ++i) {
-        uint32_t O[3], oc[3];
-        for (int k = 0; k < 3; ++k) {
-            O[k] = quantize_pos(pos[k * n + i]);
-            oc[k] = O[k] >> (kFine - D);
-        }
-        const uint32_t origin = morton3(oc[0], oc[1], oc[2]);
+        uint32_t O[3];
+        for (int k = 0; k < 3; ++k) O[k] = quantize_pos(pos[k * n + i]);
         for (int b = 0; b < NN; ++b) {
             const float *d = dirtab + 3 * b;
-            Ray r;
-            make_ray(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), r);
             int vis = 0;
             Hit h = {-1, 0u, 0u};
-            const int res = march(r, D, origin, load, 5, vis, h);
+            const int res = march(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), D,
+                                  load, 5, vis, h);
             int32_t *o = out + ((int64_t)i * NN + b) * 8;
             o[0] = res > 0;
             o[1] = res > 0 ? h.axis : -1;

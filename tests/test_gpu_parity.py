@@ -158,6 +158,17 @@ def test_march_bitexact_c2(c2, w, torch_dev, N, k):
     _march_compare(c2["o"], c2["g"], w, torch_dev, np.concatenate([cam, rnd], 1), N)
 
 
+def test_march_counts_match_oracle(c2, w, torch_dev):
+    """The per-vertex work counts used for the benchmark's algorithmic bytes
+    equal the oracle's node-test and hit counts."""
+    cam, _ = sample_cols(c2["cam"], 128, 21)
+    (dpos,) = to_dev(torch_dev, cam)
+    cnt = w.march_counts(c2["g"], dpos, w.make_opts(N=16)).cpu().numpy().astype(np.int64)
+    rec, vis = c2["o"].debug_march(cam, 16, lds_levels=5, hier=False, visits=True)
+    assert np.array_equal(cnt[:, 0], vis.sum(1))
+    assert np.array_equal(cnt[:, 1], rec[..., 0].sum(1))
+
+
 # -------------------------------------------------------------- guide_pdf ----
 def _pdf_compare(o, g, w, torch_dev, pos, N, tol=1e-5):
     (dpos,) = to_dev(torch_dev, pos)
