@@ -271,6 +271,38 @@ wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile)
 wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N, int32_t reps,
                           void *hip_stream, wfpg_tile *best_out, float *best_ms);
 
+/* ---------------------------------------------------------------------
+ * Batched bounces: the per-depth guiding of Alg. 1 for a whole wavefront
+ * (one guide_sample per bounce), captured once into a HIP graph of
+ * persistent kernels that read each bounce's queue length from device memory
+ * at replay time, so lengths may change between replays without
+ * re-instantiation.
+ *  n_bounces in [1, 64]; the arrays below are HOST arrays of n_bounces.
+ *  pos[b]: DEVICE 3 x capacity[b] SoA positions (plane stride capacity[b]).
+ *  n_dev: DEVICE int64[n_bounces], current length of each queue
+ *         (0 <= n_dev[b] <= capacity[b]; read when the graph runs).
+ *  N[b] in {8, 16, 32}; eps as in wfpg_opts.
+ *  dir_out[b] (3 x capacity[b], same stride), pdf_out[b] (capacity[b]):
+ *         DEVICE outputs. Vertex i of bounce b draws its uniforms from
+ *         Philox counter (i, bounce = b) and key seed, exactly as
+ *         guide_sample(..., seed, b, ...) would.
+ * The graph keeps the pointers; the caller keeps every buffer alive (and
+ * the SVO unchanged in structure) until wfpg_graph_destroy. Replays that
+ * overlap on the same graph race; launch them in stream order.
+ * ------------------------------------------------------------------- */
+typedef struct wfpg_bounce_graph wfpg_bounce_graph;
+
+wfpg_status wfpg_graph_create(const wfpg_svo *svo, int32_t n_bounces, const float *const *pos,
+                              const int64_t *capacity, const int64_t *n_dev, const int32_t *N,
+                              uint64_t seed, float eps, float *const *dir_out,
+                              float *const *pdf_out, void *hip_stream, wfpg_bounce_graph **out);
+
+/* Replay the captured bounces on a stream. */
+wfpg_status wfpg_graph_launch(wfpg_bounce_graph *g, void *hip_stream);
+
+/* Free the graph (synchronizes the device). NULL is a no-op. */
+void wfpg_graph_destroy(wfpg_bounce_graph *g);
+
 /* Per-vertex work counts of the march, for measurement: counts (DEVICE
  * n x 2 int32) = {occupancy tests at levels >= 5 summed over the vertex's
  * N*N bins, number of bins that hit}. The same traversal as guide_sample. */

@@ -33,6 +33,7 @@ EXPORTS = [
     "guide_pdf", "guide_sample", "pdf_eval", "svo_stats", "svo_level_size", "svo_export_level",
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
+    "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy",
 ]
 
 
@@ -98,6 +99,10 @@ def lib():
         "wfpg_last_error": (C.c_char_p, []),
         "wfpg_march_counts": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
         "wfpg_get_tile": (i32, [vp, i32, C.POINTER(Tile)]),
+        "wfpg_graph_create": (i32, [vp, i32, vp, vp, vp, vp, u64, C.c_float, vp, vp, vp,
+                                    C.POINTER(vp)]),
+        "wfpg_graph_launch": (i32, [vp, vp]),
+        "wfpg_graph_destroy": (None, [vp]),
         "wfpg_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
         "wfpg_autotune": (i32, [vp, vp, i64, i32, i32, vp, C.POINTER(Tile), C.POINTER(C.c_float)]),
         "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
@@ -303,3 +308,42 @@ def autotune(svo: SVO, pos, N: int, reps: int = 3, stream=None) -> dict:
                                                 reps, _stream(stream), C.byref(t), C.byref(ms)))
     return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
                 blocks_per_cu=t.blocks_per_cu, ms=ms.value)
+
+
+class BounceGraph:
+    """Captured multi-bounce guide_sample (see wfpg_graph_create). Holds
+    references to every tensor it was built with."""
+
+    def __init__(self, svo: SVO, queues, n_dev, Ns, seed: int, eps: float = 0.01, stream=None):
+        import torch
+        self.svo = svo
+        self.queues = [q.contiguous() for q in queues]
+        self.n_dev = n_dev
+        B = len(self.queues)
+        cap = [q.shape[1] for q in self.queues]
+        self.dirs = [torch.empty((3, c), device=q.device) for c, q in zip(cap, self.queues)]
+        self.pdfs = [torch.empty((c,), device=q.device) for c, q in zip(cap, self.queues)]
+        P = C.c_void_p * B
+        self._pos = P(*[q.data_ptr() for q in self.queues])
+        self._dir = P(*[t.data_ptr() for t in self.dirs])
+        self._pdf = P(*[t.data_ptr() for t in self.pdfs])
+        self._cap = (C.c_int64 * B)(*cap)
+        self._N = (C.c_int32 * B)(*Ns)
+        if n_dev.dtype != torch.int64 or not n_dev.is_cuda or n_dev.numel() != B:
+            raise ValueError("n_dev must be a device int64 tensor with one entry per bounce")
+        h = C.c_void_p()
+        _check("wfpg_graph_create", lib().wfpg_graph_create(
+            svo.handle, B, self._pos, self._cap, C.c_void_p(n_dev.data_ptr()), self._N, seed, eps,
+            self._dir, self._pdf, _stream(stream), C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check("wfpg_graph_launch", lib().wfpg_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.wfpg_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()

@@ -140,7 +140,7 @@ void free_svo(wfpg_svo *s)
 {
     if (!s) return;
     void *ptrs[] = {s->d_bits, s->d_rank, s->d_keys, s->d_nrm, s->d_e32, s->d_e16,
-                    s->d_sum, s->d_cnt, s->d_dropped, s->d_err};
+                    s->d_sum, s->d_cnt, s->d_dropped, s->d_err, s->d_ctr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -215,6 +215,7 @@ wfpg_status svo_build(const wfpg_rect *rects, int64_t n_rects, int32_t depth, in
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_rank, svo->total_words * sizeof(uint32_t)));
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_dropped, 2 * sizeof(unsigned long long)));
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_err, sizeof(int32_t)));
+    if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_ctr, kCounterPool * sizeof(unsigned long long)));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_bits, 0, svo->total_words * sizeof(uint64_t), s));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_dropped, 0, 2 * sizeof(unsigned long long), s));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_err, 0, sizeof(int32_t), s));

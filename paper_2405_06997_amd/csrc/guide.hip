@@ -101,220 +101,335 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 }
 
 constexpr uint32_t kMissRec = 0xffffffffu;
+constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
+
+// Per-vertex finalization (wave-wide): footprint level, node, side and value
+// of every bin from the hit records in `rec`, then the row / marginal CDFs
+// and the mode's output for vertex i. Returns the number of hit bins of this
+// lane (for the count mode).
+template <int N, int MODE>
+__device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, const float *ldir,
+                                         const uint32_t *rec, int64_t i, int64_t ps, int lane,
+                                         int vis_lane)
+{
+    constexpr int NN = N * N;
+    constexpr int BPL = NN / 64;
+    constexpr int G = 64 / N;
+    const int D = sv.depth;
+    const int fmt = sv.fmt;
+    float L[BPL];
+    int hit_sum = 0;
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const int b = j * 64 + lane;
+        const uint32_t r = rec[2 * b];
+        float val = fmt == WFPG_FP32 ? a.eps : round16(a.eps, fmt);
+        if (r != kMissRec) {
+            const int axis = (int)(r >> 30);
+            const uint32_t key = r & 0x3fffffffu;
+            const float dx = ldir[3 * b], dy = ldir[3 * b + 1], dz = ldir[3 * b + 2];
+            const float dsel = axis == 0 ? dx : (axis == 1 ? dy : dz);
+            const int k = core::footprint_levels(rec[2 * b + 1], fabsf(dsel), D, a.omega);
+            const int lf = D - k;
+            const uint32_t node = key >> (3 * k);
+            const uint32_t wi = woff(lf) + (node >> 6);
+            const uint64_t w = sv.bits[wi];
+            const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
+            const int64_t g = (int64_t)sv.rank[wi] + __popcll(msk);
+            const float4 Nn = sv.nrm[g];
+            const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
+            if (fmt == WFPG_FP32) {
+                const float2 e = sv.e32[g];
+                val = (side ? e.y : e.x) + a.eps;
+            } else {
+                val = round16(unpack16(sv.e16[g], side, fmt) + a.eps, fmt);
+            }
+            ++hit_sum;
+            if constexpr (MODE == MODE_DEBUG) {
+                int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
+                o[0] = 1; o[1] = axis; o[2] = (int32_t)key; o[3] = (int32_t)rec[2 * b + 1];
+                o[4] = k; o[5] = (int32_t)node; o[6] = (int32_t)(g - sv.noff[lf]); o[7] = side;
+            }
+        } else if constexpr (MODE == MODE_DEBUG) {
+            int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
+            o[0] = 0; o[1] = -1; o[2] = -1; o[3] = -1; o[4] = -1; o[5] = -1; o[6] = -1; o[7] = 0;
+        }
+        L[j] = val;
+    }
+    if constexpr (MODE == MODE_DEBUG) return;
+    if constexpr (MODE == MODE_COUNT) {
+        int vt = vis_lane;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            vt += __shfl_xor(vt, d);
+            hit_sum += __shfl_xor(hit_sum, d);
+        }
+        if (lane == 0) {
+            a.dbg_out[2 * i] = vt;
+            a.dbg_out[2 * i + 1] = hit_sum;
+        }
+        return;
+    }
+    // row CDFs (segmented inclusive scans), marginal CDF over the row sums
+    float S[BPL];
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) S[j] = seg_scan<N>(L[j], lane);
+    float rs = 0.f;
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const float t = __shfl(S[j], (lane % G) * N + N - 1);
+        if (lane / G == j) rs = t;
+    }
+    if (lane >= N) rs = 0.f;
+    const float M = seg_scan<N>(rs, lane);
+    const float total = __shfl(M, N - 1);
+
+    if constexpr (MODE == MODE_PDF) {
+#pragma unroll
+        for (int j = 0; j < BPL; ++j)
+            a.pdf_out[(size_t)i * NN + j * 64 + lane] = (L[j] / total) * a.pdf_scale;
+    } else if constexpr (MODE == MODE_SAMPLE) {
+        uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
+        philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
+        const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
+        const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
+        const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
+        const float tv = u1 * total;
+        const uint64_t bv = __ballot(lane < N && tv < M);
+        const int v = bv ? (__ffsll((unsigned long long)bv) - 1) : N - 1;
+        const int jv = v / G, gv = v % G;
+        float Sj = S[0], Lj = L[0];
+#pragma unroll
+        for (int j = 1; j < BPL; ++j)
+            if (j == jv) { Sj = S[j]; Lj = L[j]; }
+        const float rowsum = __shfl(Sj, gv * N + N - 1);
+        const float tu = u2 * rowsum;
+        const bool in_row = (lane / N) == gv;
+        const uint64_t bu = __ballot(in_row && tu < Sj);
+        const int u = bu ? (__ffsll((unsigned long long)bu) - 1 - gv * N) : N - 1;
+        const float Lb = __shfl(Lj, gv * N + u);
+        if (lane == 0) {
+            const float inv = 1.f / (float)N;
+            float ox, oy, oz;
+            oct_decode((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
+            a.dir_out[i] = ox;
+            a.dir_out[ps + i] = oy;
+            a.dir_out[2 * ps + i] = oz;
+            a.pdf_out[i] = (Lb / total) * a.pdf_scale;
+        }
+    } else if constexpr (MODE == MODE_EVAL) {
+        float ex, ey;
+        oct_encode(a.dir_in[i], a.dir_in[ps + i], a.dir_in[2 * ps + i], ex, ey);
+        const int u = min(max((int)floorf(ex * (float)N), 0), N - 1);
+        const int v = min(max((int)floorf(ey * (float)N), 0), N - 1);
+        const int jv = v / G, gv = v % G;
+        float Lj = L[0];
+#pragma unroll
+        for (int j = 1; j < BPL; ++j)
+            if (j == jv) Lj = L[j];
+        const float Lb = __shfl(Lj, gv * N + u);
+        if (lane == 0) a.pdf_out[i] = (Lb / total) * a.pdf_scale;
+    }
+}
+
+// Wave-uniform values, marked so for the compiler (kept in scalar registers).
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)(uint64_t)v, src);
+    const uint32_t hi = __shfl((uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // LDS layout of a block: [top-level bitmap words][N*N*3 bin directions]
-// [per wave: N*N hit records {key | axis << 30, delta}].
+// [N*N*3 quantized directions |q| | sign << 31][per wave: 2 vertex slots x
+// N*N hit records {key | axis << 30, delta}].
+//
+// A wave keeps two query vertices in flight. Idle lanes take the next
+// unmarched bin of the vertex being fed; when it has no bins left a free
+// slot is opened for the next vertex of the queue (taken from a device
+// counter, kChunk at a time), so lanes never wait for another vertex's
+// longest ray. A slot whose bins are all finished is finalized by the whole
+// wave (values, CDF, sample) and freed.
 template <int N, int MODE>
 __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds_levels)
 {
     constexpr int NN = N * N;
-    constexpr int BPL = NN / 64;  // bins per lane in the value pass
-    constexpr int G = 64 / N;     // rows per 64-bin pass
     extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int W = blockDim.x >> 6;
     const int D = sv.depth;
-    const int fmt = sv.fmt;
     const uint32_t nlw = woff(lds_levels);
     uint64_t *lbits = smem;
     float *ldir = reinterpret_cast<float *>(smem + nlw);
-    uint32_t *lrec = reinterpret_cast<uint32_t *>(ldir + 3 * NN) + (size_t)wave * 2 * NN;
+    uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
+    uint32_t *rec0 = lq + 3 * NN + (size_t)wave * 4 * NN;
+    uint32_t *rec1 = rec0 + 2 * NN;
     for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
-    for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) ldir[t] = a.dirtab[t];
+    for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) {
+        const float d = a.dirtab[t];
+        ldir[t] = d;
+        const int q = core::quantize_dir(d);
+        lq[t] = (uint32_t)(q < 0 ? -q : q) | (q < 0 ? 0x80000000u : 0u);
+    }
     __syncthreads();
 
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
+    const int64_t ps = a.stride ? a.stride : n;   // SoA plane stride
     const uint64_t *gbits = sv.bits;
     auto bits = [gbits, lbits, lds_levels](int lvl, uint32_t wi) -> uint64_t {
         return lvl < lds_levels ? lbits[wi] : gbits[wi];
     };
 
-    for (int64_t i = (int64_t)blockIdx.x * W + wave; i < n; i += (int64_t)gridDim.x * W) {
-        uint32_t O[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(a.pos[k * n + i]);
+    // wave-uniform stream and slot state
+    int64_t chunk_next = 0;
+    int chunk_left = 0;
+    bool exhausted = false;
+    int64_t v0 = -1, v1 = -1;            // vertex of each slot (-1: free)
+    uint32_t A0 = 0, A1 = 0, A2 = 0;     // origin of slot 0
+    uint32_t B0 = 0, B1 = 0, B2 = 0;     // origin of slot 1
+    uint32_t ok0 = 0, ok1 = 0;           // origin leaf keys
+    bool occ0 = false, occ1 = false;
+    int nxt0 = NN, nxt1 = NN;            // next bin to hand out
+    int rem0 = 0, rem1 = 0;              // bins not yet finished
+    int feed = -1;
+    // per-lane march state
+    int lslot = 0, lbin = -1, vis = 0, iters = 0;
+    int vis0 = 0, vis1 = 0;              // count mode: node tests per slot
+    core::MarchState st;
 
-        // ---- march every bin; lanes that finish take the next unmarched bin
-        int bin = lane;          // N*N >= 64
-        int next = 64;
-        int vis = 0, vis_tot = 0, iters = 0;
-        core::MarchState st;
-        core::march_begin(st, O, core::quantize_dir(ldir[3 * bin]), core::quantize_dir(ldir[3 * bin + 1]),
-                          core::quantize_dir(ldir[3 * bin + 2]), D);
-        while (true) {
-            const bool act = bin >= 0;
-            if (__ballot(act) == 0ull) break;
-            int res = core::STEP_CONTINUE;
-            Hit h = {-1, 0u, 0u};
-            if (act) {
-                res = core::march_step(st, D, bits, 5, vis, h);
-                if (res == core::STEP_CONTINUE && ++iters >= core::kMaxIt) {
-                    atomicOr(a.err, 1);
-                    res = core::STEP_MISS;
-                }
-            }
-            const bool fin = act && res != core::STEP_CONTINUE;
-            if (fin) {
-                lrec[2 * bin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
-                lrec[2 * bin + 1] = h.delta;
-                if constexpr (MODE == MODE_DEBUG) {
-                    if (a.dbg_visits) a.dbg_visits[(size_t)i * NN + bin] = vis;
-                }
-                vis_tot += vis;
-            }
-            const uint64_t fm = __ballot(fin);
-            if (fm) {
-                if (fin) {
-                    const int nb = next + lanes_below(fm);
-                    bin = nb < NN ? nb : -1;
-                    if (bin >= 0) {
-                        core::march_begin(st, O, core::quantize_dir(ldir[3 * bin]),
-                                          core::quantize_dir(ldir[3 * bin + 1]),
-                                          core::quantize_dir(ldir[3 * bin + 2]), D);
-                        vis = 0;
-                        iters = 0;
-                    }
-                }
-                next += __popcll(fm);
-            }
+    while (true) {
+        if (v0 >= 0 && rem0 == 0) {
+            wave_lds_fence();
+            finalize<N, MODE>(sv, a, ldir, rec0, v0, ps, lane, vis0);
+            wave_lds_fence();
+            v0 = -1;
+            vis0 = 0;
         }
-        wave_lds_fence();
-
-        // ---- field values: footprint level, node, side, exitance + eps
-        float L[BPL];
-        int hit_sum = 0;
+        if (v1 >= 0 && rem1 == 0) {
+            wave_lds_fence();
+            finalize<N, MODE>(sv, a, ldir, rec1, v1, ps, lane, vis1);
+            wave_lds_fence();
+            v1 = -1;
+            vis1 = 0;
+        }
+        // hand out bins to idle lanes
+        uint64_t idle = __ballot(lbin < 0);
+        while (idle) {
+            const bool feed_ok = (feed == 0 && v0 >= 0 && nxt0 < NN) || (feed == 1 && v1 >= 0 && nxt1 < NN);
+            if (!feed_ok) {
+                const int f = v0 < 0 ? 0 : (v1 < 0 ? 1 : -1);
+                if (f < 0 || exhausted) break;
+                if (chunk_left == 0) {
+                    int64_t b = 0;
+                    if (lane == 0) b = (int64_t)atomicAdd(a.queue_ctr, (unsigned long long)kChunk);
+                    b = uni(shfl64(b, 0));
+                    if (b >= n) { exhausted = true; break; }
+                    chunk_next = b;
+                    chunk_left = uni((int)min((int64_t)kChunk, n - b));
+                }
+                const int64_t vi = chunk_next++;
+                --chunk_left;
+                uint32_t O[3];
 #pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-            const int b = j * 64 + lane;
-            const uint32_t rec = lrec[2 * b];
-            float val = fmt == WFPG_FP32 ? a.eps : round16(a.eps, fmt);
-            int k = -1, side = 0;
-            uint32_t node = 0;
-            int64_t nidx = -1;
-            if (rec != kMissRec) {
-                const int axis = (int)(rec >> 30);
-                const uint32_t key = rec & 0x3fffffffu;
-                const float dx = ldir[3 * b], dy = ldir[3 * b + 1], dz = ldir[3 * b + 2];
-                const float dsel = axis == 0 ? dx : (axis == 1 ? dy : dz);
-                k = core::footprint_levels(lrec[2 * b + 1], fabsf(dsel), D, a.omega);
-                const int lf = D - k;
-                node = key >> (3 * k);
-                const uint32_t wi = woff(lf) + (node >> 6);
-                const uint64_t w = sv.bits[wi];
-                const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
-                const int64_t g = (int64_t)sv.rank[wi] + __popcll(msk);
-                nidx = g - sv.noff[lf];
-                const float4 Nn = sv.nrm[g];
-                side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
-                if (fmt == WFPG_FP32) {
-                    const float2 e = sv.e32[g];
-                    val = (side ? e.y : e.x) + a.eps;
+                for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(a.pos[k * ps + vi]);
+                const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D),
+                                                    O[2] >> (WFPG_FINE - D));
+                const bool oc = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
+                if (f == 0) {
+                    v0 = uni(vi); A0 = uni(O[0]); A1 = uni(O[1]); A2 = uni(O[2]); ok0 = uni(okey);
+                    occ0 = uni((int)oc) != 0; nxt0 = 0; rem0 = NN;
                 } else {
-                    val = round16(unpack16(sv.e16[g], side, fmt) + a.eps, fmt);
+                    v1 = uni(vi); B0 = uni(O[0]); B1 = uni(O[1]); B2 = uni(O[2]); ok1 = uni(okey);
+                    occ1 = uni((int)oc) != 0; nxt1 = 0; rem1 = NN;
                 }
-                ++hit_sum;
-                if constexpr (MODE == MODE_DEBUG) {
-                    int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
-                    o[0] = 1; o[1] = axis; o[2] = (int32_t)key; o[3] = (int32_t)lrec[2 * b + 1];
-                    o[4] = k; o[5] = (int32_t)node; o[6] = (int32_t)nidx; o[7] = side;
-                }
-            } else if constexpr (MODE == MODE_DEBUG) {
-                int32_t *o = a.dbg_out + ((size_t)i * NN + b) * 8;
-                o[0] = 0; o[1] = -1; o[2] = -1; o[3] = -1; o[4] = -1; o[5] = -1; o[6] = -1; o[7] = 0;
+                feed = f;
             }
-            L[j] = val;
+            const int base = feed == 0 ? nxt0 : nxt1;
+            const int take = min(__popcll(idle), NN - base);
+            const int r = lanes_below(idle);
+            const bool mine = ((idle >> lane) & 1ull) && r < take;
+            if (mine) {
+                lslot = feed;
+                lbin = base + r;
+                const uint32_t O[3] = {feed ? B0 : A0, feed ? B1 : A1, feed ? B2 : A2};
+                const uint32_t w0 = lq[3 * lbin], w1 = lq[3 * lbin + 1], w2 = lq[3 * lbin + 2];
+                const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
+                vis = 0;
+                iters = 0;
+                core::march_begin(st, O, feed ? ok1 : ok0, feed ? occ1 : occ0, a0, a1, a2,
+                                  a0 ? ((w0 >> 31) ? -1 : 1) : 0, a1 ? ((w1 >> 31) ? -1 : 1) : 0,
+                                  a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, bits, 5, vis);
+            }
+            idle &= ~__ballot(mine);
+            if (feed == 0) nxt0 = uni(nxt0 + take); else nxt1 = uni(nxt1 + take);
         }
-        wave_lds_fence();
-        if constexpr (MODE == MODE_DEBUG) continue;
-        if constexpr (MODE == MODE_COUNT) {
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                vis_tot += __shfl_xor(vis_tot, d);
-                hit_sum += __shfl_xor(hit_sum, d);
-            }
-            if (lane == 0) {
-                a.dbg_out[2 * i] = vis_tot;
-                a.dbg_out[2 * i + 1] = hit_sum;
+        if (__ballot(lbin >= 0) == 0ull) {
+            if (v0 < 0 && v1 < 0) break;
+            if (!(v0 >= 0 && rem0 == 0) && !(v1 >= 0 && rem1 == 0)) {
+                atomicOr(a.err, 2);   // no progress possible (never expected)
+                break;
             }
             continue;
         }
-
-        // ---- row CDFs (segmented inclusive scans), marginal CDF over row sums
-        float S[BPL];
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) S[j] = seg_scan<N>(L[j], lane);
-        float rs = 0.f;
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-            const float t = __shfl(S[j], (lane % G) * N + N - 1);
-            if (lane / G == j) rs = t;
-        }
-        if (lane >= N) rs = 0.f;
-        const float M = seg_scan<N>(rs, lane);
-        const float total = __shfl(M, N - 1);
-
-        if constexpr (MODE == MODE_PDF) {
-#pragma unroll
-            for (int j = 0; j < BPL; ++j)
-                a.pdf_out[(size_t)i * NN + j * 64 + lane] = (L[j] / total) * a.pdf_scale;
-        } else if constexpr (MODE == MODE_SAMPLE) {
-            uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
-            philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-            const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
-            const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
-            const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
-            const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
-            const float tv = u1 * total;
-            const uint64_t bv = __ballot(lane < N && tv < M);
-            const int v = bv ? (__ffsll((unsigned long long)bv) - 1) : N - 1;
-            const int jv = v / G, gv = v % G;
-            float Sj = S[0], Lj = L[0];
-#pragma unroll
-            for (int j = 1; j < BPL; ++j)
-                if (j == jv) { Sj = S[j]; Lj = L[j]; }
-            const float rowsum = __shfl(Sj, gv * N + N - 1);
-            const float tu = u2 * rowsum;
-            const bool in_row = (lane / N) == gv;
-            const uint64_t bu = __ballot(in_row && tu < Sj);
-            const int u = bu ? (__ffsll((unsigned long long)bu) - 1 - gv * N) : N - 1;
-            const float Lb = __shfl(Lj, gv * N + u);
-            if (lane == 0) {
-                const float inv = 1.f / (float)N;
-                float ox, oy, oz;
-                oct_decode((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
-                a.dir_out[i] = ox;
-                a.dir_out[n + i] = oy;
-                a.dir_out[2 * n + i] = oz;
-                a.pdf_out[i] = (Lb / total) * a.pdf_scale;
+        int res = core::STEP_CONTINUE;
+        Hit h = {-1, 0u, 0u};
+        if (lbin >= 0) {
+            res = core::march_step(st, D, bits, 5, vis, h);
+            if (res == core::STEP_CONTINUE && ++iters >= core::kMaxIt) {
+                atomicOr(a.err, 1);
+                res = core::STEP_MISS;
             }
-        } else if constexpr (MODE == MODE_EVAL) {
-            float ex, ey;
-            oct_encode(a.dir_in[i], a.dir_in[n + i], a.dir_in[2 * n + i], ex, ey);
-            const int u = min(max((int)floorf(ex * (float)N), 0), N - 1);
-            const int v = min(max((int)floorf(ey * (float)N), 0), N - 1);
-            const int jv = v / G, gv = v % G;
-            float Lj = L[0];
-#pragma unroll
-            for (int j = 1; j < BPL; ++j)
-                if (j == jv) Lj = L[j];
-            const float Lb = __shfl(Lj, gv * N + u);
-            if (lane == 0) a.pdf_out[i] = (Lb / total) * a.pdf_scale;
+        }
+        const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
+        if (fin) {
+            uint32_t *rec = lslot ? rec1 : rec0;
+            rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
+            rec[2 * lbin + 1] = h.delta;
+            if constexpr (MODE == MODE_DEBUG) {
+                if (a.dbg_visits) a.dbg_visits[(size_t)(lslot ? v1 : v0) * NN + lbin] = vis;
+            }
+            if (lslot) vis1 += vis; else vis0 += vis;
+            lbin = -1;
+        }
+        const uint64_t fm = __ballot(fin);
+        if (fm) {
+            const uint64_t f1 = __ballot(fin && lslot == 1);
+            rem0 = uni(rem0 - __popcll(fm & ~f1));
+            rem1 = uni(rem1 - __popcll(f1));
         }
     }
 }
 
+__global__ void k_reset_counter(unsigned long long *ctr)
+{
+    *ctr = 0ull;
+}
+
 template <int N>
-hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a, const TileConfig &tc,
+hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const TileConfig &tc,
                     hipStream_t s)
 {
+    GuideArgs a = a0;
+    if (!a.queue_ctr)
+        a.queue_ctr = svo->d_ctr + (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
     const int W = tc.waves_per_block;
-    const int64_t want = a.n_dev ? INT64_MAX : (a.n + W - 1) / W;
+    const int64_t want = a.n_dev ? INT64_MAX : ((a.n + kChunk - 1) / kChunk + W - 1) / W;
     const int64_t cap = (int64_t)device_cu_count() * tc.blocks_per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
     const size_t lds = guide_lds_bytes(N, tc);
     const dim3 blk(64 * W);
     const wfpg::SvoView v = svo->view();
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.queue_ctr);
     switch (mode) {
     case MODE_SAMPLE: hipLaunchKernelGGL((k_guide<N, MODE_SAMPLE>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     case MODE_PDF: hipLaunchKernelGGL((k_guide<N, MODE_PDF>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;

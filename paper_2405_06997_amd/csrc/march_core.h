@@ -75,35 +75,19 @@ struct Hit {
     uint32_t delta;    // |B - O| of that crossing, 2^-30 units
 };
 
-// Resumable march state: the ray, the current cell (level, key, lower
-// corner), the last crossing (parameter tn/td on axis ta; ta = -1 at the
-// start) and the cell entered by that crossing (tlvl, tkey) while its
-// ancestors are retested. Plain scalars only, so that the state lives in
-// registers.
+// Resumable march state. Between steps the state is always an EMPTY cell
+// (or the origin's leaf) that the ray is inside of just after the crossing
+// (tn/td on axis ta; ta = -1 and tn = 0 at the start): level, key and lower
+// corner. Plain scalars only, so that the state lives in registers.
 struct MarchState {
     uint32_t O0, O1, O2;      // origin, 2^-30 units
     uint32_t aq0, aq1, aq2;   // |q|
     int sg0, sg1, sg2;        // sign(q)
     uint32_t origin_key;
-    int lvl, tlvl, ta;
-    uint32_t key, tkey, tn, td;
+    int lvl, ta;
+    uint32_t key, tn, td;
     uint32_t lo0, lo1, lo2;
 };
-
-WFPG_HD void march_begin(MarchState &s, const uint32_t O[3], int q0, int q1, int q2, int D)
-{
-    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
-    s.aq0 = (uint32_t)(q0 < 0 ? -q0 : q0);
-    s.aq1 = (uint32_t)(q1 < 0 ? -q1 : q1);
-    s.aq2 = (uint32_t)(q2 < 0 ? -q2 : q2);
-    s.sg0 = (q0 > 0) - (q0 < 0);
-    s.sg1 = (q1 > 0) - (q1 < 0);
-    s.sg2 = (q2 > 0) - (q2 < 0);
-    s.origin_key = morton3(O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D));
-    s.lvl = 0; s.tlvl = 0; s.ta = -1;
-    s.key = 0; s.tkey = 0; s.tn = 0; s.td = 1;
-    s.lo0 = 0; s.lo1 = 0; s.lo2 = 0;
-}
 
 enum { STEP_CONTINUE = 0, STEP_HIT = 1, STEP_MISS = 2 };
 
@@ -128,40 +112,99 @@ WFPG_HD uint32_t far_face(uint32_t lo, uint32_t size, uint32_t O, int sg)
     return sg > 0 ? lo + size - O : (sg < 0 ? O - lo : 1u);
 }
 
-// One occupancy test followed by a descent or an exit step.
-// Bits(level, word_index) -> uint64 occupancy word.
+// Settle on the cell the ray is in after a crossing: the target cell
+// (tlvl, tkey, corner t0..t2) has known ancestors; test them top-down from
+// level `from` (all levels above are known occupied) to the first empty one.
+// If the whole path is occupied, descend below the target by mid-plane
+// comparisons until an empty cell or an occupied leaf (a hit). Every
+// occupancy test at a level >= count_from adds one to vis.
 template <class Bits>
-WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
+WFPG_HD int settle(MarchState &s, int D, int from, int tlvl, uint32_t tkey, uint32_t t0, uint32_t t1,
+                   uint32_t t2, const Bits &bits, int count_from, int &vis, Hit &h)
 {
-    const uint64_t w = bits(s.lvl, woff(s.lvl) + (s.key >> 6));
-    vis += (s.lvl >= count_from);
-    if ((w >> (s.key & 63)) & 1ull) {
-        if (s.lvl == D) {
-            if (s.key != s.origin_key) {
-                h.axis = s.ta;
-                h.key = s.key;
-                h.delta = s.tn;
-                return STEP_HIT;
-            }
-        } else {
-            const uint32_t half = 1u << (29 - s.lvl);
-            uint32_t oct;
-            if (s.lvl < s.tlvl) {
-                oct = (s.tkey >> (3 * (s.tlvl - s.lvl - 1))) & 7u;
-            } else {
-                oct = upper_half(s.lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
-                      (upper_half(s.lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
-                      (upper_half(s.lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
-            }
-            s.key = (s.key << 3) | oct;
-            s.lo0 += (oct & 1u) ? half : 0u;
-            s.lo1 += (oct & 2u) ? half : 0u;
-            s.lo2 += (oct & 4u) ? half : 0u;
-            ++s.lvl;
+    for (int l = from; l <= tlvl; ++l) {
+        const uint32_t k = tkey >> (3 * (tlvl - l));
+        const uint64_t w = bits(l, woff(l) + (k >> 6));
+        vis += (l >= count_from);
+        if (!((w >> (k & 63)) & 1ull)) {
+            const uint32_t mk = ~((1u << (kFine - l)) - 1u);
+            s.lvl = l;
+            s.key = k;
+            s.lo0 = t0 & mk;
+            s.lo1 = t1 & mk;
+            s.lo2 = t2 & mk;
             return STEP_CONTINUE;
         }
     }
-    // leave the current cell (empty, or the origin's leaf)
+    int lvl = tlvl;
+    uint32_t key = tkey, lo0 = t0, lo1 = t1, lo2 = t2;
+    while (lvl < D) {
+        const uint32_t half = 1u << (29 - lvl);
+        const uint32_t oct = upper_half(lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
+                             (upper_half(lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
+                             (upper_half(lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
+        key = (key << 3) | oct;
+        lo0 += (oct & 1u) ? half : 0u;
+        lo1 += (oct & 2u) ? half : 0u;
+        lo2 += (oct & 4u) ? half : 0u;
+        ++lvl;
+        const uint64_t w = bits(lvl, woff(lvl) + (key >> 6));
+        vis += (lvl >= count_from);
+        if (!((w >> (key & 63)) & 1ull)) {
+            s.lvl = lvl;
+            s.key = key;
+            s.lo0 = lo0;
+            s.lo1 = lo1;
+            s.lo2 = lo2;
+            return STEP_CONTINUE;
+        }
+    }
+    h.axis = s.ta;
+    h.key = key;
+    h.delta = s.tn;
+    return STEP_HIT;
+}
+
+// Start a march at the cell holding the origin. When the origin's leaf is
+// occupied all its ancestors are too, so the walk starts at that leaf (which
+// is never a hit): the top-down descent from the root would test exactly
+// those ancestors, and their tests at levels >= count_from are counted.
+// Otherwise the origin's ancestors are tested from the root down to the
+// first empty one. The result and the counts equal those of the plain
+// top-down walk from the root.
+template <class Bits>
+WFPG_HD void march_begin(MarchState &s, const uint32_t O[3], uint32_t origin_key, bool origin_occupied,
+                         uint32_t aq0, uint32_t aq1, uint32_t aq2, int sg0, int sg1, int sg2, int D,
+                         const Bits &bits, int count_from, int &vis)
+{
+    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
+    s.aq0 = aq0; s.aq1 = aq1; s.aq2 = aq2;
+    s.sg0 = sg0; s.sg1 = sg1; s.sg2 = sg2;
+    s.origin_key = origin_key;
+    s.ta = -1; s.tn = 0; s.td = 1;
+    const uint32_t mk = ~((1u << (kFine - D)) - 1u);
+    if (origin_occupied) {
+        s.lvl = D;
+        s.key = origin_key;
+        s.lo0 = O[0] & mk; s.lo1 = O[1] & mk; s.lo2 = O[2] & mk;
+        vis += D + 1 - (count_from < D ? count_from : D);   // levels count_from..D
+    } else {
+        Hit h;
+        settle(s, D, 0, D, origin_key, O[0] & mk, O[1] & mk, O[2] & mk, bits, count_from, vis, h);
+    }
+}
+
+WFPG_HD void split_dir(int q, uint32_t &aq, int &sg)
+{
+    aq = (uint32_t)(q < 0 ? -q : q);
+    sg = (q > 0) - (q < 0);
+}
+
+// One step: leave the current cell through its first exit crossing (ties:
+// lowest axis), then settle on the cell holding the ray after it.
+template <class Bits>
+WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
+{
     const uint32_t size = 1u << (kFine - s.lvl);
     const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
     const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
@@ -182,25 +225,17 @@ WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, i
     if (nl < 0 || nl >= (1ll << kFine)) return STEP_MISS;
     const uint32_t nlu = (uint32_t)nl;
     const uint32_t oldc = le >> (kFine - s.lvl), newc = nlu >> (kFine - s.lvl);
-    s.lo0 = (nlu & m0) | (s.lo0 & ~m0);
-    s.lo1 = (nlu & m1) | (s.lo1 & ~m1);
-    s.lo2 = (nlu & m2) | (s.lo2 & ~m2);
+    const uint32_t t0 = (nlu & m0) | (s.lo0 & ~m0);
+    const uint32_t t1 = (nlu & m1) | (s.lo1 & ~m1);
+    const uint32_t t2 = (nlu & m2) | (s.lo2 & ~m2);
     const uint32_t m = 0x09249249u << e;
-    s.key = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m))
-                    : ((((s.key & m) - 1u) & m) | (s.key & ~m));
+    const uint32_t tkey = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m))
+                                  : ((((s.key & m) - 1u) & m) | (s.key & ~m));
     s.tn = De;
     s.td = Qe;
     s.ta = e;
-    s.tlvl = s.lvl;
-    s.tkey = s.key;
-    const int p = 31 - __builtin_clz(oldc ^ newc);
-    s.lvl -= p;
-    s.key >>= 3 * p;
-    const uint32_t mk = ~((1u << (kFine - s.lvl)) - 1u);
-    s.lo0 &= mk;
-    s.lo1 &= mk;
-    s.lo2 &= mk;
-    return STEP_CONTINUE;
+    const int p = 31 - __builtin_clz(oldc ^ newc);   // levels above s.lvl - p are shared
+    return settle(s, D, s.lvl - p, s.lvl, tkey, t0, t1, t2, bits, count_from, vis, h);
 }
 
 // Whole march: 1 on a hit, 0 on a miss, -1 if the iteration bound is
@@ -210,7 +245,14 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
                   int count_from, int &vis, Hit &h)
 {
     MarchState s;
-    march_begin(s, O, q0, q1, q2, D);
+    uint32_t aq0, aq1, aq2;
+    int sg0, sg1, sg2;
+    split_dir(q0, aq0, sg0);
+    split_dir(q1, aq1, sg1);
+    split_dir(q2, aq2, sg2);
+    const uint32_t ok = morton3(O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D));
+    const bool occ = (bits(D, woff(D) + (ok >> 6)) >> (ok & 63)) & 1ull;
+    march_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, bits, count_from, vis);
     for (int it = 0; it < kMaxIt; ++it) {
         const int st = march_step(s, D, bits, count_from, vis, h);
         if (st == STEP_HIT) return 1;

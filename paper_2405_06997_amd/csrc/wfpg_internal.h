@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/wfpg.h"
 
 #define WFPG_MAXD 10
@@ -72,6 +74,7 @@ struct GuideArgs {
     const float *dir_in;      // MODE_EVAL
     int64_t n;                // queue length (ignored when n_dev != NULL)
     const int64_t *n_dev;     // optional device-resident queue length
+    int64_t stride;           // distance between SoA planes (0: the queue length)
     float eps;
     float omega;              // fp32(4*pi/N^2)
     float pdf_scale;          // fp32(N^2/(4*pi))
@@ -83,6 +86,7 @@ struct GuideArgs {
     int32_t *dbg_visits;
     const float *dirtab;      // N*N*3 FP32 bin centres
     int32_t *err;             // device error flags
+    unsigned long long *queue_ctr;   // vertex queue counter (reset before each launch)
 };
 
 struct TileConfig {          // launch shape chosen by the autotuner
@@ -98,10 +102,11 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
 // per-wave hit records.
 inline size_t guide_lds_bytes(int N, const TileConfig &tc)
 {
-    return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 +
-           (size_t)tc.waves_per_block * N * N * 2 * 4;
+    return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 * 2 +
+           (size_t)tc.waves_per_block * 2 * N * N * 2 * 4;
 }
 constexpr size_t kMaxGuideLds = 64 * 1024;
+constexpr int kCounterPool = 64;   // concurrent guide launches per SVO with distinct counters
 
 // Tile chosen for (device, N, depth, format): the autotuned one if present.
 TileConfig choose_tile(const struct ::wfpg_svo *svo, int N);
@@ -137,6 +142,8 @@ struct wfpg_svo {
     uint2 *d_cnt = nullptr;
     unsigned long long *d_dropped = nullptr;
     int32_t *d_err = nullptr;
+    unsigned long long *d_ctr = nullptr;   // pool of vertex-queue counters
+    mutable std::atomic<unsigned> ctr_next{0};   // round-robin slot of the pool
     wfpg::SvoView view() const
     {
         wfpg::SvoView v;

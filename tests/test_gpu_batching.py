@@ -1,0 +1,81 @@
+"""Batched bounces in a captured HIP graph, and the launch-shape autotuner.
+
+The graph's kernels read their queue lengths from device memory; every
+replay (with eager work and synchronizations in between) must equal eager
+guide_sample bit for bit, also after the lengths shrink."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_06997_amd as w
+    dev = torch.device("cuda:0")
+    room = synth.room(n_boxes=16)
+    g = w.svo_build(room, 8)
+    sp = [torch.from_numpy(a).to(dev) for a in synth.room_splats(room, 200_000, 5)]
+    w.svo_accumulate(g, *sp)
+    return torch, dev, w, room, g, sp
+
+
+def test_graph_replays_match_eager(env):
+    torch, dev, w, room, g, sp = env
+    sizes = [5000, 3001, 777, 64, 1]
+    Ns = [16, 8, 32, 16, 8]
+    queues = [torch.from_numpy(synth.area_points(room, n, 40 + b)[0]).to(dev)
+              for b, n in enumerate(sizes)]
+    n_dev = torch.tensor(sizes, dtype=torch.int64, device=dev)
+    G = w.BounceGraph(g, queues, n_dev, Ns, seed=99)
+
+    def eager(b, n):
+        return w.guide_sample(g, queues[b][:, :n].contiguous(), w.make_opts(N=Ns[b]), seed=99, bounce=b)
+
+    for rep in range(3):
+        G.launch()
+        torch.cuda.synchronize()
+        for b, n in enumerate(sizes):
+            d, p = eager(b, n)
+            assert torch.equal(G.dirs[b][:, :n], d), (rep, b)
+            assert torch.equal(G.pdfs[b][:n], p), (rep, b)
+        w.svo_accumulate(g, sp[0][:, :0].contiguous(), sp[1][:, :0].contiguous(),
+                         sp[2][:, :0].contiguous())   # eager work between replays
+        torch.cuda.synchronize()
+    # shrink the queues on the device: the same graph handles the new lengths
+    new = [1234, 0, 500, 64, 1]
+    n_dev.copy_(torch.tensor(new, dtype=torch.int64))
+    G.dirs[0].fill_(7.0)
+    G.launch()
+    torch.cuda.synchronize()
+    for b, n in enumerate(new):
+        if n == 0:
+            continue
+        d, p = eager(b, n)
+        assert torch.equal(G.dirs[b][:, :n], d) and torch.equal(G.pdfs[b][:n], p)
+    assert (G.dirs[0][:, new[0]:] == 7.0).all()   # nothing written past the live length
+    assert g.stats()["errors"] == 0
+    G.close()
+
+
+def test_autotune_and_tiles(env):
+    torch, dev, w, room, g, sp = env
+    pos = torch.from_numpy(synth.area_points(room, 20000, 3)[0]).to(dev)
+    ref_d, ref_p = w.guide_sample(g, pos, w.make_opts(N=16), seed=1, bounce=0)
+    best = w.autotune(g, pos, 16, reps=1)
+    assert best["ms"] > 0
+    assert w.get_tile(g, 16)["waves_per_block"] == best["waves_per_block"]
+    # results do not depend on the launch shape
+    for tile in [(1, 5, 2), (8, 6, 16), (2, 7, 4)]:
+        w.set_tile(g, 16, *tile)
+        d, p = w.guide_sample(g, pos, w.make_opts(N=16), seed=1, bounce=0)
+        assert torch.equal(d, ref_d) and torch.equal(p, ref_p)
+    with pytest.raises(w.WfpgError):
+        w.set_tile(g, 16, 0, 5, 2)
+    with pytest.raises(w.WfpgError):
+        w.set_tile(g, 16, 4, 12, 2)
