@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_NN = os.path.join(_HERE, "nn_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 FMT_FP32, FMT_FP16, FMT_BF16 = 0, 1, 2
@@ -32,7 +33,7 @@ def build(force: bool = True) -> str:
         subprocess.check_call([
             "gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
-            _SRC, "-o", tmp, "-lm"])
+            _SRC, _SRC_NN, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -78,6 +79,13 @@ def lib():
             "orc_oct_encode_many": (None, [vp, i64, vp]),
             "orc_oct_decode_many": (None, [vp, i64, vp]),
             "orc_num_threads": (i32, []),
+            "orc_nn_mlp_params": (i64, []),
+            "orc_nn_num_params": (i64, [vp]),
+            "orc_nn_resolutions": (None, [vp, vp]),
+            "orc_nn_forward": (None, [vp, vp, vp, vp, i64, i32, vp, vp]),
+            "orc_nn_grad": (C.c_double, [vp, vp, vp, vp, vp, i64, i32, vp]),
+            "orc_kl_rows": (None, [vp, vp, i64, vp]),
+            "orc_nn_encode_info": (None, [vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -304,3 +312,67 @@ class SVO:
         e = np.zeros(n)
         lib().orc_pdf_eval(self._h, _p(pos), _p(dirs), n, N, eps, _p(pdf), _p(b), _p(e))
         return dict(pdf=pdf, bin=b, edge=e)
+
+
+# ---------------------------------------------------------------- learned --
+class NNCfg(C.Structure):
+    _fields_ = [("log2_table", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32)]
+
+
+NN_LEVELS, NN_FEAT, NN_IN, NN_H, NN_OUT = 16, 2, 35, 64, 256
+
+
+def nn_cfg(log2_table: int = 19, n_min: int = 16, n_max: int = 1024) -> NNCfg:
+    return NNCfg(log2_table, n_min, n_max)
+
+
+def nn_num_params(cfg: NNCfg) -> int:
+    return int(lib().orc_nn_num_params(C.byref(cfg)))
+
+
+def nn_mlp_params() -> int:
+    return int(lib().orc_nn_mlp_params())
+
+
+def nn_resolutions(cfg: NNCfg) -> np.ndarray:
+    out = np.zeros(NN_LEVELS, np.int32)
+    lib().orc_nn_resolutions(C.byref(cfg), _p(out))
+    return out
+
+
+def nn_forward(params, cfg: NNCfg, pos, nrm, mode: int = 0):
+    """(probabilities, logits), each (n, 256) FP64. mode 1 = BF16-faithful."""
+    params = np.ascontiguousarray(params, np.float32)
+    pos, nrm = _soa(pos), _soa(nrm)
+    n = pos.shape[1]
+    prob = np.zeros((n, NN_OUT))
+    logit = np.zeros((n, NN_OUT))
+    lib().orc_nn_forward(_p(params), C.byref(cfg), _p(pos), _p(nrm), n, mode, _p(prob), _p(logit))
+    return prob, logit
+
+
+def nn_grad(params, cfg: NNCfg, pos, nrm, target, mode: int = 0):
+    """(loss, gradient over all parameters) of the mean cross-entropy."""
+    params = np.ascontiguousarray(params, np.float32)
+    pos, nrm = _soa(pos), _soa(nrm)
+    target = np.ascontiguousarray(target, np.float64)
+    g = np.zeros(nn_num_params(cfg))
+    loss = lib().orc_nn_grad(_p(params), C.byref(cfg), _p(pos), _p(nrm), _p(target),
+                             pos.shape[1], mode, _p(g))
+    return float(loss), g
+
+
+def kl_rows(p, q) -> np.ndarray:
+    p = np.ascontiguousarray(p, np.float64)
+    q = np.ascontiguousarray(q, np.float64)
+    out = np.zeros(p.shape[0])
+    lib().orc_kl_rows(_p(p), _p(q), p.shape[0], _p(out))
+    return out
+
+
+def nn_encode_info(cfg: NNCfg, p):
+    p = np.ascontiguousarray(p, np.float32)
+    idx = np.zeros((NN_LEVELS, 8), np.uint32)
+    w = np.zeros((NN_LEVELS, 8))
+    lib().orc_nn_encode_info(C.byref(cfg), _p(p), _p(idx), _p(w))
+    return idx, w
