@@ -813,7 +813,7 @@ void orc_debug_march(const orc_svo *s, const float *pos, int64_t n, int32_t N,
  * a miss gives eps. With 16-bit storage (fmt 1/2) the stored E is already
  * rounded and L_b is rounded once more to the 16-bit format, as the GPU
  * stores its bins. L (FP64 of the FP32/16-bit field) and Lt (FP64 truth:
- * unrounded FP64 exitance + 0.01) may be NULL. */
+ * unrounded FP64 exitance + eps) may be NULL. */
 static void field_one(const orc_svo *s, const float *p, int N, float eps, const float *tab,
                       double *L, double *Lt)
 {
@@ -825,7 +825,7 @@ static void field_one(const orc_svo *s, const float *p, int N, float eps, const 
         if (s->fmt == 0) v = (double)e + (double)eps;
         else v = (double)orc_round_fmt(bo.hit ? e + eps : eps, s->fmt);
         if (L) L[b] = v;
-        if (Lt) Lt[b] = (bo.hit ? bo.truth : 0.0) + 0.01;
+        if (Lt) Lt[b] = (bo.hit ? bo.truth : 0.0) + (double)eps;
     }
 }
 
