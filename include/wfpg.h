@@ -27,9 +27,11 @@
  *    centre = +z. Bin (u, v) covers x in [u/N, (u+1)/N), y in [v/N, (v+1)/N);
  *    rows are v and the flat bin index is b = v*N + u.
  *  - Returned pdfs are solid-angle densities in 1/sr (Eq. 2).
- *  - Concurrency: guide_pdf, guide_sample, pdf_eval and wfpg_debug_march only
- *    read the SVO and may run concurrently; svo_accumulate mutates it and must
- *    be ordered by the caller (stream order).
+ *  - Concurrency: guide_pdf, guide_sample (mode 0), pdf_eval and
+ *    wfpg_debug_march only read the SVO and may run concurrently;
+ *    svo_accumulate mutates it, and guide_train, the wfpg_nn_* calls and
+ *    guide_sample in mode 1 use the model's working buffers: the caller
+ *    orders those (stream order).
  */
 #ifndef WFPG_H
 #define WFPG_H
@@ -308,6 +310,84 @@ void wfpg_graph_destroy(wfpg_bounce_graph *g);
  * N*N bins, number of bins that hit}. The same traversal as guide_sample. */
 wfpg_status wfpg_march_counts(const wfpg_svo *svo, const float *pos, int64_t n,
                               const wfpg_opts *opts, int32_t *counts, void *hip_stream);
+
+/* ---------------------------------------------------------------------
+ * Learned stand-in for the march (guide_sample with opts->mode == 1).
+ *
+ * A multiresolution hash-grid encoding of the position (16 levels, 2^log2_table
+ * entries of 2 features per level; level l has resolution
+ * floor(n_min * b^l), b chosen so level 15 reaches n_max; a level whose
+ * (R+1)^3 corner grid fits the table is indexed densely, otherwise by the
+ * spatial hash x*1 ^ y*2654435761 ^ z*805459861 mod 2^log2_table; trilinear
+ * interpolation) is concatenated with the surface normal (3 values) and fed to
+ * a ReLU MLP 35 -> 64 -> 64 -> 64 -> 64 -> 256 whose softmax over the 256
+ * logits is a 16 x 16 bin distribution on the same octahedral field the march
+ * uses (Sec. 3.3). Table, inputs, weights and activations are BF16, products
+ * accumulate in FP32 (MFMA); master parameters and Adam moments are FP32.
+ * It is trained on pdfs the march itself produces (guide_pdf at N = 16 with
+ * eps = 0.01) by minimising the mean cross-entropy -sum_b t_b log q_b.
+ *
+ * Parameter vector order (FP32): W0[64][35], b0[64], W1[64][64], b1, W2, b2,
+ * W3, b3, W4[256][64], b4[256], then the table [16][2^log2_table][2]
+ * (31424 MLP parameters + 32 * 2^log2_table table entries).
+ * The model belongs to the SVO: created by the first guide_train or
+ * wfpg_nn_params(set = 1), freed by svo_destroy.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t log2_table;  /* entries per level = 2^log2_table, 10..24 (19) */
+    int32_t n_min;       /* coarsest resolution, >= 2 (16) */
+    int32_t n_max;       /* finest resolution; 0 = 2^depth of the SVO */
+    int32_t batch;       /* vertices per step, 64..2^22 (65536) */
+    int32_t steps;       /* Adam steps this call, >= 0 (100) */
+    float lr_mlp;        /* Adam step size of the MLP (2e-3) */
+    float lr_table;      /* Adam step size of the hash table (1e-2) */
+    float beta1, beta2;  /* Adam moment decays (0.9, 0.99) */
+    float adam_eps;      /* Adam denominator guard (1e-15) */
+    uint64_t seed;       /* initialisation seed, used when the model is created */
+} wfpg_train_cfg;
+
+wfpg_train_cfg wfpg_default_train_cfg(void);
+
+/* Run cfg->steps Adam steps. Step t takes the batch of cfg->batch consecutive
+ * vertices of the DEVICE queue pos/nrm (3 x n SoA each) starting at
+ * ((t - 1) * batch) mod n (clamped to end at n), marches their targets, and
+ * updates the model. The model configuration (log2_table, n_min, n_max, seed)
+ * is fixed when the model is created; later calls continue training it
+ * (steps = 0 only creates the model). Step counts t are global over calls.
+ * mean_loss (HOST, may be NULL): mean cross-entropy over the last 10 steps
+ * (synchronizes). Errors: EINVAL for bad arguments or configuration. */
+wfpg_status guide_train(wfpg_svo *svo, const float *pos, const float *nrm, int64_t n,
+                        const wfpg_train_cfg *cfg, float *mean_loss, void *hip_stream);
+
+/* Number of FP32 parameters of the attached model, -1 if none. */
+int64_t wfpg_nn_param_count(const wfpg_svo *svo);
+
+/* Copy the FP32 parameters to (set = 0) or from (set = 1) the HOST array
+ * host[count]; count must equal wfpg_nn_param_count. set = 1 creates a model
+ * with the default configuration if none exists and marks it trained.
+ * Synchronizes the stream. ESTATE: get without a model. */
+wfpg_status wfpg_nn_params(wfpg_svo *svo, float *host, int64_t count, int32_t set,
+                           void *hip_stream);
+
+/* Network distribution (softmax of the logits) of each vertex:
+ * prob_out DEVICE n x 256 FP32, row-major, bin b = v*16 + u. */
+wfpg_status wfpg_nn_forward(wfpg_svo *svo, const float *pos, const float *nrm, int64_t n,
+                            float *prob_out, void *hip_stream);
+
+/* Test-only: the gradient of the mean cross-entropy against DEVICE targets
+ * target[n][256] (rows summing to 1), written to DEVICE grad_out[count] in
+ * parameter order, and the loss to HOST *loss_out (may be NULL; synchronizes).
+ * Parameters are not changed. */
+wfpg_status wfpg_nn_grad(wfpg_svo *svo, const float *pos, const float *nrm, const float *target,
+                         int64_t n, float *grad_out, float *loss_out, void *hip_stream);
+
+/* Judge of the learned path: in mode 1, guide_sample marches every
+ * probe_stride-th vertex and computes the mean over those probes of
+ * KL(p_march || q_net) in nats (bins weighted by the marched pdf). If it
+ * exceeds kl_bound, the call's outputs are those of the march (mode 0) for
+ * every vertex. Last judged KL and the number of calls that fell back.
+ * Synchronizes the device. */
+wfpg_status wfpg_learned_stats(const wfpg_svo *svo, float *last_probe_kl, int64_t *fallbacks);
 
 #ifdef __cplusplus
 }

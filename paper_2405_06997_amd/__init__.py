@@ -34,6 +34,8 @@ EXPORTS = [
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy",
+    "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
+    "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
 
 
@@ -58,6 +60,13 @@ class Tile(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("mode", C.c_int32),
                 ("kl_bound", C.c_float), ("probe_stride", C.c_int32)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("log2_table", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32),
+                ("batch", C.c_int32), ("steps", C.c_int32), ("lr_mlp", C.c_float),
+                ("lr_table", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("adam_eps", C.c_float), ("seed", C.c_uint64)]
 
 
 def make_opts(N: int = 16, eps: float = 0.01, mode: int = 0, kl_bound: float = 0.05,
@@ -106,6 +115,13 @@ def lib():
         "wfpg_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
         "wfpg_autotune": (i32, [vp, vp, i64, i32, i32, vp, C.POINTER(Tile), C.POINTER(C.c_float)]),
         "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
+        "wfpg_default_train_cfg": (TrainCfg, []),
+        "guide_train": (i32, [vp, vp, vp, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp]),
+        "wfpg_nn_param_count": (i64, [vp]),
+        "wfpg_nn_params": (i32, [vp, vp, i64, i32, vp]),
+        "wfpg_nn_forward": (i32, [vp, vp, vp, i64, vp, vp]),
+        "wfpg_nn_grad": (i32, [vp, vp, vp, vp, i64, vp, C.POINTER(C.c_float), vp]),
+        "wfpg_learned_stats": (i32, [vp, C.POINTER(C.c_float), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -347,3 +363,82 @@ class BounceGraph:
 
     def __del__(self):
         self.close()
+
+
+# ------------------------------------------------------------ learned path
+
+def train_cfg(**kw) -> TrainCfg:
+    """Default training configuration with fields overridden by keyword."""
+    c = lib().wfpg_default_train_cfg()
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def guide_train(svo: SVO, pos, nrm, cfg: TrainCfg | None = None, stream=None, **kw) -> float:
+    """Adam steps of the learned model on march targets; returns the mean loss
+    of the last steps."""
+    n = pos.shape[1]
+    if nrm.shape != pos.shape:
+        raise ValueError("nrm must match pos")
+    cfg = cfg if cfg is not None else train_cfg(**kw)
+    loss = C.c_float(0)
+    _check("guide_train", lib().guide_train(svo.handle, _dptr(pos, 3, "pos"), _dptr(nrm, 3, "nrm"),
+                                            n, C.byref(cfg), C.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def nn_param_count(svo: SVO) -> int:
+    return int(lib().wfpg_nn_param_count(svo.handle))
+
+
+def nn_get_params(svo: SVO, stream=None) -> np.ndarray:
+    n = nn_param_count(svo)
+    if n < 0:
+        raise WfpgError("wfpg_nn_params", -4)
+    out = np.zeros(n, np.float32)
+    _check("wfpg_nn_params", lib().wfpg_nn_params(svo.handle, out.ctypes.data_as(C.c_void_p), n, 0,
+                                                  _stream(stream)))
+    return out
+
+
+def nn_set_params(svo: SVO, params: np.ndarray, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check("wfpg_nn_params", lib().wfpg_nn_params(svo.handle, p.ctypes.data_as(C.c_void_p), p.size, 1,
+                                                  _stream(stream)))
+
+
+def nn_forward(svo: SVO, pos, nrm, out=None, stream=None):
+    import torch
+    n = pos.shape[1]
+    if out is None:
+        out = torch.empty((n, 256), dtype=torch.float32, device=pos.device)
+    if out.numel() != n * 256:
+        raise ValueError("out must hold n*256 floats")
+    _check("wfpg_nn_forward", lib().wfpg_nn_forward(svo.handle, _dptr(pos, 3, "pos"),
+                                                    _dptr(nrm, 3, "nrm"), n, _dptr(out, name="out"),
+                                                    _stream(stream)))
+    return out
+
+
+def nn_grad(svo: SVO, pos, nrm, target, stream=None):
+    """(loss, gradient tensor) of the mean cross-entropy against target (n, 256)."""
+    import torch
+    n = pos.shape[1]
+    if target.shape != (n, 256):
+        raise ValueError("target must be (n, 256)")
+    g = torch.empty((nn_param_count(svo),), dtype=torch.float32, device=pos.device)
+    loss = C.c_float(0)
+    _check("wfpg_nn_grad", lib().wfpg_nn_grad(svo.handle, _dptr(pos, 3, "pos"), _dptr(nrm, 3, "nrm"),
+                                              _dptr(target, name="target"), n, _dptr(g, name="grad"),
+                                              C.byref(loss), _stream(stream)))
+    return float(loss.value), g
+
+
+def learned_stats(svo: SVO) -> dict:
+    kl = C.c_float(0)
+    fb = C.c_int64(0)
+    _check("wfpg_learned_stats", lib().wfpg_learned_stats(svo.handle, C.byref(kl), C.byref(fb)))
+    return {"last_probe_kl": float(kl.value), "fallbacks": int(fb.value)}

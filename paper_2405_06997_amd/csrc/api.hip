@@ -143,6 +143,7 @@ void free_svo(wfpg_svo *s)
                     s->d_sum, s->d_cnt, s->d_dropped, s->d_err, s->d_ctr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (s->nn_model) destroy_model(s->nn_model);
     delete s;
 }
 
@@ -286,9 +287,9 @@ wfpg_status guide_sample(const wfpg_svo *svo, const float *pos, const float *nrm
 {
     if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !dir_out || !pdf_out)))
         return WFPG_EINVAL;
-    if (opts->mode == 1) return WFPG_ESTATE;   // no learned model attached
-    (void)nrm;
     if (n == 0) return WFPG_OK;
+    if (opts->mode == 1)
+        return learned_sample(svo, pos, nrm, n, seed, bounce, opts, dir_out, pdf_out, (hipStream_t)hip_stream);
     GuideArgs a = base_args(svo, opts);
     a.pos = pos;
     a.n = n;

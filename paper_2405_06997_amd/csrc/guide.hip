@@ -265,6 +265,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
 {
     constexpr int NN = N * N;
     extern __shared__ uint64_t smem[];
+    if (a.gate && *a.gate == 0) return;   // uniform: every thread reads the same flag
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int D = sv.depth;

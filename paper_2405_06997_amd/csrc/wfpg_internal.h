@@ -87,6 +87,7 @@ struct GuideArgs {
     const float *dirtab;      // N*N*3 FP32 bin centres
     int32_t *err;             // device error flags
     unsigned long long *queue_ctr;   // vertex queue counter (reset before each launch)
+    const int32_t *gate;             // optional: the kernel does nothing unless *gate != 0
 };
 
 struct TileConfig {          // launch shape chosen by the autotuner
@@ -113,6 +114,10 @@ TileConfig choose_tile(const struct ::wfpg_svo *svo, int N);
 TileConfig legalize_tile(TileConfig t, int N, int depth);
 
 int device_cu_count();
+void destroy_model(void *model);
+wfpg_status learned_sample(const struct ::wfpg_svo *svo, const float *pos, const float *nrm, int64_t n,
+                           uint64_t seed, uint32_t bounce, const wfpg_opts *o, float *dir_out,
+                           float *pdf_out, hipStream_t s);
 // Records a failing HIP call (thread-local) for wfpg_last_error().
 hipError_t note_error(hipError_t e, const char *file, int line);
 #define WFPG_HIP_TRY(x)                                                                     \
@@ -143,6 +148,7 @@ struct wfpg_svo {
     unsigned long long *d_dropped = nullptr;
     int32_t *d_err = nullptr;
     unsigned long long *d_ctr = nullptr;   // pool of vertex-queue counters
+    void *nn_model = nullptr;              // learned stand-in (nn.hip), created on demand
     mutable std::atomic<unsigned> ctr_next{0};   // round-robin slot of the pool
     wfpg::SvoView view() const
     {

@@ -145,9 +145,10 @@ def area_points(rects: np.ndarray, n: int, seed: int):
 
 
 def camera_queue(rects: np.ndarray, width: int = 1920, height: int = 1080,
-                 eye=(0.5, 0.02, 0.5), vfov_deg: float = 60.0):
+                 eye=(0.5, 0.02, 0.5), vfov_deg: float = 60.0, jitter_seed: int | None = None):
     """Primary hits of a pinhole camera looking along +y (z up), one ray per
-    pixel centre, intersected analytically against the rectangles in FP64.
+    pixel centre (or, with ``jitter_seed``, per point uniform inside the pixel),
+    intersected analytically against the rectangles in FP64.
 
     Each rectangle is only tested against the pixels inside the bounding box
     of its projection (all of them when it straddles the eye plane). Returns
@@ -157,9 +158,17 @@ def camera_queue(rects: np.ndarray, width: int = 1920, height: int = 1080,
     eye = np.asarray(eye, np.float64)
     th = np.tan(np.radians(vfov_deg) / 2)
     aspect = width / height
-    sx = (np.arange(width) + 0.5) / width * 2 - 1
-    sy = 1 - (np.arange(height) + 0.5) / height * 2
-    X, Z = np.meshgrid(sx * aspect * th, sy * th)  # (H, W)
+    if jitter_seed is None:
+        jx = np.full((height, width), 0.5)
+        jy = jx
+    else:
+        rng = np.random.default_rng(jitter_seed)
+        jx = rng.random((height, width))
+        jy = rng.random((height, width))
+    sx = (np.arange(width)[None, :] + jx) / width * 2 - 1
+    sy = 1 - (np.arange(height)[:, None] + jy) / height * 2
+    X = sx * aspect * th                            # (H, W)
+    Z = sy * th
     inv = 1.0 / np.sqrt(X * X + 1.0 + Z * Z)
     D = np.stack([X * inv, inv, Z * inv], 0)       # (3, H, W) unit directions
     best_t = np.full((height, width), np.inf)

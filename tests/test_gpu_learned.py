@@ -1,0 +1,307 @@
+"""GPU tests of the learned stand-in for the march, through the C ABI.
+
+* The BF16 MFMA forward pass and the backward pass (gradients of the mean
+  cross-entropy) agree with the BF16-faithful CPU oracle, which rounds to BF16
+  at the same points (table, inputs, weights, hidden activations, logit and
+  pre-activation gradients) but accumulates in FP64. The GPU accumulates BF16
+  products in FP32 inside the matrix cores, in another order, so a value that
+  lies within an FP32 rounding of a BF16 rounding boundary may round to the
+  neighbouring BF16 value (2^-8 relative) on one side only. The bars below
+  bound the effect of a few such flips, not of a wrong term: a dropped term,
+  a transposed operand or a wrong index moves the compared quantities by
+  orders of magnitude more (the same tests against the FP64 oracle would
+  fail their bars only by the BF16 rounding itself, which is larger).
+* Sampling from the network returns the pdf of the bin it sampled.
+* Training lowers the KL to the march; the judge falls back to the march,
+  bit for bit, when the probes' KL exceeds the bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import nn_params
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(log2_table=12, n_min=4, n_max=64)
+FOUR_PI = 4 * math.pi
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def w():
+    import paper_2405_06997_amd as w
+    w.lib()
+    return w
+
+
+def dev(torch_dev, a):
+    torch, d = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a)).to(d)
+
+
+@pytest.fixture(scope="module")
+def box(w, torch_dev):
+    """Cornell box at depth 6 with one exitance splat per (leaf, side) and an
+    attached small learned model."""
+    import oracle
+    rects = synth.cornell_box()
+    o = oracle.SVO(rects, 6)
+    xyz, em = o.leaf_info()
+    sp = synth.leaf_splats(xyz, o.normals(6), em, 6, seed=2)
+    g = w.svo_build(rects, 6)
+    w.svo_accumulate(g, *[dev(torch_dev, a) for a in sp])
+    pos, nrm, _ = synth.area_points(rects, 300, 21)
+    return dict(rects=rects, g=g, pos=pos, nrm=nrm)
+
+
+def small_model(w, torch_dev, rects):
+    g = w.svo_build(rects, 6)
+    pos, nrm, _ = synth.area_points(rects, 64, 1)
+    w.guide_train(g, dev(torch_dev, pos), dev(torch_dev, nrm), steps=0, **SMALL)
+    return g
+
+
+# ------------------------------------------------------------- forward ----
+def test_forward_matches_bf16_oracle(orc, w, torch_dev, box):
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    assert w.nn_param_count(g) == n_par
+    params = nn_params.random_params(n_par, np.random.default_rng(3))
+    w.nn_set_params(g, params)
+    assert np.array_equal(w.nn_get_params(g), params)
+    pos, nrm = box["pos"], box["nrm"]          # 300 rows: 4 full 64-row tiles and a ragged one
+    prob = w.nn_forward(g, dev(torch_dev, pos), dev(torch_dev, nrm)).cpu().numpy().astype(np.float64)
+    p1, _ = orc.nn_forward(params, cfg, pos, nrm, mode=1)
+    p0, _ = orc.nn_forward(params, cfg, pos, nrm, mode=0)
+    assert np.allclose(prob.sum(1), 1, atol=1e-5)
+    kl_gpu = orc.kl_rows(p1, prob)
+    kl_ref = orc.kl_rows(p0, p1)           # the BF16 rounding itself
+    # a handful of one-ulp BF16 flips moves the KL by far less than the rounding does
+    assert kl_gpu.max() < 1e-5, kl_gpu.max()
+    assert kl_gpu.mean() < 0.05 * kl_ref.mean(), (kl_gpu.mean(), kl_ref.mean())
+    rel = np.abs(prob - p1) / p1
+    assert np.median(rel) < 1e-4 and rel.max() < 2e-2, (np.median(rel), rel.max())
+
+
+def test_forward_pinned_structure(orc, w, torch_dev, box):
+    """Zero output layer: exactly uniform; zero MLP except the output bias:
+    exactly softmax(b4) at every vertex."""
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    params = nn_params.random_params(n_par, np.random.default_rng(4))
+    lay = nn_params.layout(n_par)
+    for name in ("W4", "b4"):
+        a, m = lay[name]
+        params[a:a + m] = 0
+    w.nn_set_params(g, params)
+    pos, nrm = dev(torch_dev, box["pos"]), dev(torch_dev, box["nrm"])
+    prob = w.nn_forward(g, pos, nrm).cpu().numpy()
+    assert (prob == np.float32(1 / 256)).all()
+    a, m = lay["b4"]
+    b4 = np.random.default_rng(5).normal(0, 2, m).astype(np.float32)
+    params[a:a + m] = b4
+    a, m = lay["W4"]
+    params[a:a + m] = 0
+    w.nn_set_params(g, params)
+    prob = w.nn_forward(g, pos, nrm).cpu().numpy()
+    want = np.exp(b4.astype(np.float64) - b4.max())
+    want /= want.sum()
+    np.testing.assert_allclose(prob, np.broadcast_to(want, prob.shape), rtol=2e-6)
+
+
+# ------------------------------------------------------------ backward ----
+def test_gradient_matches_bf16_oracle(orc, w, torch_dev, box):
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    rng = np.random.default_rng(6)
+    params = nn_params.random_params(n_par, rng)
+    w.nn_set_params(g, params)
+    pos, nrm = box["pos"], box["nrm"]
+    t = rng.random((pos.shape[1], 256)) ** 4
+    t /= t.sum(1, keepdims=True)
+    loss, grad = w.nn_grad(g, dev(torch_dev, pos), dev(torch_dev, nrm), dev(torch_dev, t.astype(np.float32)))
+    grad = grad.cpu().numpy().astype(np.float64)
+    l1, g1 = orc.nn_grad(params, cfg, pos, nrm, t, mode=1)
+    l0, g0 = orc.nn_grad(params, cfg, pos, nrm, t, mode=0)
+    assert abs(loss - l1) < 1e-5 * abs(l1), (loss, l1)
+    lay = nn_params.layout(n_par)
+    report = {}
+    for name, (a, m) in lay.items():
+        d = np.linalg.norm(grad[a:a + m] - g1[a:a + m])
+        ref = np.linalg.norm(g0[a:a + m] - g1[a:a + m])
+        nrm1 = np.linalg.norm(g1[a:a + m])
+        report[name] = (d / nrm1, ref / nrm1)
+        # FP32-vs-FP64 accumulation plus a few BF16 flips, against the
+        # whole BF16 rounding (ref) and the gradient's own size
+        assert d <= 2e-2 * nrm1 and d <= 0.5 * ref + 1e-6 * nrm1, (name, report[name])
+    # the table gradient touches exactly the corners of the encoded cells
+    a, m = lay["table"]
+    assert np.array_equal(grad[a:a + m] != 0, g1[a:a + m] != 0)
+
+
+def test_gradient_step_descends(orc, w, torch_dev, box):
+    """One small step against the GPU gradient lowers the FP64 oracle's loss by
+    about |g|^2 * lr (first order)."""
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    rng = np.random.default_rng(7)
+    params = nn_params.random_params(n_par, rng)
+    w.nn_set_params(g, params)
+    pos, nrm = box["pos"], box["nrm"]
+    t = rng.random((pos.shape[1], 256)) ** 4
+    t /= t.sum(1, keepdims=True)
+    _, grad = w.nn_grad(g, dev(torch_dev, pos), dev(torch_dev, nrm), dev(torch_dev, t.astype(np.float32)))
+    grad = grad.cpu().numpy().astype(np.float64)
+    l0, _ = orc.nn_grad(params, cfg, pos, nrm, t, mode=0)
+    lr = 1e-3 / np.linalg.norm(grad)
+    l1, _ = orc.nn_grad((params - lr * grad).astype(np.float32), cfg, pos, nrm, t, mode=0)
+    want = lr * np.dot(grad, grad)
+    assert 0.5 * want < l0 - l1 < 1.5 * want, (l0 - l1, want)
+
+
+# ------------------------------------------------------------ sampling ----
+def test_learned_sample_returns_pdf_of_sampled_bin(orc, w, torch_dev, box):
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    params = nn_params.random_params(n_par, np.random.default_rng(8))
+    w.nn_set_params(g, params)
+    pos, nrm = box["pos"], box["nrm"]
+    dpos, dnrm = dev(torch_dev, pos), dev(torch_dev, nrm)
+    prob = w.nn_forward(g, dpos, dnrm).cpu().numpy().astype(np.float64)
+    opts = w.make_opts(N=16, mode=1, kl_bound=1e30, probe_stride=7)
+    d, pdf = w.guide_sample(g, dpos, opts, seed=11, bounce=2, nrm=dnrm)
+    d, pdf = d.cpu().numpy().astype(np.float64), pdf.cpu().numpy().astype(np.float64)
+    assert np.allclose(np.linalg.norm(d, axis=0), 1, atol=1e-6)
+    uv = orc.oct_encode_many(d)
+    b = np.minimum((uv * 16).astype(np.int64), 15)
+    frac = uv * 16 - np.floor(uv * 16)
+    inner = ((frac > 1e-4) & (frac < 1 - 1e-4)).all(0)
+    assert inner.mean() > 0.99
+    bin_ = b[1] * 16 + b[0]
+    want = prob[np.arange(len(bin_)), bin_] * 256 / FOUR_PI
+    np.testing.assert_allclose(pdf[inner], want[inner], rtol=1e-5)
+    st = w.learned_stats(g)
+    assert st["fallbacks"] == 0 and math.isfinite(st["last_probe_kl"])
+
+
+def test_learned_sample_chi_square(orc, w, torch_dev, box):
+    """All vertices at one position: the sampled bins follow the network's
+    distribution (chi-square over bins with expected count >= 5)."""
+    cfg = orc.nn_cfg(**SMALL)
+    n_par = orc.nn_num_params(cfg)
+    g = small_model(w, torch_dev, box["rects"])
+    params = nn_params.random_params(n_par, np.random.default_rng(9), scale=1.0)
+    w.nn_set_params(g, params)
+    n = 200_000
+    pos = np.repeat(box["pos"][:, :1], n, axis=1)
+    nrm = np.repeat(box["nrm"][:, :1], n, axis=1)
+    dpos, dnrm = dev(torch_dev, pos), dev(torch_dev, nrm)
+    p = w.nn_forward(g, dpos[:, :1].contiguous(), dnrm[:, :1].contiguous()).cpu().numpy()[0].astype(np.float64)
+    opts = w.make_opts(N=16, mode=1, kl_bound=1e30, probe_stride=1024)
+    d, _ = w.guide_sample(g, dpos, opts, seed=3, bounce=0, nrm=dnrm)
+    uv = orc.oct_encode_many(d.cpu().numpy().astype(np.float64))
+    b = np.minimum((uv * 16).astype(np.int64), 15)
+    cnt = np.bincount(b[1] * 16 + b[0], minlength=256).astype(np.float64)
+    exp = p * n
+    big = exp >= 5
+    chi2 = (((cnt - exp) ** 2 / exp)[big]).sum() + ((cnt[~big].sum() - exp[~big].sum()) ** 2 /
+                                                    max(exp[~big].sum(), 1e-9) if (~big).any() else 0)
+    dof = big.sum() + (1 if (~big).any() else 0) - 1
+    from scipy.stats import chi2 as chi2d
+    assert chi2d.sf(chi2, dof) > 1e-4, (chi2, dof)
+
+
+# ------------------------------------------------- training and judge ----
+@pytest.fixture(scope="module")
+def trained(w, torch_dev, box):
+    """Cornell box model trained on march pdfs of surface points."""
+    rects, g = box["rects"], box["g"]
+    pos, nrm, _ = synth.area_points(rects, 131072, 22)
+    dpos, dnrm = dev(torch_dev, pos), dev(torch_dev, nrm)
+    hpos, hnrm, _ = synth.area_points(rects, 4096, 23)      # held out
+    hpos, hnrm = dev(torch_dev, hpos), dev(torch_dev, hnrm)
+    opts = w.make_opts(N=16)
+    target = w.guide_pdf(g, hpos, opts).cpu().numpy().astype(np.float64) * FOUR_PI / 256
+    target /= target.sum(1, keepdims=True)
+    w.guide_train(g, dpos, dnrm, steps=0, seed=1, n_max=64)
+    kl_init = kl_to(w, g, hpos, hnrm, target)
+    losses = [w.guide_train(g, dpos, dnrm, steps=100, batch=16384, n_max=64) for _ in range(4)]
+    kl_trained = kl_to(w, g, hpos, hnrm, target)
+    return dict(g=g, dpos=dpos, dnrm=dnrm, hpos=hpos, hnrm=hnrm, target=target, kl_init=kl_init,
+                kl_trained=kl_trained, losses=losses)
+
+
+def kl_to(w, g, hpos, hnrm, target):
+    import oracle
+    q = w.nn_forward(g, hpos, hnrm).cpu().numpy().astype(np.float64)
+    return float(oracle.kl_rows(target, q).mean())
+
+
+def test_training_learns_march_pdfs(trained):
+    t = trained
+    assert t["losses"][-1] < t["losses"][0]
+    # the trained network is far closer to the march than the initial one and
+    # within the fallback bound on held-out vertices
+    assert t["kl_trained"] < 0.2 * t["kl_init"], (t["kl_trained"], t["kl_init"])
+    assert t["kl_trained"] < 0.05, t["kl_trained"]
+
+
+def test_judge_kl_is_probe_mean(orc, w, torch_dev, trained):
+    t, g = trained, trained["g"]
+    hpos, hnrm = t["hpos"], t["hnrm"]
+    stride = 16
+    opts = w.make_opts(N=16, mode=1, kl_bound=1e30, probe_stride=stride)
+    w.guide_sample(g, hpos, opts, seed=1, bounce=0, nrm=hnrm)
+    kl = w.learned_stats(g)["last_probe_kl"]
+    q = w.nn_forward(g, hpos, hnrm).cpu().numpy().astype(np.float64)
+    want = float(orc.kl_rows(t["target"][::stride], q[::stride]).mean())
+    assert abs(kl - want) <= 1e-3 * want + 1e-6, (kl, want)
+
+
+def test_fallback_is_the_march_bit_for_bit(w, torch_dev, trained):
+    g, hpos, hnrm = trained["g"], trained["hpos"], trained["hnrm"]
+    before = w.learned_stats(g)["fallbacks"]
+    d0, p0 = w.guide_sample(g, hpos, w.make_opts(N=16), seed=5, bounce=3)
+    d1, p1 = w.guide_sample(g, hpos, w.make_opts(N=16, mode=1, kl_bound=0.0), seed=5, bounce=3, nrm=hnrm)
+    assert w.learned_stats(g)["fallbacks"] == before + 1
+    assert np.array_equal(d0.cpu().numpy().view(np.uint32), d1.cpu().numpy().view(np.uint32))
+    assert np.array_equal(p0.cpu().numpy().view(np.uint32), p1.cpu().numpy().view(np.uint32))
+    # within the bound: the network's samples (they differ from the march's)
+    d2, p2 = w.guide_sample(g, hpos, w.make_opts(N=16, mode=1, kl_bound=1.0), seed=5, bounce=3, nrm=hnrm)
+    assert w.learned_stats(g)["fallbacks"] == before + 1
+    assert not np.array_equal(p0.cpu().numpy(), p2.cpu().numpy())
+
+
+def test_learned_errors(w, torch_dev, box):
+    g = w.svo_build(box["rects"], 6)
+    pos, nrm = dev(torch_dev, box["pos"]), dev(torch_dev, box["nrm"])
+    with pytest.raises(w.WfpgError) as e:
+        w.guide_sample(g, pos, w.make_opts(N=16, mode=1), seed=0, bounce=0, nrm=nrm)
+    assert e.value.status == -4
+    with pytest.raises(w.WfpgError):
+        w.nn_get_params(g)
+    with pytest.raises(w.WfpgError) as e:
+        w.guide_train(g, pos, nrm, steps=1, log2_table=30)
+    assert e.value.status == -1
+    w.guide_train(g, pos, nrm, steps=0)
+    with pytest.raises(w.WfpgError) as e:      # the learned field is 16 x 16
+        w.guide_sample(g, pos, w.make_opts(N=8, mode=1), seed=0, bounce=0, nrm=nrm)
+    assert e.value.status == -1
+    with pytest.raises(w.WfpgError) as e:      # normals are inputs of the network
+        w.guide_sample(g, pos, w.make_opts(N=16, mode=1), seed=0, bounce=0)
+    assert e.value.status == -1

@@ -7,38 +7,18 @@ import math
 import numpy as np
 import pytest
 
+import nn_params
 import synth
 
 SMALL = dict(log2_table=12, n_min=4, n_max=64)
 
 
 def layout(o, cfg):
-    """Offsets of W0,b0,...,W4,b4 and of the table in the parameter vector."""
-    fin = [o.NN_IN, 64, 64, 64, 64]
-    fout = [64, 64, 64, 64, 256]
-    off, segs = 0, []
-    for k in range(5):
-        segs.append(("W%d" % k, off, fout[k] * fin[k]))
-        off += fout[k] * fin[k]
-        segs.append(("b%d" % k, off, fout[k]))
-        off += fout[k]
-    segs.append(("table", off, o.nn_num_params(cfg) - off))
-    return {name: (a, n) for name, a, n in segs}
+    return nn_params.layout(o.nn_num_params(cfg))
 
 
 def random_params(o, cfg, rng, scale=0.3, table_scale=0.5):
-    n = o.nn_num_params(cfg)
-    lay = layout(o, cfg)
-    p = np.zeros(n, np.float32)
-    fin = [o.NN_IN, 64, 64, 64, 64]
-    for k in range(5):
-        a, m = lay["W%d" % k]
-        p[a:a + m] = rng.normal(0, scale * math.sqrt(2.0 / fin[k]), m)
-        a, m = lay["b%d" % k]
-        p[a:a + m] = rng.normal(0, 0.1, m)
-    a, m = lay["table"]
-    p[a:a + m] = rng.normal(0, table_scale, m)
-    return p
+    return nn_params.random_params(o.nn_num_params(cfg), rng, scale, table_scale)
 
 
 def test_resolutions_and_sizes(orc):
