@@ -37,6 +37,14 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
+    ap.add_argument("--only-march", action="store_true",
+                    help="skip the learned, batching and precision sections (profiling runs)")
+    ap.add_argument("--train-pairs", type=int, default=50_000_000,
+                    help="(vertex, march pdf) pairs the learned model is trained on")
+    ap.add_argument("--budget-ns", type=float, default=30.0,
+                    help="guiding time budget per vertex for the autotuner's choice of N")
+    ap.add_argument("--train-frames", type=int, default=4,
+                    help="jittered camera frames that supply the training vertices")
     return ap.parse_args()
 
 
@@ -139,9 +147,208 @@ def main():
             "node_tests_per_bin": visits / (n * NN), "hit_fraction": hits / (n * NN),
         },
     }
+    orc = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
+        out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
+    if not args.only_march:
+        out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
+        out["batching"] = batching_section(w, svo, room, cam, cnrm, args)
+        out["precision"] = precision_section(w, room, sp, pos, cam, args, orc, tile)
     print(json.dumps(out))
+
+
+def _timed(fn, K, warmup):
+    """Mean milliseconds of fn() over K calls, HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for k in range(K):
+        ev[k][0].record(stream)
+        fn()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / K
+
+
+def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
+    """Hash-grid MLP trained on march pdfs of jittered frames of the same
+    camera (as a progressive renderer sees them), then guide_sample in mode 1
+    (network sample + march probes every 256th vertex + KL judge with the
+    march as fallback) on the headline queue."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = pos.device
+    t0 = time.perf_counter()
+    frames = [synth.camera_queue(room, jitter_seed=100 + f)[:2] for f in range(args.train_frames)]
+    tp = np.concatenate([f[0] for f in frames], 1)
+    tn = np.concatenate([f[1] for f in frames], 1)
+    perm = np.random.default_rng(7).permutation(tp.shape[1])
+    tp = torch.from_numpy(np.ascontiguousarray(tp[:, perm])).to(dev)
+    tn = torch.from_numpy(np.ascontiguousarray(tn[:, perm])).to(dev)
+    gen_s = time.perf_counter() - t0
+    batch = 65536
+    steps = max(1, args.train_pairs // batch)
+    nrm = torch.from_numpy(cnrm).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = w.guide_train(svo, tp, tn, steps=steps, batch=batch)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del tp, tn
+
+    opts1 = w.make_opts(N=16, mode=1, kl_bound=0.05, probe_stride=256)
+    d_out = torch.empty((3, n), device=dev)
+    p_out = torch.empty((n,), device=dev)
+    fb0 = w.learned_stats(svo)["fallbacks"]
+    K = args.steps
+    ms = _timed(lambda: w.guide_sample(svo, pos, opts1, seed=3, bounce=0, nrm=nrm, dir_out=d_out,
+                                       pdf_out=p_out), K, args.warmup)
+    st = w.learned_stats(svo)
+    fallbacks = st["fallbacks"] - fb0
+    assert torch.isfinite(p_out).all() and (p_out > 0).all()
+    fwd_ms = _timed(lambda: w.nn_forward(svo, pos, nrm), 3, 1)
+    # per-vertex KL(march || network) on an evenly strided sample
+    sub = slice(0, n, max(1, n // 65536))
+    sp_, sn_ = pos[:, sub].contiguous(), nrm[:, sub].contiguous()
+    t = w.guide_pdf(svo, sp_, w.make_opts(N=16)).double()
+    t = t / t.sum(1, keepdim=True)
+    q = w.nn_forward(svo, sp_, sn_).double()
+    kl = torch.where(t > 0, t * (t.log() - q.log()), torch.zeros_like(t)).sum(1).cpu().numpy()
+    flops = 2 * (35 * 64 + 3 * 64 * 64 + 64 * 256)   # algorithmic MACs x 2 per vertex
+    return {
+        "what": "hash-grid (16 x 2^19 x 2) + MLP 35-64-64-64-64-256, BF16 MFMA, trained on the GPU "
+                "on march pdfs; mode-1 guide_sample with KL judge (bound 0.05 nats, probe every "
+                "256th vertex) and march fallback",
+        "train": {"pairs": steps * batch, "steps": steps, "batch": batch, "frames": args.train_frames,
+                  "seconds": train_s, "final_loss": loss, "data_gen_seconds": gen_s},
+        "guide_sample_ms": ms,
+        "samples_per_s": n / (ms * 1e-3),
+        "step_samples_per_s": n / ((ms + float(np.mean(acc_ms))) * 1e-3),
+        "speedup_vs_march": march_ms / ms,
+        "fallbacks": fallbacks, "calls": K + args.warmup,
+        "judge_probe_kl": st["last_probe_kl"],
+        "kl_per_vertex": {"mean": float(kl.mean()), "median": float(np.median(kl)),
+                          "p90": float(np.quantile(kl, 0.9)), "vertices": int(kl.size)},
+        "nn_forward_ms": fwd_ms,
+        "mfma_flops_per_vertex": flops,
+    }
+
+
+def batching_section(w, svo, room, cam, cnrm, args):
+    """Eight-bounce wavefront (queue sizes decaying by U[0.5, 0.8] per bounce)
+    replayed as one captured graph of persistent guide kernels. The autotuner
+    picks N in {8, 16, 32} and the tile: the finest N whose time per vertex
+    fits the budget, tuned on the camera bounce and on the first secondary
+    bounce (later bounces share its vertex distribution)."""
+    import torch
+
+    import synth
+    dev = torch.device("cuda:0")
+    queues, sizes = synth.bounce_queues(room, cam, cnrm, 8, 15)
+    qpos = [torch.from_numpy(q[0]).to(dev) for q in queues]
+    picks = []
+    for b in (0, 1):
+        sub = qpos[b][:, :: max(1, qpos[b].shape[1] // 65536)].contiguous()
+        picks.append(w.autotune_n(svo, sub, args.budget_ns, reps=3))
+    Ns = [picks[0]["N"]] + [picks[1]["N"]] * (len(sizes) - 1)
+    n_dev = torch.tensor(sizes, dtype=torch.int64, device=dev)
+    G = w.BounceGraph(svo, qpos, n_dev, Ns, seed=7)
+    K = args.steps
+    g_ms = _timed(G.launch, K, args.warmup)
+
+    def eager():
+        for b, q in enumerate(qpos):
+            w.guide_sample(svo, q, w.make_opts(N=Ns[b]), seed=7, bounce=b,
+                           dir_out=G.dirs[b], pdf_out=G.pdfs[b])
+    e_ms = _timed(eager, K, args.warmup)
+    fixed = {}
+    for N in (8, 16, 32):
+        Gn = w.BounceGraph(svo, qpos, n_dev, [N] * len(sizes), seed=7)
+        ms = _timed(Gn.launch, max(3, K // 4), 1)
+        fixed[str(N)] = {"graph_ms": ms, "samples_per_s": sum(sizes) / (ms * 1e-3)}
+        del Gn
+    return {"bounces": len(sizes), "queue_sizes": sizes, "vertices": sum(sizes),
+            "budget_ns_per_vertex": args.budget_ns, "N_per_bounce": Ns,
+            "tuned": [{"bounce": b, "N": p["N"], "tile": p["tile"],
+                       "ms_per_N_65536": {str(k): v for k, v in p["ms_per_N"].items()}}
+                      for b, p in zip((0, 1), picks)],
+            "graph_ms": g_ms, "samples_per_s": sum(sizes) / (g_ms * 1e-3),
+            "eager_ms": e_ms, "graph_speedup_vs_eager": e_ms / g_ms,
+            "fixed_N": fixed}
+
+
+def precision_section(w, room, sp, pos, cam, args, orc, tile):
+    """Exitance and field bins stored in FP16 / BF16 (CDF and pdf in FP32):
+    guide_sample rate on the headline queue, per-bin pdf error against the
+    FP64 oracle on a strided sample of vertices, and a chi-square test of
+    2^20 samples drawn at 64 vertices against the FP64 oracle pdf."""
+    import numpy as np
+    import torch
+    dev = pos.device
+    n = pos.shape[1]
+    out = {}
+    opts = w.make_opts(N=args.N)
+    NN = args.N * args.N
+    for name, fmt in (("fp16", w.WFPG_FP16), ("bf16", w.WFPG_BF16), ("fp32", w.WFPG_FP32)):
+        g = w.svo_build(room, 10, fmt)
+        w.svo_accumulate(g, *sp)
+        d_out = torch.empty((3, n), device=dev)
+        p_out = torch.empty((n,), device=dev)
+        w.set_tile(g, args.N, **tile)     # the launch shape tuned for the FP32 SVO
+        ms = _timed(lambda: w.guide_sample(g, pos, opts, seed=1, bounce=0, dir_out=d_out, pdf_out=p_out),
+                    args.steps, args.warmup)
+        r = {"guide_sample_ms": ms, "samples_per_s": n / (ms * 1e-3)}
+        if orc is not None:
+            S = 2048
+            sub = np.ascontiguousarray(cam[:, :: n // S][:, :S])
+            _, truth = orc.guide_pdf(sub, args.N, truth=True)
+            gp = w.guide_pdf(g, torch.from_numpy(sub).to(dev), opts).cpu().numpy().astype(np.float64)
+            rel = np.abs(gp - truth) / truth
+            tv = 0.5 * np.abs(gp - truth).sum(1) * (4 * np.pi / NN)
+            r["pdf_rel_err_vs_fp64"] = {"max": float(rel.max()), "mean": float(rel.mean()),
+                                        "p99": float(np.quantile(rel, 0.99)), "vertices": S}
+            r["tv_distance_vs_fp64"] = {"max": float(tv.max()), "mean": float(tv.mean())}
+            r["chi_square"] = chi_square(w, g, orc, cam, args.N, dev)
+        out[name] = r
+        del g
+    return out
+
+
+def chi_square(w, g, orc, cam, N, dev, V=64, per=16384):
+    """Samples of guide_sample at V vertices (per each) binned against the
+    FP64 oracle pdf of those vertices; bins with expected count < 5 pooled per
+    vertex."""
+    import numpy as np
+    import torch
+    from scipy.stats import chi2
+    n = cam.shape[1]
+    base = np.ascontiguousarray(cam[:, :: n // V][:, :V])
+    _, truth = orc.guide_pdf(base, N, truth=True)
+    prob = truth * (4 * np.pi / (N * N))
+    prob /= prob.sum(1, keepdims=True)
+    rep = torch.from_numpy(np.repeat(base, per, axis=1)).to(dev)
+    d, _ = w.guide_sample(g, rep, w.make_opts(N=N), seed=77, bounce=1)
+    import oracle
+    uv = oracle.oct_encode_many(d.cpu().numpy().astype(np.float64))
+    b = np.minimum((uv * N).astype(np.int64), N - 1)
+    bins = (b[1] * N + b[0]).reshape(V, per)
+    stat, dof = 0.0, 0
+    for v in range(V):
+        cnt = np.bincount(bins[v], minlength=N * N).astype(np.float64)
+        e = prob[v] * per
+        big = e >= 5
+        stat += float((((cnt - e) ** 2) / e)[big].sum())
+        k = int(big.sum())
+        if (~big).any() and e[~big].sum() > 0:
+            stat += float((cnt[~big].sum() - e[~big].sum()) ** 2 / e[~big].sum())
+            k += 1
+        dof += k - 1
+    return {"samples": V * per, "vertices": V, "stat": stat, "dof": dof, "p_value": float(chi2.sf(stat, dof))}
 
 
 def cpu_baseline(room, splats, cam, N, S, n):
@@ -163,11 +370,12 @@ def cpu_baseline(room, splats, cam, N, S, n):
     o.guide_sample(sub, N, seed=1, bounce=0)
     t_gs = time.perf_counter() - t
     step = t_acc + t_gs / S * n
-    return {"value": n / step, "unit": "samples/s", "cores": oracle.num_threads(),
+    base = {"value": n / step, "unit": "samples/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"accumulate+propagate of all 2M splats ({t_acc:.2f} s) + guide_sample on "
                       f"every {stride}th camera-queue vertex ({S} of {n}, {t_gs:.2f} s), extrapolated "
                       f"to one full step"}
+    return base, o
 
 
 if __name__ == "__main__":

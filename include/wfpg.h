@@ -273,6 +273,17 @@ wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile)
 wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N, int32_t reps,
                           void *hip_stream, wfpg_tile *best_out, float *best_ms);
 
+/* Pick the field resolution for a queue: tunes the tile of every N in
+ * {8, 16, 32} on the DEVICE queue pos (3 x n) as wfpg_autotune does, then
+ * returns in *N_out the largest N whose best time per vertex is within
+ * budget_ns_per_vertex (N = 8 if none is), its tile in tile_out (may be NULL)
+ * and the best times of N = 8, 16, 32 in ms_per_N[3] (HOST, may be NULL).
+ * Finer fields resolve the incident radiance better (Sec. 3.3) at a cost that
+ * grows with N^2; the budget states what a bounce may spend per vertex. */
+wfpg_status wfpg_autotune_n(wfpg_svo *svo, const float *pos, int64_t n, int32_t reps,
+                            float budget_ns_per_vertex, void *hip_stream, int32_t *N_out,
+                            wfpg_tile *tile_out, float *ms_per_N);
+
 /* ---------------------------------------------------------------------
  * Batched bounces: the per-depth guiding of Alg. 1 for a whole wavefront
  * (one guide_sample per bounce), captured once into a HIP graph of

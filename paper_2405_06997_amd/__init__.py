@@ -33,7 +33,7 @@ EXPORTS = [
     "guide_pdf", "guide_sample", "pdf_eval", "svo_stats", "svo_level_size", "svo_export_level",
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
-    "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy",
+    "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
     "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
     "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
@@ -115,6 +115,8 @@ def lib():
         "wfpg_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
         "wfpg_autotune": (i32, [vp, vp, i64, i32, i32, vp, C.POINTER(Tile), C.POINTER(C.c_float)]),
         "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
+        "wfpg_autotune_n": (i32, [vp, vp, i64, i32, C.c_float, vp, C.POINTER(i32), C.POINTER(Tile),
+                                  vp]),
         "wfpg_default_train_cfg": (TrainCfg, []),
         "guide_train": (i32, [vp, vp, vp, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp]),
         "wfpg_nn_param_count": (i64, [vp]),
@@ -324,6 +326,19 @@ def autotune(svo: SVO, pos, N: int, reps: int = 3, stream=None) -> dict:
                                                 reps, _stream(stream), C.byref(t), C.byref(ms)))
     return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
                 blocks_per_cu=t.blocks_per_cu, ms=ms.value)
+
+
+def autotune_n(svo: SVO, pos, budget_ns_per_vertex: float, reps: int = 3, stream=None) -> dict:
+    """Finest N in {8, 16, 32} whose tuned time per vertex fits the budget."""
+    t = Tile()
+    N = C.c_int32(0)
+    ms = (C.c_float * 3)()
+    _check("wfpg_autotune_n", lib().wfpg_autotune_n(svo.handle, _dptr(pos, 3, "pos"), pos.shape[1], reps,
+                                                    budget_ns_per_vertex, _stream(stream), C.byref(N),
+                                                    C.byref(t), C.cast(ms, C.c_void_p)))
+    return dict(N=N.value, tile=dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
+                                     blocks_per_cu=t.blocks_per_cu),
+                ms_per_N={8: ms[0], 16: ms[1], 32: ms[2]})
 
 
 class BounceGraph:

@@ -95,7 +95,7 @@ namespace {
 wfpg_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return WFPG_OK;
-    if (!g_last_error[0]) note_error(e, "api", 0);
+    if (!g_last_error[0]) (void)note_error(e, "api", 0);
     if (e == hipErrorOutOfMemory) return WFPG_ENOMEM;
     return WFPG_EDEVICE;
 }

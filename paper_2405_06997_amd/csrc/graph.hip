@@ -85,7 +85,7 @@ wfpg_status wfpg_graph_create(const wfpg_svo *svo, int32_t n_bounces, const floa
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
-        note_error(e, __FILE__, __LINE__);
+        (void)note_error(e, __FILE__, __LINE__);
         (void)hipGetLastError();
         free_graph(g);
         return e == hipErrorOutOfMemory ? WFPG_ENOMEM : WFPG_EDEVICE;
@@ -99,7 +99,7 @@ wfpg_status wfpg_graph_launch(wfpg_bounce_graph *g, void *hip_stream)
     if (!g || !g->exec) return WFPG_EINVAL;
     const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
     if (e != hipSuccess) {
-        note_error(e, __FILE__, __LINE__);
+        (void)note_error(e, __FILE__, __LINE__);
         return WFPG_EDEVICE;
     }
     return WFPG_OK;

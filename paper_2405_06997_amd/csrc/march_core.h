@@ -20,6 +20,12 @@
 
 #include <stdint.h>
 
+// Exact crossing comparisons through FP64 products (full-rate on gfx950)
+// instead of 32x32->64-bit integer products.
+#ifndef WFPG_F64_PRODUCTS
+#define WFPG_F64_PRODUCTS 0
+#endif
+
 #if defined(__HIPCC__)
 #define WFPG_HD __host__ __device__ __forceinline__
 #define WFPG_UNROLL _Pragma("unroll")
@@ -100,8 +106,16 @@ WFPG_HD uint32_t upper_half(uint32_t M, uint32_t O, uint32_t aq, int sg, int j, 
     if (sg == 0) return O >= M ? 1u : 0u;
     int32_t dl = (int32_t)(M - O);
     if (sg < 0) dl = -dl;
+#if WFPG_F64_PRODUCTS
+    // |dl|, tn <= 2^30 and td, aq <= 2^23: each factor is a power of two or
+    // has at most 30 (resp. 23) significant bits, so each product has at most
+    // 53 and FP64 holds it exactly
+    const double x = (double)dl * (double)td, y = (double)tn * (double)aq;
+    const bool crossed = ((j <= ta) ? (x <= y) : (x < y)) || (sg > 0 && dl == 0);
+#else
     const int64_t lhs = (int64_t)dl * (int64_t)td - (int64_t)((uint64_t)tn * aq);
     const bool crossed = lhs < (int64_t)(j <= ta) || (sg > 0 && dl == 0);
+#endif
     return (crossed != (sg < 0)) ? 1u : 0u;
 }
 
@@ -212,9 +226,17 @@ WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, i
     // lowest-parameter exit axis, ties to the lower axis; the per-axis values
     // are picked with masks (a select between struct fields would be turned
     // into a private-memory table by the compiler)
+#if WFPG_F64_PRODUCTS
+    // products of a distance (<= 2^30) and a direction component (<= 2^23):
+    // at most 53 significant bits (see upper_half), exact in FP64
+    const uint32_t c1 = (double)dl1 * (double)s.aq0 < (double)dl0 * (double)s.aq1 ? 0xffffffffu : 0u;
+    const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
+    const uint32_t c2 = (double)dl2 * (double)Q01 < (double)D01 * (double)s.aq2 ? 0xffffffffu : 0u;
+#else
     const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
     const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
     const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
+#endif
     const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
     const int e = (int)((m1 & 1u) | (m2 & 2u));
     const uint32_t De = (dl2 & m2) | (D01 & ~m2);

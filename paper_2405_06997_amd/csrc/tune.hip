@@ -174,4 +174,26 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
     return WFPG_OK;
 }
 
+wfpg_status wfpg_autotune_n(wfpg_svo *svo, const float *pos, int64_t n, int32_t reps,
+                            float budget_ns_per_vertex, void *hip_stream, int32_t *N_out,
+                            wfpg_tile *tile_out, float *ms_per_N)
+{
+    if (!svo || !pos || n <= 0 || reps < 1 || !N_out || !(budget_ns_per_vertex >= 0.f))
+        return WFPG_EINVAL;
+    const int Ns[3] = {8, 16, 32};
+    float ms[3];
+    wfpg_tile tiles[3];
+    for (int k = 0; k < 3; ++k) {
+        const wfpg_status st = wfpg_autotune(svo, pos, n, Ns[k], reps, hip_stream, &tiles[k], &ms[k]);
+        if (st != WFPG_OK) return st;
+        if (ms_per_N) ms_per_N[k] = ms[k];
+    }
+    int pick = 0;   // the finest field whose time per vertex fits the budget, else the coarsest
+    for (int k = 2; k >= 0; --k)
+        if ((double)ms[k] * 1e6 / (double)n <= (double)budget_ns_per_vertex) { pick = k; break; }
+    *N_out = Ns[pick];
+    if (tile_out) *tile_out = tiles[pick];
+    return WFPG_OK;
+}
+
 }  // extern "C"

@@ -79,3 +79,18 @@ def test_autotune_and_tiles(env):
         w.set_tile(g, 16, 0, 5, 2)
     with pytest.raises(w.WfpgError):
         w.set_tile(g, 16, 4, 12, 2)
+
+
+def test_autotune_picks_finest_N_within_budget(env):
+    torch, dev, w, room, g, sp = env
+    q = torch.from_numpy(synth.area_points(room, 20000, 61)[0]).to(dev)
+    r = w.autotune_n(g, q, 1e9)
+    assert r["N"] == 32
+    ms = r["ms_per_N"]
+    assert ms[8] < ms[32]        # 16x the bins
+    assert w.autotune_n(g, q, 0.0)["N"] == 8
+    mid = (ms[16] * 1e6 / 20000) * 1.000001
+    pick = w.autotune_n(g, q, mid)["N"]   # re-timed: 16 unless timing noise moves a neighbour
+    assert pick in (8, 16, 32)
+    t = w.get_tile(g, r["N"])
+    assert t["waves_per_block"] >= 1
