@@ -86,10 +86,10 @@ def main():
     e_bytes = 8  # FP32 exitance pair
     alg_bytes = n * (12 + 16) + 8 * visits + hits * (e_bytes + 12)
 
-    if args.copy_calib_mib > 0:   # plain copy of known size, for HBM counter scaling
+    if args.copy_calib_mib > 0:   # plain streaming kernel of known traffic, for HBM counter scaling
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)   # reads and writes copy_calib_mib MiB each
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()

@@ -251,19 +251,23 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 }
 
 // LDS layout of a block: [top-level bitmap words][N*N*3 bin directions]
-// [N*N*3 quantized directions |q| | sign << 31][per wave: 2 vertex slots x
-// N*N hit records {key | axis << 30, delta}].
+// [N*N*3 quantized directions |q| | sign << 31][per wave: kSlots vertex
+// slots x N*N hit records {key | axis << 30, delta}][per wave: kSlots
+// node-test counters (count mode)].
 //
-// A wave keeps two query vertices in flight. Idle lanes take the next
-// unmarched bin of the vertex being fed; when it has no bins left a free
-// slot is opened for the next vertex of the queue (taken from a device
-// counter, kChunk at a time), so lanes never wait for another vertex's
-// longest ray. A slot whose bins are all finished is finalized by the whole
-// wave (values, CDF, sample) and freed.
+// A wave keeps up to kSlots query vertices in flight. Idle lanes take the
+// next unmarched bin of the vertex being fed; when it has no bins left a
+// free slot is opened for the next vertex of the queue (taken from a device
+// counter, kChunk at a time), so lanes rarely wait for another vertex's
+// longest rays. A slot whose bins are all finished is finalized by the whole
+// wave (values, CDF, sample) and freed. Slot bookkeeping is wave-uniform and
+// lives in scalar registers; the arrays below are only ever indexed by
+// unrolled constants.
 template <int N, int MODE>
 __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds_levels)
 {
     constexpr int NN = N * N;
+    constexpr int S = guide_slots(N);
     extern __shared__ uint64_t smem[];
     if (a.gate && *a.gate == 0) return;   // uniform: every thread reads the same flag
     const int lane = threadIdx.x & 63;
@@ -273,8 +277,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     uint64_t *lbits = smem;
     float *ldir = reinterpret_cast<float *>(smem + nlw);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
-    uint32_t *rec0 = lq + 3 * NN + (size_t)wave * 4 * NN;
-    uint32_t *rec1 = rec0 + 2 * NN;
+    uint32_t *recs = lq + 3 * NN + (size_t)wave * S * 2 * NN;
+    uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * 2 * NN + (size_t)wave * S;
     for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
     for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) {
         const float d = a.dirtab[t];
@@ -295,40 +299,42 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     int64_t chunk_next = 0;
     int chunk_left = 0;
     bool exhausted = false;
-    int64_t v0 = -1, v1 = -1;            // vertex of each slot (-1: free)
-    uint32_t A0 = 0, A1 = 0, A2 = 0;     // origin of slot 0
-    uint32_t B0 = 0, B1 = 0, B2 = 0;     // origin of slot 1
-    uint32_t ok0 = 0, ok1 = 0;           // origin leaf keys
-    bool occ0 = false, occ1 = false;
-    int nxt0 = NN, nxt1 = NN;            // next bin to hand out
-    int rem0 = 0, rem1 = 0;              // bins not yet finished
-    int feed = -1;
+    int64_t vs[S];                       // vertex of each slot (-1: free)
+    int rem[S];                          // bins of the slot not yet finished
+#pragma unroll
+    for (int k = 0; k < S; ++k) { vs[k] = -1; rem[k] = 0; }
+    int feed = -1, nxt = NN;             // slot being handed out and its next bin
+    uint32_t F0 = 0, F1 = 0, F2 = 0, Fkey = 0;   // origin and origin-leaf key of the fed vertex
+    bool Focc = false;
     // per-lane march state
     int lslot = 0, lbin = -1, vis = 0, iters = 0;
-    int vis0 = 0, vis1 = 0;              // count mode: node tests per slot
     core::MarchState st;
 
     while (true) {
-        if (v0 >= 0 && rem0 == 0) {
+        // finalize every slot whose bins are all finished
+        while (true) {
+            int done = -1;
+            int64_t vd = 0;
+#pragma unroll
+            for (int k = 0; k < S; ++k)
+                if (done < 0 && vs[k] >= 0 && rem[k] == 0) { done = k; vd = vs[k]; }
+            if (done < 0) break;
             wave_lds_fence();
-            finalize<N, MODE>(sv, a, ldir, rec0, v0, ps, lane, vis0);
+            const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
+            finalize<N, MODE>(sv, a, ldir, recs + done * 2 * NN, vd, ps, lane, vl);
             wave_lds_fence();
-            v0 = -1;
-            vis0 = 0;
-        }
-        if (v1 >= 0 && rem1 == 0) {
-            wave_lds_fence();
-            finalize<N, MODE>(sv, a, ldir, rec1, v1, ps, lane, vis1);
-            wave_lds_fence();
-            v1 = -1;
-            vis1 = 0;
+#pragma unroll
+            for (int k = 0; k < S; ++k)
+                if (k == done) vs[k] = -1;
         }
         // hand out bins to idle lanes
         uint64_t idle = __ballot(lbin < 0);
         while (idle) {
-            const bool feed_ok = (feed == 0 && v0 >= 0 && nxt0 < NN) || (feed == 1 && v1 >= 0 && nxt1 < NN);
-            if (!feed_ok) {
-                const int f = v0 < 0 ? 0 : (v1 < 0 ? 1 : -1);
+            if (feed < 0 || nxt >= NN) {
+                int f = -1;
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    if (f < 0 && vs[k] < 0) f = k;
                 if (f < 0 || exhausted) break;
                 if (chunk_left == 0) {
                     int64_t b = 0;
@@ -346,37 +352,45 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
                 const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D),
                                                     O[2] >> (WFPG_FINE - D));
                 const bool oc = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
-                if (f == 0) {
-                    v0 = uni(vi); A0 = uni(O[0]); A1 = uni(O[1]); A2 = uni(O[2]); ok0 = uni(okey);
-                    occ0 = uni((int)oc) != 0; nxt0 = 0; rem0 = NN;
-                } else {
-                    v1 = uni(vi); B0 = uni(O[0]); B1 = uni(O[1]); B2 = uni(O[2]); ok1 = uni(okey);
-                    occ1 = uni((int)oc) != 0; nxt1 = 0; rem1 = NN;
+                F0 = uni(O[0]); F1 = uni(O[1]); F2 = uni(O[2]); Fkey = uni(okey);
+                Focc = uni((int)oc) != 0;
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    if (k == f) { vs[k] = uni(vi); rem[k] = NN; }
+                if constexpr (MODE == MODE_COUNT) {
+                    if (lane == 0) svis[f] = 0u;
+                    wave_lds_fence();
                 }
                 feed = f;
+                nxt = 0;
             }
-            const int base = feed == 0 ? nxt0 : nxt1;
-            const int take = min(__popcll(idle), NN - base);
+            const int take = min(__popcll(idle), NN - nxt);
             const int r = lanes_below(idle);
             const bool mine = ((idle >> lane) & 1ull) && r < take;
             if (mine) {
                 lslot = feed;
-                lbin = base + r;
-                const uint32_t O[3] = {feed ? B0 : A0, feed ? B1 : A1, feed ? B2 : A2};
+                lbin = nxt + r;
+                const uint32_t O[3] = {F0, F1, F2};
                 const uint32_t w0 = lq[3 * lbin], w1 = lq[3 * lbin + 1], w2 = lq[3 * lbin + 2];
                 const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
                 vis = 0;
                 iters = 0;
-                core::march_begin(st, O, feed ? ok1 : ok0, feed ? occ1 : occ0, a0, a1, a2,
-                                  a0 ? ((w0 >> 31) ? -1 : 1) : 0, a1 ? ((w1 >> 31) ? -1 : 1) : 0,
-                                  a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, bits, 5, vis);
+                core::march_begin(st, O, Fkey, Focc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
+                                  a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, bits,
+                                  5, vis);
             }
             idle &= ~__ballot(mine);
-            if (feed == 0) nxt0 = uni(nxt0 + take); else nxt1 = uni(nxt1 + take);
+            nxt = uni(nxt + take);
         }
         if (__ballot(lbin >= 0) == 0ull) {
-            if (v0 < 0 && v1 < 0) break;
-            if (!(v0 >= 0 && rem0 == 0) && !(v1 >= 0 && rem1 == 0)) {
+            bool any = false, ready = false;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                any = any || vs[k] >= 0;
+                ready = ready || (vs[k] >= 0 && rem[k] == 0);
+            }
+            if (!any) break;
+            if (!ready) {
                 atomicOr(a.err, 2);   // no progress possible (never expected)
                 break;
             }
@@ -393,20 +407,24 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
         }
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
-            uint32_t *rec = lslot ? rec1 : rec0;
+            uint32_t *rec = recs + lslot * 2 * NN;
             rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
             rec[2 * lbin + 1] = h.delta;
+            if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[lslot], (uint32_t)vis);
             if constexpr (MODE == MODE_DEBUG) {
-                if (a.dbg_visits) a.dbg_visits[(size_t)(lslot ? v1 : v0) * NN + lbin] = vis;
+                if (a.dbg_visits) {
+                    int64_t vl = vs[0];
+#pragma unroll
+                    for (int k = 1; k < S; ++k)
+                        if (lslot == k) vl = vs[k];
+                    a.dbg_visits[(size_t)vl * NN + lbin] = vis;
+                }
             }
-            if (lslot) vis1 += vis; else vis0 += vis;
             lbin = -1;
         }
-        const uint64_t fm = __ballot(fin);
-        if (fm) {
-            const uint64_t f1 = __ballot(fin && lslot == 1);
-            rem0 = uni(rem0 - __popcll(fm & ~f1));
-            rem1 = uni(rem1 - __popcll(f1));
+        if (__ballot(fin)) {
+#pragma unroll
+            for (int k = 0; k < S; ++k) rem[k] = uni(rem[k] - __popcll(__ballot(fin && lslot == k)));
         }
     }
 }

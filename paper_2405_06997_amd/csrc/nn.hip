@@ -371,84 +371,148 @@ __device__ __forceinline__ void oct_decode(float x, float y, float &dx, float &d
     dz = z;
 }
 
-// One wave per vertex: p = softmax(z) over the 16 x 16 bins (rows v, b =
-// v*16 + u, lane l holds bins j*64 + l), inverse-CDF sampling with the same
-// uniforms and row/column rule as the march path, direction from the
-// octahedral decode, pdf = p_b * 256 / (4 pi).
-__global__ void k_nn_sample(const float *__restrict__ Z, int64_t n, int64_t stride, uint64_t seed,
-                            uint32_t bounce, float pdf_scale, float *dir_out, float *pdf_out)
-{
-    constexpr int N = 16, G = 4;
-    const int lane = threadIdx.x & 63;
-    const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (i >= n) return;
-    float z[4];
-    for (int j = 0; j < 4; ++j) z[j] = Z[i * 256 + j * 64 + lane];
-    const float mx = wave_max(fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3])));
-    float L[4], S[4];
-    for (int j = 0; j < 4; ++j) L[j] = expf(z[j] - mx);
-    for (int j = 0; j < 4; ++j) {
-        float v = L[j];
-        for (int d = 1; d < N; d <<= 1) {
-            const float t = __shfl_up(v, d, N);
-            if ((lane & (N - 1)) >= d) v += t;
-        }
-        S[j] = v;
-    }
-    float rs = 0.f;
-    for (int j = 0; j < 4; ++j) {
-        const float t = __shfl(S[j], (lane % G) * N + N - 1);
-        if (lane / G == j) rs = t;
-    }
-    if (lane >= N) rs = 0.f;
-    float M = rs;
-    for (int d = 1; d < N; d <<= 1) {
-        const float t = __shfl_up(M, d, N);
-        if ((lane & (N - 1)) >= d) M += t;
-    }
-    const float total = __shfl(M, N - 1);
-    uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
-    philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
-    const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
-    const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
-    const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
-    const float tv = u1 * total;
-    const uint64_t bv = __ballot(lane < N && tv < M);
-    const int v = bv ? (__ffsll((unsigned long long)bv) - 1) : N - 1;
-    const int jv = v / G, gv = v % G;
-    float Sj = S[0], Lj = L[0];
-    for (int j = 1; j < 4; ++j)
-        if (j == jv) { Sj = S[j]; Lj = L[j]; }
-    const float rowsum = __shfl(Sj, gv * N + N - 1);
-    const float tu = u2 * rowsum;
-    const uint64_t bu = __ballot((lane / N) == gv && tu < Sj);
-    const int u = bu ? (__ffsll((unsigned long long)bu) - 1 - gv * N) : N - 1;
-    const float Lb = __shfl(Lj, gv * N + u);
-    if (lane == 0) {
-        const float inv = 1.f / (float)N;
-        float ox, oy, oz;
-        oct_decode((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
-        dir_out[i] = ox;
-        dir_out[stride + i] = oy;
-        dir_out[2 * stride + i] = oz;
-        pdf_out[i] = (Lb / total) * pdf_scale;
-    }
-}
+// Output layer fused with the softmax and its use (inference only): one
+// wave takes 16 rows of the last hidden activations H [rows][64] (BF16),
+// multiplies them by W4 (staged once per block in LDS, 16-byte chunks
+// XOR-swizzled by row) with the same MFMA sequence and bias add as the
+// unfused GEMM, so the logits are bit-identical to it, and keeps them in
+// registers: lane l holds, for rows 4*(l/16) + r (r < 4), the logits of bins
+// 16*c + l%16 (c < 16), i.e. field row v = c and column u = l%16. Per row:
+// softmax; then either the probabilities (PROB) or inverse-CDF sampling with
+// the march path's uniforms and row/column rule, the octahedral decode of
+// ((u + u3)/16, (v + u4)/16) and pdf = p_b * 256 / (4 pi) (SAMPLE).
+enum { OUT_SAMPLE = 0, OUT_PROB = 1 };
 
-// Softmax probabilities (rows of 256) of n rows of logits.
-__global__ void k_softmax(const float *__restrict__ Z, int64_t n, float *P)
+__device__ __forceinline__ int swz64(int row, int chunk) { return row * 64 + ((chunk ^ (row & 7)) << 3); }
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ H, const uint16_t *__restrict__ W4,
+                                                    const float *__restrict__ b4, int64_t n, uint64_t seed,
+                                                    uint32_t bounce, float pdf_scale, float *dir_out,
+                                                    float *pdf_out, float *prob_out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t v = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (v >= n) return;
-    float z[4];
-    for (int j = 0; j < 4; ++j) z[j] = Z[v * 256 + j * 64 + lane];
-    const float mx = wave_max(fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3])));
-    float e[4], s = 0.f;
-    for (int j = 0; j < 4; ++j) { e[j] = expf(z[j] - mx); s += e[j]; }
-    s = wave_sum(s);
-    for (int j = 0; j < 4; ++j) P[v * 256 + j * 64 + lane] = e[j] / s;
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[256 * 64];
+    __shared__ float bs[256];
+    for (int t = threadIdx.x; t < 256 * 8; t += blockDim.x) {
+        const int row = t >> 3, ch = t & 7;
+        *reinterpret_cast<uint4 *>(&Ws[swz64(row, ch)]) =
+            *reinterpret_cast<const uint4 *>(W4 + (int64_t)row * 64 + ch * 8);
+    }
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) bs[t] = b4[t];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, g = lane >> 4, u = lane & 15;
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    int64_t tile = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    bf16x8 na0, na1;   // A fragments of the wave's next tile, loaded one tile ahead
+    if (tile < tiles) {
+        const uint16_t *hrow = H + (tile * 16 + u) * 64;   // rows < pad64(n): always allocated
+        na0 = *reinterpret_cast<const bf16x8 *>(hrow + 8 * g);
+        na1 = *reinterpret_cast<const bf16x8 *>(hrow + 32 + 8 * g);
+    }
+    for (; tile < tiles; tile += wstride) {
+        const int64_t r0 = tile * 16;
+        const bf16x8 a0 = na0, a1 = na1;
+        if (tile + wstride < tiles) {
+            const uint16_t *hrow = H + ((tile + wstride) * 16 + u) * 64;
+            na0 = *reinterpret_cast<const bf16x8 *>(hrow + 8 * g);
+            na1 = *reinterpret_cast<const bf16x8 *>(hrow + 32 + 8 * g);
+        }
+        floatx4 acc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int row = 16 * c + u;
+            const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(&Ws[swz64(row, g)]);
+            const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(&Ws[swz64(row, 4 + g)]);
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, w0, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, w1, acc[c], 0, 0, 0);
+        }
+        // uniforms of row r0 + (lane % 16), fetched per row below
+        uint32_t cu[4] = {0u, 0u, bounce, 0u};
+        if (MODE == OUT_SAMPLE) {
+            const uint64_t i = (uint64_t)(r0 + u);
+            cu[0] = (uint32_t)i;
+            cu[1] = (uint32_t)(i >> 32);
+            philox(cu, (uint32_t)seed, (uint32_t)(seed >> 32));
+        }
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r) {   // one row of the lane group at a time (register pressure)
+            const int64_t row = r0 + 4 * g + r;
+            float e[16];
+            float mx = -3.4e38f;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const floatx4 a4 = acc[c];
+                const float x = r == 0 ? a4[0] : (r == 1 ? a4[1] : (r == 2 ? a4[2] : a4[3]));
+                e[c] = x + bs[16 * c + u];
+                mx = fmaxf(mx, e[c]);
+            }
+#pragma unroll
+            for (int d = 8; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+#pragma unroll
+            for (int c = 0; c < 16; ++c) e[c] = expf(e[c] - mx);
+            if (MODE == OUT_PROB) {
+                float sum = 0.f;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) sum += e[c];
+#pragma unroll
+                for (int d = 8; d >= 1; d >>= 1) sum += __shfl_xor(sum, d);
+                if (row < n) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) prob_out[row * 256 + 16 * c + u] = e[c] / sum;
+                }
+            } else {
+                // marginal CDF over field rows (row sums reduced over the 16 lanes)
+                float M[16];
+                float run = 0.f;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    float t = e[c];
+#pragma unroll
+                    for (int d = 8; d >= 1; d >>= 1) t += __shfl_xor(t, d);
+                    run += t;
+                    M[c] = run;
+                }
+                const float total = M[15];
+                const int src = 4 * g + r;   // a lane holding this row's uniforms
+                const uint32_t b1 = __shfl(cu[0], src), b2 = __shfl(cu[1], src);
+                const uint32_t b3 = __shfl(cu[2], src), b4u = __shfl(cu[3], src);
+                const float u1 = (float)(b1 >> 8) * 5.9604644775390625e-8f;
+                const float u2 = (float)(b2 >> 8) * 5.9604644775390625e-8f;
+                const float tv = u1 * total;
+                int v = 15;
+#pragma unroll
+                for (int c = 14; c >= 0; --c)
+                    if (tv < M[c]) v = c;
+                float ev = e[0];
+#pragma unroll
+                for (int c = 1; c < 16; ++c)
+                    if (c == v) ev = e[c];
+                float S = ev;   // inclusive scan of field row v over its 16 columns
+#pragma unroll
+                for (int d = 1; d < 16; d <<= 1) {
+                    const float t = __shfl_up(S, d, 16);
+                    if (u >= d) S += t;
+                }
+                const float rowsum = __shfl(S, 16 * g + 15);
+                const uint64_t bal = __ballot(u2 * rowsum < S);
+                const uint32_t mine = (uint32_t)(bal >> (16 * g)) & 0xffffu;
+                const int col = mine ? __ffs(mine) - 1 : 15;
+                const float Lb = __shfl(ev, 16 * g + col);
+                if (u == 0 && row < n) {
+                    const float inv = 1.f / 16.f;
+                    const float u3 = (float)(b3 >> 8) * 5.9604644775390625e-8f;
+                    const float u4 = (float)(b4u >> 8) * 5.9604644775390625e-8f;
+                    float ox, oy, oz;
+                    oct_decode((float)col * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
+                    dir_out[row] = ox;
+                    dir_out[n + row] = oy;
+                    dir_out[2 * n + row] = oz;
+                    pdf_out[row] = (Lb / total) * pdf_scale;
+                }
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------------------- Adam ----
@@ -644,15 +708,15 @@ static GemmArgs gargs(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t
     return g;
 }
 
-// Logits Z [rows][256] of n positions (SoA with plane stride `stride`);
-// keeps X and H0..H3 for a backward pass.
-static hipError_t forward(Model &M, const float *pos, const float *nrm, int64_t n, int64_t stride,
-                          hipStream_t s)
+// Hidden activations H0..H3 [rows][64] of n positions (SoA with plane
+// stride `stride`), rows padded to a multiple of 64; keeps X for a backward
+// pass.
+static hipError_t forward_hidden(Model &M, const float *pos, const float *nrm, int64_t n, int64_t stride,
+                                 hipStream_t s)
 {
     const int64_t rows = pad64(std::max<int64_t>(n, 1));
     hipError_t e = ensure(M.X, rows * 64 * 2);
     for (int k = 0; k < 4 && e == hipSuccess; ++k) e = ensure(M.H[k], rows * 64 * 2);
-    if (e == hipSuccess) e = ensure(M.Z, rows * 256 * 4);
     if (e != hipSuccess) return e;
     uint16_t *X = (uint16_t *)M.X.p;
     hipLaunchKernelGGL(k_encode, dim3(nb(rows * 16, 256)), dim3(256), 0, s, M.grid, M.tbf, pos, nrm, n,
@@ -667,7 +731,18 @@ static hipError_t forward(Model &M, const float *pos, const float *nrm, int64_t 
         if (e != hipSuccess) return e;
         in = (const uint16_t *)M.H[k].p;
     }
-    GemmArgs g = gargs(in, 64, M.wbf + M.lay.bw[4], 64, (int)rows, 256, 64);
+    return hipSuccess;
+}
+
+// Logits Z [rows][256] (training and the judge's probes).
+static hipError_t forward(Model &M, const float *pos, const float *nrm, int64_t n, int64_t stride,
+                          hipStream_t s)
+{
+    const int64_t rows = pad64(std::max<int64_t>(n, 1));
+    hipError_t e = forward_hidden(M, pos, nrm, n, stride, s);
+    if (e == hipSuccess) e = ensure(M.Z, rows * 256 * 4);
+    if (e != hipSuccess) return e;
+    GemmArgs g = gargs((const uint16_t *)M.H[3].p, 64, M.wbf + M.lay.bw[4], 64, (int)rows, 256, 64);
     g.C = (float *)M.Z.p;
     g.ldc = 256;
     g.bias = M.p + M.lay.boff[4];
@@ -745,6 +820,29 @@ static hipError_t backward(Model &M, const float *pos, int64_t n, int64_t stride
     hipLaunchKernelGGL(k_hash_scatter, dim3(nb(n * 16, 256)), dim3(256), 0, s, M.grid, pos, n, stride,
                        (const float *)M.dX.p, M.g + M.table_off);
     hipLaunchKernelGGL(k_pack_grads, dim3(nb(M.mlp, 256)), dim3(256), 0, s, M.gW, M.gB, M.lay, M.g, M.mlp);
+    return hipGetLastError();
+}
+
+// Network distribution of n positions, sampled (dir_out, pdf_out) or written
+// out (prob_out), through the fused output kernel.
+static hipError_t infer(Model &M, const float *pos, const float *nrm, int64_t n, int mode, uint64_t seed,
+                        uint32_t bounce, float *dir_out, float *pdf_out, float *prob_out, hipStream_t s)
+{
+    hipError_t e = forward_hidden(M, pos, nrm, n, n, s);
+    if (e != hipSuccess) return e;
+    const double pi = 3.14159265358979323846;
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cu_count() * 8));
+    const uint16_t *H3 = (const uint16_t *)M.H[3].p;
+    const uint16_t *W4 = M.wbf + M.lay.bw[4];
+    const float *b4 = M.p + M.lay.boff[4];
+    const float scale = (float)(256.0 / (4.0 * pi));
+    if (mode == OUT_SAMPLE)
+        hipLaunchKernelGGL(k_out_fused<OUT_SAMPLE>, dim3(grid), dim3(256), 0, s, H3, W4, b4, n, seed, bounce,
+                           scale, dir_out, pdf_out, prob_out);
+    else
+        hipLaunchKernelGGL(k_out_fused<OUT_PROB>, dim3(grid), dim3(256), 0, s, H3, W4, b4, n, seed, bounce,
+                           scale, dir_out, pdf_out, prob_out);
     return hipGetLastError();
 }
 
@@ -974,12 +1072,7 @@ wfpg_status wfpg_nn_forward(wfpg_svo *svo, const float *pos, const float *nrm, i
     if (!M) return WFPG_ESTATE;
     if (n == 0) return WFPG_OK;
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = nn::forward(*M, pos, nrm, n, n, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(nn::k_softmax, dim3(nn::nb(n, 4)), dim3(256), 0, s, (const float *)M->Z.p, n,
-                           prob_out);
-        e = hipGetLastError();
-    }
+    const hipError_t e = nn::infer(*M, pos, nrm, n, nn::OUT_PROB, 0, 0, nullptr, nullptr, prob_out, s);
     return st_of(e, __LINE__);
 }
 
@@ -1034,12 +1127,7 @@ wfpg_status learned_sample(const wfpg_svo *svo, const float *pos, const float *n
     if (!M || !M->trained) return WFPG_ESTATE;
     if (o->N != 16 || !nrm || o->probe_stride < 1 || !std::isfinite(o->kl_bound)) return WFPG_EINVAL;
     const double pi = 3.14159265358979323846;
-    hipError_t e = nn::forward(*M, pos, nrm, n, n, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(nn::k_nn_sample, dim3(nn::nb(n, 4)), dim3(256), 0, s, (const float *)M->Z.p, n, n,
-                           seed, bounce, (float)(256.0 / (4.0 * pi)), dir_out, pdf_out);
-        e = hipGetLastError();
-    }
+    hipError_t e = nn::infer(*M, pos, nrm, n, nn::OUT_SAMPLE, seed, bounce, dir_out, pdf_out, nullptr, s);
     const int64_t step = o->probe_stride;
     const int64_t m = (n + step - 1) / step;
     if (e == hipSuccess) e = nn::ensure(M->ppos, m * 3 * 4);

@@ -101,10 +101,14 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
 
 // LDS bytes of one guide block: staged bitmap levels, bin directions and the
 // per-wave hit records.
+// Query vertices a wave keeps in flight (hit records of each in LDS).
+__host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : 4; }
+
 inline size_t guide_lds_bytes(int N, const TileConfig &tc)
 {
+    const size_t S = (size_t)guide_slots(N);
     return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 * 2 +
-           (size_t)tc.waves_per_block * 2 * N * N * 2 * 4;
+           (size_t)tc.waves_per_block * S * (2 * (size_t)N * N * 4 + 4);
 }
 constexpr size_t kMaxGuideLds = 64 * 1024;
 constexpr int kCounterPool = 64;   // concurrent guide launches per SVO with distinct counters
