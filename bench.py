@@ -34,7 +34,10 @@ def parse():
     ap.add_argument("--N", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep the guide kernel's launch shape first (its launches then show up in a "
+                         "kernel trace of this command); default: the library's default tile")
+    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
     ap.add_argument("--only-march", action="store_true",
@@ -75,7 +78,7 @@ def main():
     p_out = torch.empty((n,), device=dev)
 
     # launch shape: autotuned on an evenly strided quarter-million-vertex subset
-    if not args.no_autotune:
+    if args.autotune and not args.no_autotune:
         sub = pos[:, :: max(1, n // 262144)].contiguous()
         w.autotune(svo, sub, args.N, reps=3)
     tile = w.get_tile(svo, args.N)

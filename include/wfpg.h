@@ -263,7 +263,8 @@ typedef struct {
 wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out);
 
 /* Force a tile for resolution N (EINVAL if it exceeds the kernel's limits:
- * 1..16 waves, 1..depth+1 levels, 1..64 blocks per CU, 64 KiB of LDS). */
+ * 1..16 waves, 1..depth+1 levels, 1..64 blocks per CU, the device's LDS
+ * per workgroup: 160 KiB on MI355X). */
 wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile);
 
 /* Sweep candidate tiles for resolution N on the given DEVICE queue pos

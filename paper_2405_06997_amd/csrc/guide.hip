@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "march_core.h"
 #include "wfpg_internal.h"
@@ -122,16 +123,31 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
 #pragma unroll
     for (int j = 0; j < BPL; ++j) {
         const int b = j * 64 + lane;
-        const uint32_t r = rec[2 * b];
         float val = fmt == WFPG_FP32 ? a.eps : round16(a.eps, fmt);
-        if (r != kMissRec) {
-            const int axis = (int)(r >> 30);
-            const uint32_t key = r & 0x3fffffffu;
-            const float dx = ldir[3 * b], dy = ldir[3 * b + 1], dz = ldir[3 * b + 2];
-            const float dsel = axis == 0 ? dx : (axis == 1 ? dy : dz);
-            const int k = core::footprint_levels(rec[2 * b + 1], fabsf(dsel), D, a.omega);
-            const int lf = D - k;
-            const uint32_t node = key >> (3 * k);
+        bool hit;
+        int lf = 0, k = 0, axis = 0;
+        uint32_t node = 0, key = 0;
+        const float dx = ldir[3 * b], dy = ldir[3 * b + 1], dz = ldir[3 * b + 2];
+        if constexpr (MODE == MODE_DEBUG) {   // raw record: key | axis << 30, |B - O|
+            const uint32_t r = rec[2 * b];
+            hit = r != kMissRec;
+            if (hit) {
+                axis = (int)(r >> 30);
+                key = r & 0x3fffffffu;
+                const float dsel = axis == 0 ? dx : (axis == 1 ? dy : dz);
+                k = core::footprint_levels(rec[2 * b + 1], fabsf(dsel), D, a.omega);
+                lf = D - k;
+                node = key >> (3 * k);
+            }
+        } else {                              // footprint node: 1 << 3*lf | key (0: miss)
+            const uint32_t r = rec[b];
+            hit = r != 0u;
+            if (hit) {
+                lf = (31 - __builtin_clz(r)) / 3;
+                node = r ^ (1u << (3 * lf));
+            }
+        }
+        if (hit) {
             const uint32_t wi = woff(lf) + (node >> 6);
             const uint64_t w = sv.bits[wi];
             const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
@@ -252,8 +268,10 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 
 // LDS layout of a block: [top-level bitmap words][N*N*3 bin directions]
 // [N*N*3 quantized directions |q| | sign << 31][per wave: kSlots vertex
-// slots x N*N hit records {key | axis << 30, delta}][per wave: kSlots
-// node-test counters (count mode)].
+// slots x N*N hit records][per wave: kSlots node-test counters (count
+// mode)]. A hit record is the node the cone footprint selects, as
+// 1 << 3*level | key (0 for a miss); the debug mode keeps the raw traversal
+// record {key | axis << 30, |B - O|} instead.
 //
 // A wave keeps up to kSlots query vertices in flight. Idle lanes take the
 // next unmarched bin of the vertex being fed; when it has no bins left a
@@ -277,8 +295,9 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     uint64_t *lbits = smem;
     float *ldir = reinterpret_cast<float *>(smem + nlw);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
-    uint32_t *recs = lq + 3 * NN + (size_t)wave * S * 2 * NN;
-    uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * 2 * NN + (size_t)wave * S;
+    constexpr int RW = guide_rec_words(MODE);
+    uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
+    uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * RW * NN + (size_t)wave * S;
     for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
     for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) {
         const float d = a.dirtab[t];
@@ -321,7 +340,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
             if (done < 0) break;
             wave_lds_fence();
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
-            finalize<N, MODE>(sv, a, ldir, recs + done * 2 * NN, vd, ps, lane, vl);
+            finalize<N, MODE>(sv, a, ldir, recs + done * RW * NN, vd, ps, lane, vl);
             wave_lds_fence();
 #pragma unroll
             for (int k = 0; k < S; ++k)
@@ -407,9 +426,20 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
         }
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
-            uint32_t *rec = recs + lslot * 2 * NN;
-            rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
-            rec[2 * lbin + 1] = h.delta;
+            uint32_t *rec = recs + lslot * RW * NN;
+            if constexpr (MODE == MODE_DEBUG) {
+                rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
+                rec[2 * lbin + 1] = h.delta;
+            } else {
+                // cone footprint (Eq. 7) decided here: the record is the node it selects
+                uint32_t rv = 0u;
+                if (res == core::STEP_HIT) {
+                    const float dsel = ldir[3 * lbin + h.axis];
+                    const int k = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
+                    rv = (1u << (3 * (D - k))) | (h.key >> (3 * k));
+                }
+                rec[lbin] = rv;
+            }
             if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[lslot], (uint32_t)vis);
             if constexpr (MODE == MODE_DEBUG) {
                 if (a.dbg_visits) {
@@ -441,11 +471,32 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     GuideArgs a = a0;
     if (!a.queue_ctr)
         a.queue_ctr = svo->d_ctr + (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
-    const int W = tc.waves_per_block;
+    TileConfig t = tc;   // debug records are twice as large: shrink the workgroup if needed
+    while (t.waves_per_block > 1 && guide_lds_bytes(N, t, mode) > guide_max_lds()) --t.waves_per_block;
+    const int W = t.waves_per_block;
     const int64_t want = a.n_dev ? INT64_MAX : ((a.n + kChunk - 1) / kChunk + W - 1) / W;
-    const int64_t cap = (int64_t)device_cu_count() * tc.blocks_per_cu;
+    const int64_t cap = (int64_t)device_cu_count() * t.blocks_per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    const size_t lds = guide_lds_bytes(N, tc);
+    const size_t lds = guide_lds_bytes(N, t, mode);
+    if (lds > guide_max_lds()) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {   // opt in to the device's whole LDS once per kernel
+        static std::atomic<bool> opted[5];
+        const int m = mode < 0 || mode > 4 ? MODE_DEBUG : mode;
+        if (!opted[m].load()) {
+            const void *fn = nullptr;
+            switch (m) {
+            case MODE_SAMPLE: fn = (const void *)&k_guide<N, MODE_SAMPLE>; break;
+            case MODE_PDF: fn = (const void *)&k_guide<N, MODE_PDF>; break;
+            case MODE_EVAL: fn = (const void *)&k_guide<N, MODE_EVAL>; break;
+            case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT>; break;
+            default: fn = (const void *)&k_guide<N, MODE_DEBUG>; break;
+            }
+            const hipError_t e =
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)guide_max_lds());
+            if (e != hipSuccess) return e;
+            opted[m].store(true);
+        }
+    }
     const dim3 blk(64 * W);
     const wfpg::SvoView v = svo->view();
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.queue_ctr);

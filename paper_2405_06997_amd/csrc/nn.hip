@@ -251,44 +251,60 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// One wave per row: p = softmax(z); target t = march pdf * (4 pi / 256)
-// (renormalized); dZ = (p - t) * inv_b (BF16 for the products, FP32 summed
-// into the output-bias gradient); loss += -sum t ln p * inv_b. Rows >= n of
-// the padded batch get dZ = 0.
-__global__ void k_softmax_xent(const float *__restrict__ Z, const float *__restrict__ tpdf, int64_t n,
-                               int64_t rows, float inv_b, uint16_t *dZ, float *db, float *loss)
+// One wave per row (grid-stride over the padded batch): p = softmax(z);
+// target t = march pdf renormalized to sum 1; dZ = (p - t) * inv_b (BF16 for
+// the products; rows >= n get 0); loss = -sum t ln p * inv_b. The output-bias
+// gradient (FP32, unrounded) and the loss are summed per lane across the
+// wave's rows, then across the block in LDS, and added with one atomic per
+// bin and block.
+__global__ void __launch_bounds__(256) k_softmax_xent(const float *__restrict__ Z, const float *__restrict__ tpdf,
+                                                      int64_t n, int64_t rows, float inv_b, uint16_t *dZ,
+                                                      float *db, float *loss)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t v = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (v >= rows) return;
-    if (v >= n) {
-        for (int j = 0; j < 4; ++j) dZ[v * 256 + j * 64 + lane] = 0;
-        return;
+    __shared__ float sdb[4][256];
+    __shared__ float sloss[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    float lacc = 0.f;
+    const int64_t wstride = (int64_t)gridDim.x * 4;
+    for (int64_t v = blockIdx.x * 4 + wave; v < rows; v += wstride) {
+        if (v >= n) {
+            for (int j = 0; j < 4; ++j) dZ[v * 256 + j * 64 + lane] = 0;
+            continue;
+        }
+        float z[4], t[4];
+        for (int j = 0; j < 4; ++j) {
+            z[j] = Z[v * 256 + j * 64 + lane];
+            t[j] = tpdf[v * 256 + j * 64 + lane];
+        }
+        const float mx = wave_max(fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3])));
+        float e[4], s = 0.f, ts = 0.f;
+        for (int j = 0; j < 4; ++j) {
+            e[j] = expf(z[j] - mx);
+            s += e[j];
+            ts += t[j];
+        }
+        s = wave_sum(s);
+        ts = wave_sum(ts);
+        const float ls = logf(s);
+        float l = 0.f;
+        for (int j = 0; j < 4; ++j) {
+            const float p = e[j] / s, tt = t[j] / ts;
+            const float g = (p - tt) * inv_b;
+            dZ[v * 256 + j * 64 + lane] = f2bf(g);
+            acc[j] += g;
+            if (tt > 0.f) l -= tt * (z[j] - mx - ls);
+        }
+        lacc += l;
     }
-    float z[4], t[4];
-    for (int j = 0; j < 4; ++j) {
-        z[j] = Z[v * 256 + j * 64 + lane];
-        t[j] = tpdf[v * 256 + j * 64 + lane];
-    }
-    const float mx = wave_max(fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3])));
-    float e[4], s = 0.f, ts = 0.f;
-    for (int j = 0; j < 4; ++j) {
-        e[j] = expf(z[j] - mx);
-        s += e[j];
-        ts += t[j];
-    }
-    s = wave_sum(s);
-    ts = wave_sum(ts);
-    float l = 0.f;
-    for (int j = 0; j < 4; ++j) {
-        const float p = e[j] / s, tt = t[j] / ts;
-        const float g = (p - tt) * inv_b;
-        dZ[v * 256 + j * 64 + lane] = f2bf(g);
-        unsafeAtomicAdd(&db[j * 64 + lane], g);
-        if (tt > 0.f) l -= tt * (z[j] - mx - logf(s));
-    }
-    l = wave_sum(l);
-    if (lane == 0) unsafeAtomicAdd(loss, l * inv_b);
+    for (int j = 0; j < 4; ++j) sdb[wave][j * 64 + lane] = acc[j];
+    lacc = wave_sum(lacc);
+    if (lane == 0) sloss[wave] = lacc;
+    __syncthreads();
+    const int b = threadIdx.x;   // 256 threads: one output bin each
+    const float sum = (sdb[0][b] + sdb[1][b]) + (sdb[2][b] + sdb[3][b]);
+    unsafeAtomicAdd(&db[b], sum);
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, ((sloss[0] + sloss[1]) + (sloss[2] + sloss[3])) * inv_b);
 }
 
 // KL(p_march || p_net) of probe rows: tpdf (march pdfs), Z (net logits of the
@@ -765,7 +781,8 @@ static hipError_t backward(Model &M, const float *pos, int64_t n, int64_t stride
     if (e == hipSuccess) e = fill(M.d_loss, 1, 0.f, s);
     if (e != hipSuccess) return e;
     uint16_t *dZ = (uint16_t *)M.dZ.p;
-    hipLaunchKernelGGL(k_softmax_xent, dim3(nb(rows, 4)), dim3(256), 0, s, (const float *)M.Z.p, tpdf, n,
+    hipLaunchKernelGGL(k_softmax_xent, dim3((unsigned)std::min<int64_t>(nb(rows, 4), (int64_t)device_cu_count() * 4)),
+                       dim3(256), 0, s, (const float *)M.Z.p, tpdf, n,
                        rows, 1.f / (float)n, dZ, M.gB + 4 * kH, M.d_loss);
     const int ksplit = 2048;   // vertices per split-K chunk of the weight gradients
     const int splits = (int)((rows + ksplit - 1) / ksplit);

@@ -30,21 +30,37 @@ Key key_of(const wfpg_svo *svo, int N)
 TileConfig default_tile(int N, int depth)
 {
     TileConfig t;
-    t.waves_per_block = 4;
-    t.lds_levels = 6;
+    t.waves_per_block = 4;   // the tuner's usual pick for the frame-scale room at N = 16
+    t.lds_levels = 5;
     t.blocks_per_cu = N == 32 ? 4 : 8;
     return legalize_tile(t, N, depth);
 }
 
 }  // namespace
 
+size_t guide_max_lds()
+{
+    static std::mutex mu;
+    static std::map<int, size_t> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 64 * 1024;
+    cache[dev] = (size_t)v;
+    return (size_t)v;
+}
+
 TileConfig legalize_tile(TileConfig t, int N, int depth)
 {
     t.waves_per_block = std::min(std::max(t.waves_per_block, 1), 16);
     t.blocks_per_cu = std::min(std::max(t.blocks_per_cu, 1), 64);
     t.lds_levels = std::min(std::max(t.lds_levels, 1), std::min(7, depth + 1));
-    while (t.lds_levels > 1 && guide_lds_bytes(N, t) > kMaxGuideLds) --t.lds_levels;
-    while (t.waves_per_block > 1 && guide_lds_bytes(N, t) > kMaxGuideLds) --t.waves_per_block;
+    while (t.lds_levels > 1 && guide_lds_bytes(N, t) > guide_max_lds()) --t.lds_levels;
+    while (t.waves_per_block > 1 && guide_lds_bytes(N, t) > guide_max_lds()) --t.waves_per_block;
     return t;
 }
 
@@ -81,7 +97,7 @@ wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile)
     t.blocks_per_cu = tile->blocks_per_cu;
     if (t.waves_per_block < 1 || t.waves_per_block > 16 || t.blocks_per_cu < 1 ||
         t.blocks_per_cu > 64 || t.lds_levels < 1 || t.lds_levels > svo->depth + 1 ||
-        guide_lds_bytes(N, t) > kMaxGuideLds)
+        guide_lds_bytes(N, t) > guide_max_lds())
         return WFPG_EINVAL;
     std::lock_guard<std::mutex> g(g_mu);
     g_cache[key_of(svo, N)] = t;
@@ -115,9 +131,9 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
         a.err = svo->d_err;
         a.dir_out = d_dir;
         a.pdf_out = d_pdf;
-        const int waves[] = {1, 2, 4, 8};
+        const int waves[] = {1, 2, 4, 8, 16};
         const int levels[] = {5, 6, 7};
-        const int bpcu[] = {2, 4, 8, 16};
+        const int bpcu[] = {1, 2, 4, 8, 16};
         std::vector<TileConfig> cand;
         for (int w : waves)
             for (int l : levels)
@@ -126,7 +142,7 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
                     t.waves_per_block = w;
                     t.lds_levels = std::min(l, svo->depth + 1);
                     t.blocks_per_cu = b;
-                    if (guide_lds_bytes(N, t) > kMaxGuideLds) continue;
+                    if (guide_lds_bytes(N, t) > guide_max_lds() || w * b > 32) continue;
                     bool dup = false;
                     for (const TileConfig &c : cand)
                         dup = dup || (c.waves_per_block == t.waves_per_block &&

@@ -104,13 +104,18 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
 // Query vertices a wave keeps in flight (hit records of each in LDS).
 __host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : 4; }
 
-inline size_t guide_lds_bytes(int N, const TileConfig &tc)
+// 32-bit words of one bin's hit record: the debug mode keeps the raw
+// traversal record, every other mode the footprint node only.
+__host__ __device__ constexpr int guide_rec_words(int mode) { return mode == MODE_DEBUG ? 2 : 1; }
+
+inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE)
 {
     const size_t S = (size_t)guide_slots(N);
     return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 * 2 +
-           (size_t)tc.waves_per_block * S * (2 * (size_t)N * N * 4 + 4);
+           (size_t)tc.waves_per_block * S * ((size_t)guide_rec_words(mode) * N * N * 4 + 4);
 }
-constexpr size_t kMaxGuideLds = 64 * 1024;
+// LDS a guide workgroup may use on the current device (all modes but debug).
+size_t guide_max_lds();
 constexpr int kCounterPool = 64;   // concurrent guide launches per SVO with distinct counters
 
 // Tile chosen for (device, N, depth, format): the autotuned one if present.
