@@ -25,6 +25,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 
+# HBM bytes per launch of k_guide<16, SAMPLE> on this workload, from two
+# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) each scaled by what the same
+# counter reads for a 1 GiB streaming kernel; the record is
+# profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
+# sources it was taken on and the default tile, and is reported only for them.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "6e969df22c7b3db06314bccb08b034582d75544782d18bdfadce8c570acb0ca4",
+    "N": 16,
+    "tile": {"waves_per_block": 4, "lds_levels": 5, "blocks_per_cu": 8},
+    "bytes_per_launch": 4721501901,
+}
+KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h"]
+
+
+def measured_traffic(N, tile):
+    """The counter-derived traffic if it still describes the kernel that runs."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_06997_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m = MEASURED_TRAFFIC
+    if h.hexdigest() != m["sources_sha256"] or N != m["N"] or tile != m["tile"]:
+        return None
+    return m["bytes_per_launch"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,8 +66,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
-    ap.add_argument("--only-march", action="store_true",
-                    help="skip the learned, batching and precision sections (profiling runs)")
+    ap.add_argument("--sections", default="learned,batching,precision",
+                    help="comma-separated extra sections after the headline march step "
+                         "(learned, batching, precision; empty for none)")
+    ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
     ap.add_argument("--train-pairs", type=int, default=50_000_000,
                     help="(vertex, march pdf) pairs the learned model is trained on")
     ap.add_argument("--budget-ns", type=float, default=30.0,
@@ -120,6 +148,7 @@ def main():
 
     gs_avg = float(np.mean(gs_ms))
     achieved = alg_bytes / (gs_avg * 1e-3) / 1e9
+    traffic = measured_traffic(args.N, tile)
     out = {
         "metric": "guided samples/sec (PDF build+sample) on 1 MI355X; MLP vs SVO march at KL<=0.05",
         "value": n / (step_ms * 1e-3),
@@ -145,17 +174,24 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_guide<16, SAMPLE>",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
+            "traffic_gbs": None if traffic is None else traffic / (gs_avg * 1e-3) / 1e9,
             "node_tests_per_bin": visits / (n * NN), "hit_fraction": hits / (n * NN),
         },
     }
     orc = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
-    if not args.only_march:
+    sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
+    unknown = sections - {"learned", "batching", "precision"}
+    if unknown:
+        raise SystemExit(f"unknown sections: {sorted(unknown)}")
+    if "learned" in sections:
         out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
+    if "batching" in sections:
         out["batching"] = batching_section(w, svo, room, cam, cnrm, args)
+    if "precision" in sections:
         out["precision"] = precision_section(w, room, sp, pos, cam, args, orc, tile)
     print(json.dumps(out))
 
@@ -222,6 +258,12 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
     t = t / t.sum(1, keepdim=True)
     q = w.nn_forward(svo, sp_, sn_).double()
     kl = torch.where(t > 0, t * (t.log() - q.log()), torch.zeros_like(t)).sum(1).cpu().numpy()
+    # how much the march pdf itself moves within a pixel: centre vs the jittered
+    # training point of the same pixel (every pixel hits, so indices correspond)
+    jp = torch.from_numpy(np.ascontiguousarray(frames[0][0][:, sub])).to(dev)
+    tj = w.guide_pdf(svo, jp, w.make_opts(N=16)).double()
+    tj = tj / tj.sum(1, keepdim=True)
+    klj = torch.where(t > 0, t * (t.log() - tj.log()), torch.zeros_like(t)).sum(1).cpu().numpy()
     flops = 2 * (35 * 64 + 3 * 64 * 64 + 64 * 256)   # algorithmic MACs x 2 per vertex
     return {
         "what": "hash-grid (16 x 2^19 x 2) + MLP 35-64-64-64-64-256, BF16 MFMA, trained on the GPU "
@@ -237,6 +279,9 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
         "judge_probe_kl": st["last_probe_kl"],
         "kl_per_vertex": {"mean": float(kl.mean()), "median": float(np.median(kl)),
                           "p90": float(np.quantile(kl, 0.9)), "vertices": int(kl.size)},
+        "march_kl_within_pixel": {"mean": float(klj.mean()), "median": float(np.median(klj)),
+                                  "what": "KL(march pdf at the pixel centre || march pdf at a "
+                                          "jittered point of the same pixel), same vertices"},
         "nn_forward_ms": fwd_ms,
         "mfma_flops_per_vertex": flops,
     }

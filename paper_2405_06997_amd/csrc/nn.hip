@@ -399,6 +399,42 @@ __device__ __forceinline__ void oct_decode(float x, float y, float &dx, float &d
 // ((u + u3)/16, (v + u4)/16) and pdf = p_b * 256 / (4 pi) (SAMPLE).
 enum { OUT_SAMPLE = 0, OUT_PROB = 1 };
 
+// Reductions and scans over the 16 lanes of a DPP row, all in VALU data-
+// parallel primitives (no LDS crossbar): the butterfly uses quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror, so every
+// lane ends with the same bits (each step adds two equal partial sums in
+// either order); the inclusive scan is Hillis-Steele over row_shr 1, 2, 4, 8
+// (lanes shifted in from outside the row read 0).
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += dppf<0xB1>(v);
+    v += dppf<0x4E>(v);
+    v += dppf<0x141>(v);
+    v += dppf<0x140>(v);
+    return v;
+}
+__device__ __forceinline__ float row16_max(float v)
+{
+    v = fmaxf(v, dppf<0xB1>(v));
+    v = fmaxf(v, dppf<0x4E>(v));
+    v = fmaxf(v, dppf<0x141>(v));
+    v = fmaxf(v, dppf<0x140>(v));
+    return v;
+}
+__device__ __forceinline__ float row16_scan(float v)
+{
+    v += dppf<0x111>(v);
+    v += dppf<0x112>(v);
+    v += dppf<0x114>(v);
+    v += dppf<0x118>(v);
+    return v;
+}
+
 __device__ __forceinline__ int swz64(int row, int chunk) { return row * 64 + ((chunk ^ (row & 7)) << 3); }
 
 template <int MODE>
@@ -427,6 +463,9 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
         na1 = *reinterpret_cast<const bf16x8 *>(hrow + 32 + 8 * g);
     }
     for (; tile < tiles; tile += wstride) {
+        // re-read the W4 fragments from LDS every tile rather than pinning
+        // 128 registers for them (occupancy hides the load latency)
+        asm volatile("" ::: "memory");
         const int64_t r0 = tile * 16;
         const bf16x8 a0 = na0, a1 = na1;
         if (tile + wstride < tiles) {
@@ -463,16 +502,14 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
                 e[c] = x + bs[16 * c + u];
                 mx = fmaxf(mx, e[c]);
             }
-#pragma unroll
-            for (int d = 8; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+            mx = row16_max(mx);
 #pragma unroll
             for (int c = 0; c < 16; ++c) e[c] = expf(e[c] - mx);
             if (MODE == OUT_PROB) {
                 float sum = 0.f;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) sum += e[c];
-#pragma unroll
-                for (int d = 8; d >= 1; d >>= 1) sum += __shfl_xor(sum, d);
+                sum = row16_sum(sum);
                 if (row < n) {
 #pragma unroll
                     for (int c = 0; c < 16; ++c) prob_out[row * 256 + 16 * c + u] = e[c] / sum;
@@ -483,10 +520,7 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
                 float run = 0.f;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
-                    float t = e[c];
-#pragma unroll
-                    for (int d = 8; d >= 1; d >>= 1) t += __shfl_xor(t, d);
-                    run += t;
+                    run += row16_sum(e[c]);
                     M[c] = run;
                 }
                 const float total = M[15];
@@ -504,12 +538,7 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
 #pragma unroll
                 for (int c = 1; c < 16; ++c)
                     if (c == v) ev = e[c];
-                float S = ev;   // inclusive scan of field row v over its 16 columns
-#pragma unroll
-                for (int d = 1; d < 16; d <<= 1) {
-                    const float t = __shfl_up(S, d, 16);
-                    if (u >= d) S += t;
-                }
+                const float S = row16_scan(ev);   // inclusive scan of field row v over its 16 columns
                 const float rowsum = __shfl(S, 16 * g + 15);
                 const uint64_t bal = __ballot(u2 * rowsum < S);
                 const uint32_t mine = (uint32_t)(bal >> (16 * g)) & 0xffffu;
