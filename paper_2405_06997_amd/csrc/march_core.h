@@ -260,13 +260,151 @@ WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, i
     return settle(s, D, s.lvl - p, s.lvl, tkey, t0, t1, t2, bits, count_from, vis, h);
 }
 
+// ---------------------------------------------------------------------------
+// The same traversal as a machine that performs exactly one occupancy test per
+// call, so that the lanes of a wave, each on its own ray, advance in lockstep
+// one test at a time instead of waiting for the longest ancestor walk or
+// descent of the wave. Phases:
+//  PH_ADVANCE  the state is an empty cell (or the origin's leaf): leave it
+//              through its first exit crossing, then test the first unshared
+//              ancestor of the cell entered (same call);
+//  PH_PATH     key/lo/lvl hold the cell entered; its ancestors from level l
+//              down are tested one per call (levels above l are occupied);
+//  PH_DESCEND  key/lo/lvl hold an occupied cell; each call tests the child the
+//              ray is in (mid-plane comparisons).
+// Tests, their order and their counts are those of march_step/settle.
+enum { PH_ADVANCE = 0, PH_PATH = 1, PH_DESCEND = 2 };
+constexpr int kMaxTests = 1 << 17;   // > worst-case occupancy tests of a depth-10 ray
+
+struct MicroState {
+    uint32_t O0, O1, O2;      // origin, 2^-30 units
+    uint32_t aq0, aq1, aq2;   // |q|
+    int sg0, sg1, sg2;        // sign(q)
+    int lvl, ta, l, phase;
+    uint32_t key, tn, td;
+    uint32_t lo0, lo1, lo2;
+};
+
+// Start at the origin's cell. When the origin's leaf is occupied it is the
+// cell to leave (never a hit) and the ancestors the top-down walk would test
+// are counted; otherwise the origin's path is tested from the root down.
+WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key, bool origin_occupied,
+                         uint32_t aq0, uint32_t aq1, uint32_t aq2, int sg0, int sg1, int sg2, int D,
+                         int count_from, int &vis)
+{
+    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
+    s.aq0 = aq0; s.aq1 = aq1; s.aq2 = aq2;
+    s.sg0 = sg0; s.sg1 = sg1; s.sg2 = sg2;
+    s.ta = -1; s.tn = 0; s.td = 1;
+    const uint32_t mk = ~((1u << (kFine - D)) - 1u);
+    s.lvl = D;
+    s.key = origin_key;
+    s.lo0 = O[0] & mk; s.lo1 = O[1] & mk; s.lo2 = O[2] & mk;
+    s.l = 0;
+    if (origin_occupied) {
+        s.phase = PH_ADVANCE;
+        vis += D + 1 - (count_from < D ? count_from : D);   // levels count_from..D
+    } else {
+        s.phase = PH_PATH;
+    }
+}
+
+template <class Bits>
+WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
+{
+    if (s.phase == PH_ADVANCE) {
+        const uint32_t size = 1u << (kFine - s.lvl);
+        const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
+        const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
+        const uint32_t dl2 = far_face(s.lo2, size, s.O2, s.sg2);
+#if WFPG_F64_PRODUCTS
+        const uint32_t c1 = (double)dl1 * (double)s.aq0 < (double)dl0 * (double)s.aq1 ? 0xffffffffu : 0u;
+        const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
+        const uint32_t c2 = (double)dl2 * (double)Q01 < (double)D01 * (double)s.aq2 ? 0xffffffffu : 0u;
+#else
+        const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
+        const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
+        const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
+#endif
+        const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
+        const int e = (int)((m1 & 1u) | (m2 & 2u));
+        const uint32_t De = (dl2 & m2) | (D01 & ~m2);
+        const uint32_t Qe = (s.aq2 & m2) | (Q01 & ~m2);
+        const int sgn = (int)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) | ((uint32_t)s.sg2 & m2));
+        const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
+        const int64_t nl = (int64_t)le + (int64_t)sgn * (int64_t)size;
+        if (nl < 0 || nl >= (1ll << kFine)) return STEP_MISS;
+        const uint32_t nlu = (uint32_t)nl;
+        const uint32_t oldc = le >> (kFine - s.lvl), newc = nlu >> (kFine - s.lvl);
+        const uint32_t m = 0x09249249u << e;
+        s.key = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m)) : ((((s.key & m) - 1u) & m) | (s.key & ~m));
+        s.lo0 = (nlu & m0) | (s.lo0 & ~m0);
+        s.lo1 = (nlu & m1) | (s.lo1 & ~m1);
+        s.lo2 = (nlu & m2) | (s.lo2 & ~m2);
+        s.tn = De;
+        s.td = Qe;
+        s.ta = e;
+        s.l = s.lvl - (31 - __builtin_clz(oldc ^ newc));   // first level not shared with the cell left
+        s.phase = PH_PATH;
+    }
+    // the cell to test: an ancestor of the entered cell, or the child the ray is in
+    int tl;
+    uint32_t tk, n0 = s.lo0, n1 = s.lo1, n2 = s.lo2;
+    if (s.phase == PH_PATH) {
+        tl = s.l;
+        tk = s.key >> (3 * (s.lvl - s.l));
+    } else {
+        const uint32_t half = 1u << (29 - s.lvl);
+        const uint32_t oct = upper_half(s.lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
+                             (upper_half(s.lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
+                             (upper_half(s.lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
+        tk = (s.key << 3) | oct;
+        n0 += (oct & 1u) ? half : 0u;
+        n1 += (oct & 2u) ? half : 0u;
+        n2 += (oct & 4u) ? half : 0u;
+        tl = s.lvl + 1;
+    }
+    const uint64_t w = bits(tl, woff(tl) + (tk >> 6));
+    vis += (tl >= count_from);
+    if (!((w >> (tk & 63)) & 1ull)) {   // empty: the cell to leave next
+        const uint32_t mk = ~((1u << (kFine - tl)) - 1u);
+        s.lvl = tl;
+        s.key = tk;
+        s.lo0 = n0 & mk;
+        s.lo1 = n1 & mk;
+        s.lo2 = n2 & mk;
+        s.phase = PH_ADVANCE;
+        return STEP_CONTINUE;
+    }
+    if (s.phase == PH_PATH) {
+        if (tl < s.lvl) {
+            s.l = tl + 1;
+            return STEP_CONTINUE;
+        }
+        s.phase = PH_DESCEND;   // the entered cell is occupied
+    } else {
+        s.lvl = tl;
+        s.key = tk;
+        s.lo0 = n0;
+        s.lo1 = n1;
+        s.lo2 = n2;
+    }
+    if (s.lvl == D) {
+        h.axis = s.ta;
+        h.key = s.key;
+        h.delta = s.tn;
+        return STEP_HIT;
+    }
+    return STEP_CONTINUE;
+}
+
 // Whole march: 1 on a hit, 0 on a miss, -1 if the iteration bound is
 // exceeded (never expected).
 template <class Bits>
 WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits &bits,
                   int count_from, int &vis, Hit &h)
 {
-    MarchState s;
+    MicroState s;
     uint32_t aq0, aq1, aq2;
     int sg0, sg1, sg2;
     split_dir(q0, aq0, sg0);
@@ -274,9 +412,9 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
     split_dir(q2, aq2, sg2);
     const uint32_t ok = morton3(O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D));
     const bool occ = (bits(D, woff(D) + (ok >> 6)) >> (ok & 63)) & 1ull;
-    march_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, bits, count_from, vis);
-    for (int it = 0; it < kMaxIt; ++it) {
-        const int st = march_step(s, D, bits, count_from, vis, h);
+    micro_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, count_from, vis);
+    for (int it = 0; it < kMaxTests; ++it) {
+        const int st = micro_step(s, D, bits, count_from, vis, h);
         if (st == STEP_HIT) return 1;
         if (st == STEP_MISS) return 0;
     }
