@@ -31,10 +31,10 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6e969df22c7b3db06314bccb08b034582d75544782d18bdfadce8c570acb0ca4",
+    "sources_sha256": "72adeee46999ae1b16b02f4ea4c130842e7ebd85a8566cde13ddab58fe4c0859",
     "N": 16,
     "tile": {"waves_per_block": 4, "lds_levels": 5, "blocks_per_cu": 8},
-    "bytes_per_launch": 4721501901,
+    "bytes_per_launch": 5096900546,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h"]
 
@@ -251,6 +251,10 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
     fallbacks = st["fallbacks"] - fb0
     assert torch.isfinite(p_out).all() and (p_out > 0).all()
     fwd_ms = _timed(lambda: w.nn_forward(svo, pos, nrm), 3, 1)
+    # the learned path's own cost: network samples + probe march + judge, no fallback
+    opts_nf = w.make_opts(N=16, mode=1, kl_bound=3.0e38, probe_stride=256)
+    nf_ms = _timed(lambda: w.guide_sample(svo, pos, opts_nf, seed=3, bounce=0, nrm=nrm, dir_out=d_out,
+                                          pdf_out=p_out), K, args.warmup)
     # per-vertex KL(march || network) on an evenly strided sample
     sub = slice(0, n, max(1, n // 65536))
     sp_, sn_ = pos[:, sub].contiguous(), nrm[:, sub].contiguous()
@@ -283,6 +287,8 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
                                   "what": "KL(march pdf at the pixel centre || march pdf at a "
                                           "jittered point of the same pixel), same vertices"},
         "nn_forward_ms": fwd_ms,
+        "no_fallback_guide_sample_ms": nf_ms,
+        "no_fallback_speedup_vs_march": march_ms / nf_ms,
         "mfma_flops_per_vertex": flops,
     }
 
@@ -291,18 +297,15 @@ def batching_section(w, svo, room, cam, cnrm, args):
     """Eight-bounce wavefront (queue sizes decaying by U[0.5, 0.8] per bounce)
     replayed as one captured graph of persistent guide kernels. The autotuner
     picks N in {8, 16, 32} and the tile: the finest N whose time per vertex
-    fits the budget, tuned on the camera bounce and on the first secondary
-    bounce (later bounces share its vertex distribution)."""
+    on the whole queue fits the budget, for the camera bounce and for the
+    first secondary bounce (later bounces share its vertex distribution)."""
     import torch
 
     import synth
     dev = torch.device("cuda:0")
     queues, sizes = synth.bounce_queues(room, cam, cnrm, 8, 15)
     qpos = [torch.from_numpy(q[0]).to(dev) for q in queues]
-    picks = []
-    for b in (0, 1):
-        sub = qpos[b][:, :: max(1, qpos[b].shape[1] // 65536)].contiguous()
-        picks.append(w.autotune_n(svo, sub, args.budget_ns, reps=3))
+    picks = [w.autotune_n(svo, qpos[b], args.budget_ns, reps=3) for b in (0, 1)]
     Ns = [picks[0]["N"]] + [picks[1]["N"]] * (len(sizes) - 1)
     n_dev = torch.tensor(sizes, dtype=torch.int64, device=dev)
     G = w.BounceGraph(svo, qpos, n_dev, Ns, seed=7)
@@ -323,7 +326,7 @@ def batching_section(w, svo, room, cam, cnrm, args):
     return {"bounces": len(sizes), "queue_sizes": sizes, "vertices": sum(sizes),
             "budget_ns_per_vertex": args.budget_ns, "N_per_bounce": Ns,
             "tuned": [{"bounce": b, "N": p["N"], "tile": p["tile"],
-                       "ms_per_N_65536": {str(k): v for k, v in p["ms_per_N"].items()}}
+                       "queue_ms_per_N": {str(k): v for k, v in p["ms_per_N"].items()}}
                       for b, p in zip((0, 1), picks)],
             "graph_ms": g_ms, "samples_per_s": sum(sizes) / (g_ms * 1e-3),
             "eager_ms": e_ms, "graph_speedup_vs_eager": e_ms / g_ms,

@@ -101,11 +101,8 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Occupancy tests each lane makes between the wave's bookkeeping points
-// (0: one whole cell step instead).
-#ifndef WFPG_MICRO_K
-#define WFPG_MICRO_K 0
-#endif
+// Occupancy tests each lane makes between the wave's bookkeeping points.
+constexpr int kMicro = 4;
 
 constexpr uint32_t kMissRec = 0xffffffffu;
 constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
@@ -333,11 +330,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     bool Focc = false;
     // per-lane march state
     int lslot = 0, lbin = -1, vis = 0, iters = 0;
-#if WFPG_MICRO_K
     core::MicroState st;
-#else
-    core::MarchState st;
-#endif
 
     while (true) {
         // finalize every slot whose bins are all finished
@@ -404,14 +397,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
                 const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
                 vis = 0;
                 iters = 0;
-#if WFPG_MICRO_K
                 core::micro_begin(st, O, Fkey, Focc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
                                   a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, vis);
-#else
-                core::march_begin(st, O, Fkey, Focc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
-                                  a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, bits,
-                                  5, vis);
-#endif
             }
             idle &= ~__ballot(mine);
             nxt = uni(nxt + take);
@@ -433,16 +420,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
         int res = core::STEP_CONTINUE;
         Hit h = {-1, 0u, 0u};
         if (lbin >= 0) {
-#if WFPG_MICRO_K
-            for (int m = 0; m < WFPG_MICRO_K; ++m) {
+            for (int m = 0; m < kMicro; ++m) {
                 res = core::micro_step(st, D, bits, 5, vis, h);
                 if (res != core::STEP_CONTINUE) break;
             }
-            if (res == core::STEP_CONTINUE && (iters += WFPG_MICRO_K) >= core::kMaxTests) {
-#else
-            res = core::march_step(st, D, bits, 5, vis, h);
-            if (res == core::STEP_CONTINUE && ++iters >= core::kMaxIt) {
-#endif
+            if (res == core::STEP_CONTINUE && (iters += kMicro) >= core::kMaxTests) {
                 atomicOr(a.err, 1);
                 res = core::STEP_MISS;
             }

@@ -20,12 +20,6 @@
 
 #include <stdint.h>
 
-// Exact crossing comparisons through FP64 products (full-rate on gfx950)
-// instead of 32x32->64-bit integer products.
-#ifndef WFPG_F64_PRODUCTS
-#define WFPG_F64_PRODUCTS 0
-#endif
-
 #if defined(__HIPCC__)
 #define WFPG_HD __host__ __device__ __forceinline__
 #define WFPG_UNROLL _Pragma("unroll")
@@ -38,7 +32,6 @@ namespace wfpg {
 namespace core {
 
 constexpr int kFine = 30;
-constexpr int kMaxIt = 1 << 15;   // > worst-case steps of a depth-10 ray
 
 // Word offset of level l in the concatenated occupancy bitmaps (levels 0..2
 // take one 64-bit word each, level l >= 3 takes 8^l / 64 words).
@@ -81,20 +74,6 @@ struct Hit {
     uint32_t delta;    // |B - O| of that crossing, 2^-30 units
 };
 
-// Resumable march state. Between steps the state is always an EMPTY cell
-// (or the origin's leaf) that the ray is inside of just after the crossing
-// (tn/td on axis ta; ta = -1 and tn = 0 at the start): level, key and lower
-// corner. Plain scalars only, so that the state lives in registers.
-struct MarchState {
-    uint32_t O0, O1, O2;      // origin, 2^-30 units
-    uint32_t aq0, aq1, aq2;   // |q|
-    int sg0, sg1, sg2;        // sign(q)
-    uint32_t origin_key;
-    int lvl, ta;
-    uint32_t key, tn, td;
-    uint32_t lo0, lo1, lo2;
-};
-
 enum { STEP_CONTINUE = 0, STEP_HIT = 1, STEP_MISS = 2 };
 
 // Which half of a cell the ray is in along one axis just after the current
@@ -106,16 +85,8 @@ WFPG_HD uint32_t upper_half(uint32_t M, uint32_t O, uint32_t aq, int sg, int j, 
     if (sg == 0) return O >= M ? 1u : 0u;
     int32_t dl = (int32_t)(M - O);
     if (sg < 0) dl = -dl;
-#if WFPG_F64_PRODUCTS
-    // |dl|, tn <= 2^30 and td, aq <= 2^23: each factor is a power of two or
-    // has at most 30 (resp. 23) significant bits, so each product has at most
-    // 53 and FP64 holds it exactly
-    const double x = (double)dl * (double)td, y = (double)tn * (double)aq;
-    const bool crossed = ((j <= ta) ? (x <= y) : (x < y)) || (sg > 0 && dl == 0);
-#else
     const int64_t lhs = (int64_t)dl * (int64_t)td - (int64_t)((uint64_t)tn * aq);
     const bool crossed = lhs < (int64_t)(j <= ta) || (sg > 0 && dl == 0);
-#endif
     return (crossed != (sg < 0)) ? 1u : 0u;
 }
 
@@ -126,142 +97,13 @@ WFPG_HD uint32_t far_face(uint32_t lo, uint32_t size, uint32_t O, int sg)
     return sg > 0 ? lo + size - O : (sg < 0 ? O - lo : 1u);
 }
 
-// Settle on the cell the ray is in after a crossing: the target cell
-// (tlvl, tkey, corner t0..t2) has known ancestors; test them top-down from
-// level `from` (all levels above are known occupied) to the first empty one.
-// If the whole path is occupied, descend below the target by mid-plane
-// comparisons until an empty cell or an occupied leaf (a hit). Every
-// occupancy test at a level >= count_from adds one to vis.
-template <class Bits>
-WFPG_HD int settle(MarchState &s, int D, int from, int tlvl, uint32_t tkey, uint32_t t0, uint32_t t1,
-                   uint32_t t2, const Bits &bits, int count_from, int &vis, Hit &h)
-{
-    for (int l = from; l <= tlvl; ++l) {
-        const uint32_t k = tkey >> (3 * (tlvl - l));
-        const uint64_t w = bits(l, woff(l) + (k >> 6));
-        vis += (l >= count_from);
-        if (!((w >> (k & 63)) & 1ull)) {
-            const uint32_t mk = ~((1u << (kFine - l)) - 1u);
-            s.lvl = l;
-            s.key = k;
-            s.lo0 = t0 & mk;
-            s.lo1 = t1 & mk;
-            s.lo2 = t2 & mk;
-            return STEP_CONTINUE;
-        }
-    }
-    int lvl = tlvl;
-    uint32_t key = tkey, lo0 = t0, lo1 = t1, lo2 = t2;
-    while (lvl < D) {
-        const uint32_t half = 1u << (29 - lvl);
-        const uint32_t oct = upper_half(lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
-                             (upper_half(lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
-                             (upper_half(lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
-        key = (key << 3) | oct;
-        lo0 += (oct & 1u) ? half : 0u;
-        lo1 += (oct & 2u) ? half : 0u;
-        lo2 += (oct & 4u) ? half : 0u;
-        ++lvl;
-        const uint64_t w = bits(lvl, woff(lvl) + (key >> 6));
-        vis += (lvl >= count_from);
-        if (!((w >> (key & 63)) & 1ull)) {
-            s.lvl = lvl;
-            s.key = key;
-            s.lo0 = lo0;
-            s.lo1 = lo1;
-            s.lo2 = lo2;
-            return STEP_CONTINUE;
-        }
-    }
-    h.axis = s.ta;
-    h.key = key;
-    h.delta = s.tn;
-    return STEP_HIT;
-}
-
-// Start a march at the cell holding the origin. When the origin's leaf is
-// occupied all its ancestors are too, so the walk starts at that leaf (which
-// is never a hit): the top-down descent from the root would test exactly
-// those ancestors, and their tests at levels >= count_from are counted.
-// Otherwise the origin's ancestors are tested from the root down to the
-// first empty one. The result and the counts equal those of the plain
-// top-down walk from the root.
-template <class Bits>
-WFPG_HD void march_begin(MarchState &s, const uint32_t O[3], uint32_t origin_key, bool origin_occupied,
-                         uint32_t aq0, uint32_t aq1, uint32_t aq2, int sg0, int sg1, int sg2, int D,
-                         const Bits &bits, int count_from, int &vis)
-{
-    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
-    s.aq0 = aq0; s.aq1 = aq1; s.aq2 = aq2;
-    s.sg0 = sg0; s.sg1 = sg1; s.sg2 = sg2;
-    s.origin_key = origin_key;
-    s.ta = -1; s.tn = 0; s.td = 1;
-    const uint32_t mk = ~((1u << (kFine - D)) - 1u);
-    if (origin_occupied) {
-        s.lvl = D;
-        s.key = origin_key;
-        s.lo0 = O[0] & mk; s.lo1 = O[1] & mk; s.lo2 = O[2] & mk;
-        vis += D + 1 - (count_from < D ? count_from : D);   // levels count_from..D
-    } else {
-        Hit h;
-        settle(s, D, 0, D, origin_key, O[0] & mk, O[1] & mk, O[2] & mk, bits, count_from, vis, h);
-    }
-}
-
 WFPG_HD void split_dir(int q, uint32_t &aq, int &sg)
 {
     aq = (uint32_t)(q < 0 ? -q : q);
     sg = (q > 0) - (q < 0);
 }
 
-// One step: leave the current cell through its first exit crossing (ties:
-// lowest axis), then settle on the cell holding the ray after it.
-template <class Bits>
-WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
-{
-    const uint32_t size = 1u << (kFine - s.lvl);
-    const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
-    const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
-    const uint32_t dl2 = far_face(s.lo2, size, s.O2, s.sg2);
-    // lowest-parameter exit axis, ties to the lower axis; the per-axis values
-    // are picked with masks (a select between struct fields would be turned
-    // into a private-memory table by the compiler)
-#if WFPG_F64_PRODUCTS
-    // products of a distance (<= 2^30) and a direction component (<= 2^23):
-    // at most 53 significant bits (see upper_half), exact in FP64
-    const uint32_t c1 = (double)dl1 * (double)s.aq0 < (double)dl0 * (double)s.aq1 ? 0xffffffffu : 0u;
-    const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
-    const uint32_t c2 = (double)dl2 * (double)Q01 < (double)D01 * (double)s.aq2 ? 0xffffffffu : 0u;
-#else
-    const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
-    const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
-    const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
-#endif
-    const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
-    const int e = (int)((m1 & 1u) | (m2 & 2u));
-    const uint32_t De = (dl2 & m2) | (D01 & ~m2);
-    const uint32_t Qe = (s.aq2 & m2) | (Q01 & ~m2);
-    const int sgn = (int)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) | ((uint32_t)s.sg2 & m2));
-    const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
-    const int64_t nl = (int64_t)le + (int64_t)sgn * (int64_t)size;
-    if (nl < 0 || nl >= (1ll << kFine)) return STEP_MISS;
-    const uint32_t nlu = (uint32_t)nl;
-    const uint32_t oldc = le >> (kFine - s.lvl), newc = nlu >> (kFine - s.lvl);
-    const uint32_t t0 = (nlu & m0) | (s.lo0 & ~m0);
-    const uint32_t t1 = (nlu & m1) | (s.lo1 & ~m1);
-    const uint32_t t2 = (nlu & m2) | (s.lo2 & ~m2);
-    const uint32_t m = 0x09249249u << e;
-    const uint32_t tkey = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m))
-                                  : ((((s.key & m) - 1u) & m) | (s.key & ~m));
-    s.tn = De;
-    s.td = Qe;
-    s.ta = e;
-    const int p = 31 - __builtin_clz(oldc ^ newc);   // levels above s.lvl - p are shared
-    return settle(s, D, s.lvl - p, s.lvl, tkey, t0, t1, t2, bits, count_from, vis, h);
-}
-
-// ---------------------------------------------------------------------------
-// The same traversal as a machine that performs exactly one occupancy test per
+// The traversal is a machine that performs exactly one occupancy test per
 // call, so that the lanes of a wave, each on its own ray, advance in lockstep
 // one test at a time instead of waiting for the longest ancestor walk or
 // descent of the wave. Phases:
@@ -272,7 +114,6 @@ WFPG_HD int march_step(MarchState &s, int D, const Bits &bits, int count_from, i
 //              down are tested one per call (levels above l are occupied);
 //  PH_DESCEND  key/lo/lvl hold an occupied cell; each call tests the child the
 //              ray is in (mid-plane comparisons).
-// Tests, their order and their counts are those of march_step/settle.
 enum { PH_ADVANCE = 0, PH_PATH = 1, PH_DESCEND = 2 };
 constexpr int kMaxTests = 1 << 17;   // > worst-case occupancy tests of a depth-10 ray
 
@@ -317,15 +158,9 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
         const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
         const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
         const uint32_t dl2 = far_face(s.lo2, size, s.O2, s.sg2);
-#if WFPG_F64_PRODUCTS
-        const uint32_t c1 = (double)dl1 * (double)s.aq0 < (double)dl0 * (double)s.aq1 ? 0xffffffffu : 0u;
-        const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
-        const uint32_t c2 = (double)dl2 * (double)Q01 < (double)D01 * (double)s.aq2 ? 0xffffffffu : 0u;
-#else
         const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
         const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
         const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
-#endif
         const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
         const int e = (int)((m1 & 1u) | (m2 & 2u));
         const uint32_t De = (dl2 & m2) | (D01 & ~m2);

@@ -140,6 +140,14 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
     }
 }
 
+// MLP parameters: FP32 master -> BF16 copy in the padded GEMM layout (W0 is
+// stored [64][64] with zero columns 35..63).
+struct MlpLayout {
+    int64_t woff[5], boff[5];   // offsets in the FP32 parameter vector
+    int fin[5], fout[5];
+    int64_t bw[5];              // offsets of the BF16 weight copies
+};
+
 // --------------------------------------------------------- hash encoding ---
 struct Grid {
     int32_t res[16];
@@ -165,22 +173,12 @@ __device__ __forceinline__ void cell_of(const float p[3], int32_t R, uint32_t c[
     }
 }
 
-// X[v][0..63] = bf16(features of 16 levels x 2, then the normal, then zeros).
-// One thread per (vertex, level); rows >= n (padding) are zeroed.
-__global__ void k_encode(Grid gr, const uint16_t *__restrict__ table, const float *__restrict__ pos,
-                         const float *__restrict__ nrm, int64_t n, int64_t stride, int64_t rows,
-                         uint16_t *X)
+// The two BF16 features of level l at position p (low half: feature 0):
+// trilinear interpolation, FP32 weights (wx * wy) * wz, corners x fastest,
+// FP32 sums in that order, rounded once to BF16.
+__device__ __forceinline__ uint32_t encode_level(const Grid &gr, const uint16_t *__restrict__ table, const float p[3],
+                                                 int l)
 {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t v = t >> 4;
-    const int l = (int)(t & 15);
-    if (v >= rows) return;
-    uint16_t *x = X + v * 64;
-    if (v >= n) {
-        for (int k = 0; k < 4; ++k) x[4 * l + k] = 0;
-        return;
-    }
-    const float p[3] = {pos[v], pos[stride + v], pos[2 * stride + v]};
     uint32_t c[3];
     float fr[3];
     cell_of(p, gr.res[l], c, fr);
@@ -197,8 +195,28 @@ __global__ void k_encode(Grid gr, const uint16_t *__restrict__ table, const floa
         a0 = a0 + w * bf2f((uint16_t)(pr & 0xffffu));
         a1 = a1 + w * bf2f((uint16_t)(pr >> 16));
     }
-    x[2 * l] = f2bf(a0);
-    x[2 * l + 1] = f2bf(a1);
+    return (uint32_t)f2bf(a0) | ((uint32_t)f2bf(a1) << 16);
+}
+
+// X[v][0..63] = bf16(features of 16 levels x 2, then the normal, then zeros).
+// One thread per (vertex, level); rows >= n (padding) are zeroed.
+__global__ void k_encode(Grid gr, const uint16_t *__restrict__ table, const float *__restrict__ pos,
+                         const float *__restrict__ nrm, int64_t n, int64_t stride, int64_t rows,
+                         uint16_t *X)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t v = t >> 4;
+    const int l = (int)(t & 15);
+    if (v >= rows) return;
+    uint16_t *x = X + v * 64;
+    if (v >= n) {
+        for (int k = 0; k < 4; ++k) x[4 * l + k] = 0;
+        return;
+    }
+    const float p[3] = {pos[v], pos[stride + v], pos[2 * stride + v]};
+    const uint32_t pair = encode_level(gr, table, p, l);
+    x[2 * l] = (uint16_t)(pair & 0xffffu);
+    x[2 * l + 1] = (uint16_t)(pair >> 16);
     if (l == 0) {
         x[32] = f2bf(nrm ? nrm[v] : 0.f);
         x[33] = f2bf(nrm ? nrm[stride + v] : 0.f);
@@ -387,16 +405,18 @@ __device__ __forceinline__ void oct_decode(float x, float y, float &dx, float &d
     dz = z;
 }
 
-// Output layer fused with the softmax and its use (inference only): one
-// wave takes 16 rows of the last hidden activations H [rows][64] (BF16),
-// multiplies them by W4 (staged once per block in LDS, 16-byte chunks
-// XOR-swizzled by row) with the same MFMA sequence and bias add as the
-// unfused GEMM, so the logits are bit-identical to it, and keeps them in
-// registers: lane l holds, for rows 4*(l/16) + r (r < 4), the logits of bins
-// 16*c + l%16 (c < 16), i.e. field row v = c and column u = l%16. Per row:
-// softmax; then either the probabilities (PROB) or inverse-CDF sampling with
-// the march path's uniforms and row/column rule, the octahedral decode of
-// ((u + u3)/16, (v + u4)/16) and pdf = p_b * 256 / (4 pi) (SAMPLE).
+// Whole network fused with the softmax and its use (inference only). One
+// wave takes 16 rows (vertices): it encodes them into a BF16 tile in LDS,
+// runs the four hidden layers and the output layer on the matrix cores with
+// the weights staged once per block in LDS (16-byte chunks XOR-swizzled by
+// row), with the same MFMA sequence, bias add, ReLU and BF16 rounding as the
+// unfused encode + GEMM path (so the logits are bit-identical to it), and
+// keeps the logits in registers: lane l holds, for rows 4*(l/16) + r (r < 4),
+// the logits of bins 16*c + l%16 (c < 16), i.e. field row v = c and column
+// u = l%16. Per row: softmax; then either the probabilities (PROB) or
+// inverse-CDF sampling with the march path's uniforms and row/column rule,
+// the octahedral decode of ((u + u3)/16, (v + u4)/16) and
+// pdf = p_b * 256 / (4 pi) (SAMPLE). Activations never reach HBM.
 enum { OUT_SAMPLE = 0, OUT_PROB = 1 };
 
 // Reductions and scans over the 16 lanes of a DPP row, all in VALU data-
@@ -437,42 +457,115 @@ __device__ __forceinline__ float row16_scan(float v)
 
 __device__ __forceinline__ int swz64(int row, int chunk) { return row * 64 + ((chunk ^ (row & 7)) << 3); }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ H, const uint16_t *__restrict__ W4,
-                                                    const float *__restrict__ b4, int64_t n, uint64_t seed,
-                                                    uint32_t bounce, float pdf_scale, float *dir_out,
-                                                    float *pdf_out, float *prob_out)
+// LDS element index of column e of a swizzled [rows][64] BF16 tile.
+__device__ __forceinline__ int swz_el(int row, int e) { return swz64(row, e >> 3) + (e & 7); }
+
+__device__ __forceinline__ void wave_fence()
 {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+struct InferArgs {
+    Grid gr;
+    const uint16_t *table;     // BF16 hash table [16][T][2]
+    const uint16_t *wbf;       // BF16 weights, layer k at bw[k], [out][64]
+    const float *params;       // FP32 parameters (biases)
+    MlpLayout lay;
+    const float *pos, *nrm;    // 3 x n SoA
+    int64_t n;
+    uint64_t seed;
+    uint32_t bounce;
+    float pdf_scale;
+    float *dir_out, *pdf_out, *prob_out;
+};
+
+constexpr int kInferWaves = 4;
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * kInferWaves) k_nn_infer(InferArgs A)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Wh[4][64 * 64];
     __shared__ __attribute__((aligned(16))) uint16_t Ws[256 * 64];
+    __shared__ float bh[4][64];
     __shared__ float bs[256];
+    __shared__ __attribute__((aligned(16))) uint16_t act[kInferWaves][16 * 64];
+    for (int t = threadIdx.x; t < 4 * 64 * 8; t += blockDim.x) {
+        const int k = t >> 9, row = (t >> 3) & 63, ch = t & 7;
+        *reinterpret_cast<uint4 *>(&Wh[k][swz64(row, ch)]) =
+            *reinterpret_cast<const uint4 *>(A.wbf + A.lay.bw[k] + (int64_t)row * 64 + ch * 8);
+    }
     for (int t = threadIdx.x; t < 256 * 8; t += blockDim.x) {
         const int row = t >> 3, ch = t & 7;
         *reinterpret_cast<uint4 *>(&Ws[swz64(row, ch)]) =
-            *reinterpret_cast<const uint4 *>(W4 + (int64_t)row * 64 + ch * 8);
+            *reinterpret_cast<const uint4 *>(A.wbf + A.lay.bw[4] + (int64_t)row * 64 + ch * 8);
     }
-    for (int t = threadIdx.x; t < 256; t += blockDim.x) bs[t] = b4[t];
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+        bh[t >> 6][t & 63] = A.params[A.lay.boff[t >> 6] + (t & 63)];
+        bs[t] = A.params[A.lay.boff[4] + t];
+    }
     __syncthreads();
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, g = lane >> 4, u = lane & 15;
+    uint16_t *X = act[wave];
+    const int64_t n = A.n;
     const int64_t tiles = (n + 15) / 16;
-    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
-    int64_t tile = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    bf16x8 na0, na1;   // A fragments of the wave's next tile, loaded one tile ahead
-    if (tile < tiles) {
-        const uint16_t *hrow = H + (tile * 16 + u) * 64;   // rows < pad64(n): always allocated
-        na0 = *reinterpret_cast<const bf16x8 *>(hrow + 8 * g);
-        na1 = *reinterpret_cast<const bf16x8 *>(hrow + 32 + 8 * g);
-    }
-    for (; tile < tiles; tile += wstride) {
-        // re-read the W4 fragments from LDS every tile rather than pinning
-        // 128 registers for them (occupancy hides the load latency)
-        asm volatile("" ::: "memory");
+    const int64_t wstride = (int64_t)gridDim.x * kInferWaves;
+    for (int64_t tile = blockIdx.x * (int64_t)kInferWaves + wave; tile < tiles; tile += wstride) {
+        wave_fence();   // the previous tile's reads of X are done (also keeps LDS loads in the loop)
         const int64_t r0 = tile * 16;
-        const bf16x8 a0 = na0, a1 = na1;
-        if (tile + wstride < tiles) {
-            const uint16_t *hrow = H + ((tile + wstride) * 16 + u) * 64;
-            na0 = *reinterpret_cast<const bf16x8 *>(hrow + 8 * g);
-            na1 = *reinterpret_cast<const bf16x8 *>(hrow + 32 + 8 * g);
+        // encode: item j of a lane is row 4j + g, level u; lanes 0..15 also
+        // write the normal and the zero padding of row u
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 4 * j + g;
+            const int64_t v = min(r0 + row, n - 1);
+            const float p[3] = {A.pos[v], A.pos[n + v], A.pos[2 * n + v]};
+            const uint32_t pair = r0 + row < n ? encode_level(A.gr, A.table, p, u) : 0u;
+            *reinterpret_cast<uint32_t *>(&X[swz_el(row, 2 * u)]) = pair;
         }
+        if (lane < 16) {
+            const int64_t v = min(r0 + lane, n - 1);
+            const bool ok = r0 + lane < n;
+            uint32_t w4[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w4[k] = 0u;
+            if (ok) {
+                w4[0] = (uint32_t)f2bf(A.nrm[v]) | ((uint32_t)f2bf(A.nrm[n + v]) << 16);
+                w4[1] = (uint32_t)f2bf(A.nrm[2 * n + v]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)   // columns 32..63: chunks 4..7
+                *reinterpret_cast<uint4 *>(&X[swz64(lane, 4 + k)]) =
+                    make_uint4(w4[4 * k], w4[4 * k + 1], w4[4 * k + 2], w4[4 * k + 3]);
+        }
+        wave_fence();
+        // hidden layers: H = bf16(relu(X W^T + b)), written back over the tile
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(&X[swz64(u, g)]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(&X[swz64(u, 4 + g)]);
+            floatx4 hc[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int row = 16 * c + u;
+                const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(&Wh[k][swz64(row, g)]);
+                const bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(&Wh[k][swz64(row, 4 + g)]);
+                hc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, w0, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                hc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, w1, hc[c], 0, 0, 0);
+            }
+            wave_fence();   // every lane has read its A fragments
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = hc[c][r] + bh[k][16 * c + u];
+                    X[swz_el(4 * g + r, 16 * c + u)] = f2bf(v > 0.f ? v : 0.f);
+                }
+            wave_fence();
+        }
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(&X[swz64(u, g)]);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(&X[swz64(u, 4 + g)]);
         floatx4 acc[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -483,12 +576,12 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
             acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, w1, acc[c], 0, 0, 0);
         }
         // uniforms of row r0 + (lane % 16), fetched per row below
-        uint32_t cu[4] = {0u, 0u, bounce, 0u};
+        uint32_t cu[4] = {0u, 0u, A.bounce, 0u};
         if (MODE == OUT_SAMPLE) {
             const uint64_t i = (uint64_t)(r0 + u);
             cu[0] = (uint32_t)i;
             cu[1] = (uint32_t)(i >> 32);
-            philox(cu, (uint32_t)seed, (uint32_t)(seed >> 32));
+            philox(cu, (uint32_t)A.seed, (uint32_t)(A.seed >> 32));
         }
 #pragma unroll 1
         for (int r = 0; r < 4; ++r) {   // one row of the lane group at a time (register pressure)
@@ -512,7 +605,7 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
                 sum = row16_sum(sum);
                 if (row < n) {
 #pragma unroll
-                    for (int c = 0; c < 16; ++c) prob_out[row * 256 + 16 * c + u] = e[c] / sum;
+                    for (int c = 0; c < 16; ++c) A.prob_out[row * 256 + 16 * c + u] = e[c] / sum;
                 }
             } else {
                 // marginal CDF over field rows (row sums reduced over the 16 lanes)
@@ -550,10 +643,10 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
                     const float u4 = (float)(b4u >> 8) * 5.9604644775390625e-8f;
                     float ox, oy, oz;
                     oct_decode((float)col * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
-                    dir_out[row] = ox;
-                    dir_out[n + row] = oy;
-                    dir_out[2 * n + row] = oz;
-                    pdf_out[row] = (Lb / total) * pdf_scale;
+                    A.dir_out[row] = ox;
+                    A.dir_out[n + row] = oy;
+                    A.dir_out[2 * n + row] = oz;
+                    A.pdf_out[row] = (Lb / total) * A.pdf_scale;
                 }
             }
         }
@@ -561,13 +654,6 @@ __global__ void __launch_bounds__(256) k_out_fused(const uint16_t *__restrict__ 
 }
 
 // ----------------------------------------------------------------- Adam ----
-// MLP parameters: FP32 master -> BF16 copy in the padded GEMM layout (W0 is
-// stored [64][64] with zero columns 35..63).
-struct MlpLayout {
-    int64_t woff[5], boff[5];   // offsets in the FP32 parameter vector
-    int fin[5], fout[5];
-    int64_t bw[5];              // offsets of the BF16 weight copies
-};
 
 __global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t count, float lr,
                        float b1, float b2, float eps, float c1, float c2, int64_t mlp_count,
@@ -874,21 +960,29 @@ static hipError_t backward(Model &M, const float *pos, int64_t n, int64_t stride
 static hipError_t infer(Model &M, const float *pos, const float *nrm, int64_t n, int mode, uint64_t seed,
                         uint32_t bounce, float *dir_out, float *pdf_out, float *prob_out, hipStream_t s)
 {
-    hipError_t e = forward_hidden(M, pos, nrm, n, n, s);
-    if (e != hipSuccess) return e;
     const double pi = 3.14159265358979323846;
+    InferArgs A;
+    A.gr = M.grid;
+    A.table = M.tbf;
+    A.wbf = M.wbf;
+    A.params = M.p;
+    A.lay = M.lay;
+    A.pos = pos;
+    A.nrm = nrm;
+    A.n = n;
+    A.seed = seed;
+    A.bounce = bounce;
+    A.pdf_scale = (float)(256.0 / (4.0 * pi));
+    A.dir_out = dir_out;
+    A.pdf_out = pdf_out;
+    A.prob_out = prob_out;
     const int64_t tiles = (n + 15) / 16;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cu_count() * 8));
-    const uint16_t *H3 = (const uint16_t *)M.H[3].p;
-    const uint16_t *W4 = M.wbf + M.lay.bw[4];
-    const float *b4 = M.p + M.lay.boff[4];
-    const float scale = (float)(256.0 / (4.0 * pi));
+    const unsigned grid = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((tiles + kInferWaves - 1) / kInferWaves, (int64_t)device_cu_count() * 2));
     if (mode == OUT_SAMPLE)
-        hipLaunchKernelGGL(k_out_fused<OUT_SAMPLE>, dim3(grid), dim3(256), 0, s, H3, W4, b4, n, seed, bounce,
-                           scale, dir_out, pdf_out, prob_out);
+        hipLaunchKernelGGL(k_nn_infer<OUT_SAMPLE>, dim3(grid), dim3(64 * kInferWaves), 0, s, A);
     else
-        hipLaunchKernelGGL(k_out_fused<OUT_PROB>, dim3(grid), dim3(256), 0, s, H3, W4, b4, n, seed, bounce,
-                           scale, dir_out, pdf_out, prob_out);
+        hipLaunchKernelGGL(k_nn_infer<OUT_PROB>, dim3(grid), dim3(64 * kInferWaves), 0, s, A);
     return hipGetLastError();
 }
 

@@ -94,3 +94,15 @@ def test_autotune_picks_finest_N_within_budget(env):
     assert pick in (8, 16, 32)
     t = w.get_tile(g, r["N"])
     assert t["waves_per_block"] >= 1
+
+
+def test_autotune_n_on_a_large_queue_uses_a_subset(env):
+    """Above 2 x 262,144 vertices the tile sweep runs on a strided subset; the
+    whole queue is then timed per N."""
+    torch, dev, w, room, g, sp = env
+    q = torch.from_numpy(synth.area_points(room, 600_000, 62)[0]).to(dev)
+    ref_d, ref_p = w.guide_sample(g, q, w.make_opts(N=8), seed=2, bounce=1)
+    r = w.autotune_n(g, q, 1e9, reps=1)
+    assert r["N"] == 32 and all(v > 0 for v in r["ms_per_N"].values())
+    d, p = w.guide_sample(g, q, w.make_opts(N=8), seed=2, bounce=1)
+    assert torch.equal(d, ref_d) and torch.equal(p, ref_p)

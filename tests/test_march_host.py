@@ -13,14 +13,12 @@ import synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["int64-products", "f64-products"])
-def host_lib(tmp_path_factory, request):
-    """Both forms of the exact crossing comparison (64-bit integer products,
-    FP64 products)."""
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
     out = tmp_path_factory.mktemp("host") / "march_host.so"
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
-                           "-ffp-contract=off", "-DWFPG_F64_PRODUCTS=%d" % request.param,
-                           os.path.join(HERE, "host", "march_host.cpp"), "-o", str(out)])
+                           "-ffp-contract=off", os.path.join(HERE, "host", "march_host.cpp"),
+                           "-o", str(out)])
     L = C.CDLL(str(out))
     L.host_debug_march.restype = None
     L.host_debug_march.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_int64,
