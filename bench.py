@@ -79,6 +79,11 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -93,6 +98,7 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    log("building the frame-scale room SVO and inputs")
     room = synth.room()
     svo = w.svo_build(room, 10)
     splats = synth.room_splats(room, 2_000_000, 13)
@@ -124,6 +130,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()
+    log(f"timing {args.steps} steps of accumulate + guide_sample")
     for _ in range(args.warmup):
         w.svo_accumulate(svo, *sp)
         w.guide_sample(svo, pos, opts, seed=1, bounce=0, dir_out=d_out, pdf_out=p_out)
@@ -182,16 +189,20 @@ def main():
     }
     orc = None
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
     unknown = sections - {"learned", "batching", "precision"}
     if unknown:
         raise SystemExit(f"unknown sections: {sorted(unknown)}")
     if "learned" in sections:
+        log("learned section")
         out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
     if "batching" in sections:
+        log("batching section")
         out["batching"] = batching_section(w, svo, room, cam, cnrm, args)
     if "precision" in sections:
+        log("precision section")
         out["precision"] = precision_section(w, room, sp, pos, cam, args, orc, tile)
     print(json.dumps(out))
 
@@ -235,6 +246,7 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
     nrm = torch.from_numpy(cnrm).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    log(f"training {steps} steps of {batch}")
     loss = w.guide_train(svo, tp, tn, steps=steps, batch=batch)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -305,7 +317,10 @@ def batching_section(w, svo, room, cam, cnrm, args):
     dev = torch.device("cuda:0")
     queues, sizes = synth.bounce_queues(room, cam, cnrm, 8, 15)
     qpos = [torch.from_numpy(q[0]).to(dev) for q in queues]
-    picks = [w.autotune_n(svo, qpos[b], args.budget_ns, reps=3) for b in (0, 1)]
+    picks = []
+    for b in (0, 1):
+        log(f"choosing N for bounce {b} ({sizes[b]} vertices)")
+        picks.append(w.autotune_n(svo, qpos[b], args.budget_ns, reps=3))
     Ns = [picks[0]["N"]] + [picks[1]["N"]] * (len(sizes) - 1)
     n_dev = torch.tensor(sizes, dtype=torch.int64, device=dev)
     G = w.BounceGraph(svo, qpos, n_dev, Ns, seed=7)
@@ -346,6 +361,7 @@ def precision_section(w, room, sp, pos, cam, args, orc, tile):
     opts = w.make_opts(N=args.N)
     NN = args.N * args.N
     for name, fmt in (("fp16", w.WFPG_FP16), ("bf16", w.WFPG_BF16), ("fp32", w.WFPG_FP32)):
+        log(f"precision {name}")
         g = w.svo_build(room, 10, fmt)
         w.svo_accumulate(g, *sp)
         d_out = torch.empty((3, n), device=dev)

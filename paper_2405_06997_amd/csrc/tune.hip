@@ -142,7 +142,9 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
                     t.waves_per_block = w;
                     t.lds_levels = std::min(l, svo->depth + 1);
                     t.blocks_per_cu = b;
-                    if (guide_lds_bytes(N, t) > guide_max_lds() || w * b > 32) continue;
+                    // at least 4 and at most 32 waves per CU: fewer cannot hide the
+                    // march's memory latency, more cannot be resident
+                    if (guide_lds_bytes(N, t) > guide_max_lds() || w * b > 32 || w * b < 4) continue;
                     bool dup = false;
                     for (const TileConfig &c : cand)
                         dup = dup || (c.waves_per_block == t.waves_per_block &&

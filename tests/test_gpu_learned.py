@@ -338,3 +338,22 @@ def test_uniform_enclosure_target_is_learned(orc, w, torch_dev):
     q = w.nn_forward(g, dpos, dnrm).cpu().numpy().astype(np.float64)
     kl = orc.kl_rows(np.full_like(q, 1 / 256), q)
     assert kl.mean() < 1e-4, kl.mean()
+
+
+def test_forward_full_size_configuration(orc, w, torch_dev):
+    """The configuration the bench trains (16 levels x 2^19 entries, N_min 16,
+    N_max 2^10 on a depth-10 SVO): resolutions, dense/hashed levels and the
+    forward pass agree with the oracle."""
+    rects = synth.room(n_boxes=8)
+    g = w.svo_build(rects, 10)
+    pos, nrm, _ = synth.area_points(rects, 200, 41)
+    w.guide_train(g, dev(torch_dev, pos), dev(torch_dev, nrm), steps=0)
+    cfg = orc.nn_cfg(log2_table=19, n_min=16, n_max=1024)
+    n_par = orc.nn_num_params(cfg)
+    assert w.nn_param_count(g) == n_par
+    params = nn_params.random_params(n_par, np.random.default_rng(12))
+    w.nn_set_params(g, params)
+    prob = w.nn_forward(g, dev(torch_dev, pos), dev(torch_dev, nrm)).cpu().numpy().astype(np.float64)
+    p1, _ = orc.nn_forward(params, cfg, pos, nrm, mode=1)
+    kl = orc.kl_rows(p1, prob)
+    assert kl.max() < 1e-5, kl.max()
