@@ -72,6 +72,9 @@ def lib():
             "orc_guide_pdf": (None, [vp, vp, i64, i32, f32, vp, vp]),
             "orc_guide_sample": (None, [vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp, vp]),
             "orc_pdf_eval": (None, [vp, vp, vp, i64, i32, f32, vp, vp, vp]),
+            "orc_partition": (None, [vp, vp, i64, i32, i32, vp, vp]),
+            "orc_binned_sample": (None, [vp, vp, i64, i32, i32, u64, u32, i32, f32, vp, vp, vp, vp, vp, vp,
+                                         vp]),
             "orc_march_one": (None, [vp, vp, vp, i32, i32, vp]),
             "orc_quantize": (None, [vp, vp, vp, vp]),
             "orc_round_fmt_array": (None, [vp, vp, i64, i32]),
@@ -302,6 +305,31 @@ class SVO:
         lib().orc_guide_sample(self._h, _p(pos), n, seed, bounce, N, eps,
                                _p(ctr) if ctr is not None else None, _p(d), _p(pdf), _p(b), _p(m))
         return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+    def partition(self, pos, c_ray: int, l_min: int):
+        """Positional bins (Alg. 2): (level, index within level) per query."""
+        pos = _soa(pos)
+        n = pos.shape[1]
+        lv = np.zeros(n, np.int32)
+        ix = np.zeros(n, np.int64)
+        lib().orc_partition(self._h, _p(pos), n, c_ray, l_min, _p(lv), _p(ix))
+        return lv, ix
+
+    def binned_sample(self, pos, c_ray: int, l_min: int, N: int, seed: int, bounce: int,
+                      eps: float = 0.01):
+        """Per-bin fields and member samples (Alg. 2 + Alg. 3)."""
+        pos = _soa(pos)
+        n = pos.shape[1]
+        d = np.zeros((3, n))
+        pdf = np.zeros(n)
+        b = np.zeros((n, 2), np.int32)
+        m = np.zeros((n, 2))
+        lv = np.zeros(n, np.int32)
+        ix = np.zeros(n, np.int64)
+        org = np.zeros(n, np.int64)
+        lib().orc_binned_sample(self._h, _p(pos), n, c_ray, l_min, seed, bounce, N, eps, _p(d), _p(pdf),
+                                _p(b), _p(m), _p(lv), _p(ix), _p(org))
+        return dict(dir=d, pdf=pdf, bin=b, margin=m, level=lv, index=ix, origin=org)
 
     def pdf_eval(self, pos, dirs, N: int, eps: float = 0.01):
         pos = _soa(pos)

@@ -870,6 +870,45 @@ void orc_guide_pdf(const orc_svo *s, const float *pos, int64_t n, int32_t N, flo
     free(tab);
 }
 
+/* One sample of the field L (N x N, rows v) for query i with RNG counter
+ * ctr; see orc_guide_sample. Writes entry i of the n-long outputs. */
+static void sample_field(const double *L, int N, uint64_t seed, uint32_t bounce, int64_t ctr, int64_t n,
+                         int64_t i, double *dir, double *pdf, int32_t *bin, double *margin)
+{
+    int NN = N * N;
+    double M[64], rows[64], R[64];
+    double tot = 0.0;
+    for (int v = 0; v < N; v++) {
+        double rs = 0.0;
+        for (int u = 0; u < N; u++) rs += L[v * N + u];
+        rows[v] = rs;
+        tot += rs;
+        M[v] = tot;
+    }
+    double u4[4];
+    uniforms(seed, bounce, ctr, u4);
+    double tv = u4[0] * tot;
+    int v = 0;
+    while (v < N - 1 && !(tv < M[v])) v++;
+    double acc = 0.0;
+    for (int u = 0; u < N; u++) { acc += L[v * N + u]; R[u] = acc; }
+    double tu = u4[1] * rows[v];
+    int u = 0;
+    while (u < N - 1 && !(tu < R[u])) u++;
+    double d[3];
+    orc_oct_decode((u + u4[2]) / N, (v + u4[3]) / N, d);
+    for (int k = 0; k < 3; k++) dir[k * n + i] = d[k];
+    pdf[i] = L[v * N + u] / tot * (double)NN / (4.0 * M_PI);
+    bin[2 * i] = u;
+    bin[2 * i + 1] = v;
+    if (margin) {
+        double lo = v > 0 ? M[v - 1] : 0.0, hi = M[v];
+        margin[2 * i + 1] = fmin(tv - lo, hi - tv) / tot;
+        double lo2 = u > 0 ? R[u - 1] : 0.0, hi2 = R[u];
+        margin[2 * i] = fmin(tu - lo2, hi2 - tu) / rows[v];
+    }
+}
+
 /* Inverse-CDF sampling of the piecewise-constant 2D field (Sec. 3.5): the
  * row v is the first with u1 * total < M_v (M = inclusive prefix of the row
  * sums, rows are v), the column u the first with u2 * rowsum_v < R_v[u]
@@ -888,39 +927,10 @@ void orc_guide_sample(const orc_svo *s, const float *pos, int64_t n, uint64_t se
     orc_dir_table(N, tab);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double L[4096], M[64], rows[64], R[64];
+        double L[4096];
         float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
         field_one(s, p, N, eps, tab, L, NULL);
-        double tot = 0.0;
-        for (int v = 0; v < N; v++) {
-            double rs = 0.0;
-            for (int u = 0; u < N; u++) rs += L[v * N + u];
-            rows[v] = rs;
-            tot += rs;
-            M[v] = tot;
-        }
-        double u4[4];
-        uniforms(seed, bounce, counter ? counter[i] : i, u4);
-        double tv = u4[0] * tot;
-        int v = 0;
-        while (v < N - 1 && !(tv < M[v])) v++;
-        double acc = 0.0;
-        for (int u = 0; u < N; u++) { acc += L[v * N + u]; R[u] = acc; }
-        double tu = u4[1] * rows[v];
-        int u = 0;
-        while (u < N - 1 && !(tu < R[u])) u++;
-        double d[3];
-        orc_oct_decode((u + u4[2]) / N, (v + u4[3]) / N, d);
-        for (int k = 0; k < 3; k++) dir[k * n + i] = d[k];
-        pdf[i] = L[v * N + u] / tot * (double)NN / (4.0 * M_PI);
-        bin[2 * i] = u;
-        bin[2 * i + 1] = v;
-        if (margin) {
-            double lo = v > 0 ? M[v - 1] : 0.0, hi = M[v];
-            margin[2 * i + 1] = fmin(tv - lo, hi - tv) / tot;
-            double lo2 = u > 0 ? R[u - 1] : 0.0, hi2 = R[u];
-            margin[2 * i] = fmin(tu - lo2, hi2 - tu) / rows[v];
-        }
+        sample_field(L, N, seed, bounce, counter ? counter[i] : i, n, i, dir, pdf, bin, margin);
     }
     free(tab);
 }
@@ -1022,4 +1032,138 @@ int32_t orc_num_threads(void)
         t = omp_get_num_threads();
     }
     return t;
+}
+
+/* ------------------------------------------- positional binning (Alg. 2) - */
+/* Partition-S. Each query descends to the deepest existing node that holds
+ * its quantized position (its leaf when occupied) and adds one to that node's
+ * count. Bottom-up from the leaves to level l_min, a node's total T is its own
+ * count plus its children's totals, and the node is marked when T >= c_ray or
+ * when it lies on level l_min (reading: the leaf level takes part with T = its
+ * own count). A query's bin is the deepest marked node on the path from its
+ * node to the root, the node itself included; a query whose node lies above
+ * l_min is its own bin. Output: the bin's level and index within the level. */
+void orc_partition(const orc_svo *s, const float *pos, int64_t n, int32_t c_ray, int32_t l_min,
+                   int32_t *bin_level, int64_t *bin_index)
+{
+    int D = s->depth;
+    int64_t *T[MAXD + 1];
+    for (int l = 0; l <= D; l++) T[l] = calloc((size_t)(s->n[l] ? s->n[l] : 1), sizeof(int64_t));
+    int32_t *nl = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t *ni = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; i++) {   /* DescendLeaf + AtomicAdd */
+        float p[3] = {pos[i], pos[n + i], pos[2 * n + i]}, d0[3] = {0, 0, 0};
+        qray r;
+        quantize(p, d0, &r);
+        uint32_t key = orc_morton((uint32_t)(r.O[0] >> (FINE - D)), (uint32_t)(r.O[1] >> (FINE - D)),
+                                  (uint32_t)(r.O[2] >> (FINE - D)));
+        int l = D;
+        int64_t idx = find_key(s->keys[l], s->n[l], key);
+        while (idx < 0 && l > 0) {
+            l--;
+            key >>= 3;
+            idx = find_key(s->keys[l], s->n[l], key);
+        }
+        nl[i] = idx < 0 ? -1 : l;
+        ni[i] = idx;
+        if (idx >= 0) T[l][idx] += 1;
+    }
+    uint8_t *mark[MAXD + 1];
+    for (int l = 0; l <= D; l++) mark[l] = calloc((size_t)(s->n[l] ? s->n[l] : 1), 1);
+    for (int l = D; l >= l_min && l >= 0; l--) {   /* bottom-up totals and marks */
+        if (l < D) {
+            for (int64_t c = 0; c < s->n[l + 1]; c++) {
+                int64_t par = find_key(s->keys[l], s->n[l], s->keys[l + 1][c] >> 3);
+                T[l][par] += T[l + 1][c];
+            }
+        }
+        for (int64_t k = 0; k < s->n[l]; k++) mark[l][k] = (T[l][k] >= c_ray) || (l == l_min);
+    }
+    for (int64_t i = 0; i < n; i++) {   /* AscendAndFindMarked */
+        int l = nl[i];
+        int64_t idx = ni[i];
+        if (l < 0) { bin_level[i] = -1; bin_index[i] = -1; continue; }
+        int bl = l;
+        int64_t bi = idx;
+        uint32_t key = s->keys[l][idx];
+        for (int m = l; m >= l_min && m >= 0; m--) {
+            int64_t k = find_key(s->keys[m], s->n[m], key >> (3 * (l - m)));
+            if (mark[m][k]) { bl = m; bi = k; break; }
+        }
+        bin_level[i] = bl;
+        bin_index[i] = bi;
+    }
+    for (int l = 0; l <= D; l++) { free(T[l]); free(mark[l]); }
+    free(nl);
+    free(ni);
+}
+
+/* Origin choice of a bin (SelectOrigin, Alg. 3; a random member of the bin,
+ * Sec. 4): the member minimizing (h_i, i) with h_i the first word of
+ * Philox-4x32-10 at counter (i_lo, i_hi, bounce, 1), key (seed_lo, seed_hi).
+ * The counter's last word keeps this stream apart from the sampling
+ * uniforms (which use 0). */
+static uint32_t origin_hash(uint64_t seed, uint32_t bounce, int64_t i)
+{
+    uint32_t ctr[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 1};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    orc_philox(ctr, key, o);
+    return o[0];
+}
+
+/* Binned guiding (Alg. 2 then Alg. 3): partition the queue, take each bin's
+ * origin, generate the N x N field once per bin at its origin (as
+ * orc_guide_pdf does for a vertex), and sample every member from its bin's
+ * field with the member's own uniforms (counter = its index i). Outputs as
+ * orc_guide_sample, plus the bin (level, index) and the queue index of the
+ * bin's origin per member. Queries without a bin (empty SVO) get pdf 0. */
+void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_ray, int32_t l_min,
+                       uint64_t seed, uint32_t bounce, int32_t N, float eps, double *dir, double *pdf,
+                       int32_t *bin, double *margin, int32_t *bin_level, int64_t *bin_index,
+                       int64_t *origin)
+{
+    int D = s->depth, NN = N * N;
+    orc_partition(s, pos, n, c_ray, l_min, bin_level, bin_index);
+    /* origin per bin: argmin over members of (h, i) */
+    int64_t *best[MAXD + 1];
+    uint32_t *besth[MAXD + 1];
+    for (int l = 0; l <= D; l++) {
+        size_t m = (size_t)(s->n[l] ? s->n[l] : 1);
+        best[l] = malloc(sizeof(int64_t) * m);
+        besth[l] = malloc(sizeof(uint32_t) * m);
+        for (size_t k = 0; k < m; k++) best[l][k] = -1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int l = bin_level[i];
+        if (l < 0) continue;
+        int64_t k = bin_index[i];
+        uint32_t h = origin_hash(seed, bounce, i);
+        if (best[l][k] < 0 || h < besth[l][k] || (h == besth[l][k] && i < best[l][k])) {
+            best[l][k] = i;
+            besth[l][k] = h;
+        }
+    }
+    float *tab = malloc(sizeof(float) * 3 * (size_t)NN);
+    orc_dir_table(N, tab);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        int l = bin_level[i];
+        if (l < 0) {
+            origin[i] = -1;
+            pdf[i] = 0.0;
+            for (int k = 0; k < 3; k++) dir[k * n + i] = 0.0;
+            bin[2 * i] = bin[2 * i + 1] = -1;
+            if (margin) margin[2 * i] = margin[2 * i + 1] = 0.0;
+            continue;
+        }
+        int64_t o = best[l][bin_index[i]];
+        origin[i] = o;
+        double L[4096];
+        float p[3] = {pos[o], pos[n + o], pos[2 * n + o]};
+        field_one(s, p, N, eps, tab, L, NULL);
+        sample_field(L, N, seed, bounce, i, n, i, dir, pdf, bin, margin);
+    }
+    free(tab);
+    for (int l = 0; l <= D; l++) { free(best[l]); free(besth[l]); }
 }
