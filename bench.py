@@ -66,9 +66,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
-    ap.add_argument("--sections", default="learned,batching,precision",
+    ap.add_argument("--sections", default="binned,learned,batching,precision",
                     help="comma-separated extra sections after the headline march step "
-                         "(learned, batching, precision; empty for none)")
+                         "(binned, learned, batching, precision; empty for none)")
     ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
     ap.add_argument("--train-pairs", type=int, default=50_000_000,
                     help="(vertex, march pdf) pairs the learned model is trained on")
@@ -192,9 +192,12 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
-    unknown = sections - {"learned", "batching", "precision"}
+    unknown = sections - {"binned", "learned", "batching", "precision"}
     if unknown:
         raise SystemExit(f"unknown sections: {sorted(unknown)}")
+    if "binned" in sections:
+        log("binned section")
+        out["binned"] = binned_section(w, svo, pos, n, args, gs_avg)
     if "learned" in sections:
         log("learned section")
         out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
@@ -221,6 +224,31 @@ def _timed(fn, K, warmup):
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     return sum(a.elapsed_time(b) for a, b in ev) / K
+
+
+def binned_section(w, svo, pos, n, args, march_ms):
+    """Positional binning (Alg. 2, c_ray = 512, l_min = 5 as in the paper's
+    runs) and one field per bin at a random member (Alg. 3), every member
+    sampling its bin's field: the paper's own amortization, on the headline
+    queue."""
+    import numpy as np
+    import torch
+    out = {}
+    for N in (16, 32):
+        o = w.bin_opts(N=N, c_ray=512, l_min=5)
+        d_out = torch.empty((3, n), device=pos.device)
+        p_out = torch.empty((n,), device=pos.device)
+        ms = _timed(lambda: w.guide_sample_binned(svo, pos, o, seed=5, bounce=0, dir_out=d_out, pdf_out=p_out),
+                    args.steps, args.warmup)
+        _, _, b = w.guide_sample_binned(svo, pos, o, seed=5, bounce=0, dir_out=d_out, pdf_out=p_out, bins=True)
+        bins = b.cpu().numpy()
+        nb = int(len(np.unique(bins[bins >= 0])))
+        assert torch.isfinite(p_out).all() and (p_out > 0).all()
+        out[str(N)] = {"guide_sample_binned_ms": ms, "samples_per_s": n / (ms * 1e-3), "bins": nb,
+                       "rays_per_bin": n / max(nb, 1), "field_cone_traces": nb * N * N}
+    out["c_ray"], out["l_min"] = 512, 5
+    out["speedup_vs_per_vertex_march_N16"] = march_ms / out["16"]["guide_sample_binned_ms"]
+    return out
 
 
 def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):

@@ -324,6 +324,53 @@ wfpg_status wfpg_march_counts(const wfpg_svo *svo, const float *pos, int64_t n,
                               const wfpg_opts *opts, int32_t *counts, void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Positional binning and per-bin fields (Alg. 2 Partition-S, Sec. 3.4; Alg. 3
+ * GuideRays with SelectOrigin). One field is generated per bin of nearby
+ * queries instead of one per query.
+ *  Partition-S: each query descends to the deepest existing SVO node that
+ *  holds its quantized position (its leaf when occupied) and adds one to
+ *  that node's count; bottom-up from the leaves to level l_min, a node's
+ *  total T is its own count plus its children's totals, and the node is
+ *  marked when T >= c_ray or it lies on level l_min (the leaf level takes
+ *  part with T = its own count). A query's bin is the deepest marked node on
+ *  its path to the root, the node itself included (a query whose node lies
+ *  above l_min is its own bin).
+ *  SelectOrigin: a random member of the bin, drawn as the member i with the
+ *  smallest (h_i, i), h_i = first word of Philox-4x32-10 at counter (i_lo,
+ *  i_hi, bounce, 1) and key (seed_lo, seed_hi).
+ *  The N x N field of the bin is generated at its origin exactly as
+ *  guide_pdf does for a vertex, and every member samples it with its own
+ *  uniforms (counter (i_lo, i_hi, bounce, 0)) by the guide_sample rule.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int32_t N;       /* 8, 16 or 32 (16) */
+    float eps;       /* as wfpg_opts (0.01) */
+    int32_t c_ray;   /* queries that make a bin, >= 1 (512) */
+    int32_t l_min;   /* coarsest bin level, 0..depth (5) */
+} wfpg_bin_opts;
+
+wfpg_bin_opts wfpg_default_bin_opts(void);
+
+/* The bins alone: bin_out DEVICE n int32 = global node index of each query's
+ * bin (levels are consecutive ranges of svo_level_size; -1 for an empty
+ * SVO); origin_out DEVICE n int32 (may be NULL) = queue index of the bin's
+ * origin. n < 2^31. Uses the SVO's binning scratch (calls on one SVO must be
+ * stream-ordered). */
+wfpg_status wfpg_partition(const wfpg_svo *svo, const float *pos, int64_t n, int32_t c_ray,
+                           int32_t l_min, uint64_t seed, uint32_t bounce, int32_t *bin_out,
+                           int32_t *origin_out, void *hip_stream);
+
+/* Binned guide_sample: pos DEVICE 3 x n; dir_out DEVICE 3 x n, pdf_out DEVICE
+ * n (pdf of the sampled direction under the member's bin field, 1/sr; 0 and
+ * a zero direction for a query without a bin); bin_out DEVICE n int32 (may
+ * be NULL) as wfpg_partition. Synchronizes once (to size the per-bin fields)
+ * and uses the SVO's binning scratch (calls on one SVO must be
+ * stream-ordered). Errors: EINVAL for bad arguments, n >= 2^31. */
+wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
+                                uint32_t bounce, const wfpg_bin_opts *opts, float *dir_out,
+                                float *pdf_out, int32_t *bin_out, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Learned stand-in for the march (guide_sample with opts->mode == 1).
  *
  * A multiresolution hash-grid encoding of the position (16 levels, 2^log2_table

@@ -34,6 +34,7 @@ EXPORTS = [
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
+    "wfpg_default_bin_opts", "wfpg_partition", "guide_sample_binned",
     "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
     "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
@@ -60,6 +61,10 @@ class Tile(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("mode", C.c_int32),
                 ("kl_bound", C.c_float), ("probe_stride", C.c_int32)]
+
+
+class BinOpts(C.Structure):
+    _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("c_ray", C.c_int32), ("l_min", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -117,6 +122,9 @@ def lib():
         "wfpg_debug_march": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp, vp]),
         "wfpg_autotune_n": (i32, [vp, vp, i64, i32, C.c_float, vp, C.POINTER(i32), C.POINTER(Tile),
                                   vp]),
+        "wfpg_default_bin_opts": (BinOpts, []),
+        "wfpg_partition": (i32, [vp, vp, i64, i32, i32, u64, u32, vp, vp, vp]),
+        "guide_sample_binned": (i32, [vp, vp, i64, u64, u32, C.POINTER(BinOpts), vp, vp, vp, vp]),
         "wfpg_default_train_cfg": (TrainCfg, []),
         "guide_train": (i32, [vp, vp, vp, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp]),
         "wfpg_nn_param_count": (i64, [vp]),
@@ -457,3 +465,37 @@ def learned_stats(svo: SVO) -> dict:
     fb = C.c_int64(0)
     _check("wfpg_learned_stats", lib().wfpg_learned_stats(svo.handle, C.byref(kl), C.byref(fb)))
     return {"last_probe_kl": float(kl.value), "fallbacks": int(fb.value)}
+
+
+# ------------------------------------------------------ positional binning
+
+def bin_opts(N: int = 16, eps: float = 0.01, c_ray: int = 512, l_min: int = 5) -> BinOpts:
+    return BinOpts(N, eps, c_ray, l_min)
+
+
+def partition(svo: SVO, pos, c_ray: int, l_min: int, seed: int = 0, bounce: int = 0, stream=None):
+    """(bin global node index, origin queue index) per query, int32 tensors."""
+    import torch
+    n = pos.shape[1]
+    b = torch.empty((n,), dtype=torch.int32, device=pos.device)
+    o = torch.empty((n,), dtype=torch.int32, device=pos.device)
+    _check("wfpg_partition", lib().wfpg_partition(svo.handle, _dptr(pos, 3, "pos"), n, c_ray, l_min, seed,
+                                                  bounce, _dptr(b, name="bin"), _dptr(o, name="origin"),
+                                                  _stream(stream)))
+    return b, o
+
+
+def guide_sample_binned(svo: SVO, pos, opts: BinOpts, seed: int, bounce: int, dir_out=None, pdf_out=None,
+                        bins: bool = False, stream=None):
+    """Per-bin fields sampled by every member: (dir (3, n), pdf (n,)[, bin (n,)])."""
+    import torch
+    n = pos.shape[1]
+    if dir_out is None:
+        dir_out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+    if pdf_out is None:
+        pdf_out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    b = torch.empty((n,), dtype=torch.int32, device=pos.device) if bins else None
+    _check("guide_sample_binned", lib().guide_sample_binned(
+        svo.handle, _dptr(pos, 3, "pos"), n, seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"),
+        _dptr(pdf_out, name="pdf_out"), _dptr(b, name="bin") if bins else None, _stream(stream)))
+    return (dir_out, pdf_out, b) if bins else (dir_out, pdf_out)

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libwfpg.so")
-SOURCES = ["api.hip", "build.hip", "accumulate.hip", "guide.hip", "tune.hip", "graph.hip", "nn.hip"]
+SOURCES = ["api.hip", "build.hip", "accumulate.hip", "guide.hip", "tune.hip", "graph.hip", "nn.hip", "binning.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -144,6 +144,7 @@ void free_svo(wfpg_svo *s)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->nn_model) destroy_model(s->nn_model);
+    if (s->bin_work) destroy_bin_work(s->bin_work);
     delete s;
 }
 

@@ -1,0 +1,456 @@
+// Positional binning and per-bin guiding on gfx950 (Alg. 2 Partition-S, then
+// Alg. 3 with one field per bin): queries are counted into the deepest SVO
+// node that holds them, totals are summed bottom-up over the occupancy
+// pyramid, nodes with at least c_ray queries (or on level l_min) are marked,
+// every query takes its deepest marked ancestor as its bin, each bin draws
+// one member as its origin (SelectOrigin), the guide kernel marches one
+// N x N field per bin origin, and every member samples its bin's field with
+// its own uniforms.
+//
+// Node identity is the global node index (rank + popcount over the level's
+// occupancy bitmap), so all per-node state is a flat array over the SVO's
+// nodes; no sort or partition of the queue is needed: members read their
+// bin's CDF in place.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "march_core.h"
+#include "wfpg_internal.h"
+
+namespace wfpg {
+namespace {
+
+using core::woff;
+
+// Philox-4x32-10 (Salmon et al., SC'11), the generator of the guide kernels.
+__device__ __forceinline__ void core_philox(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ bool node_index(const SvoView &sv, int l, uint32_t key, int64_t &g)
+{
+    const uint32_t wi = woff(l) + (key >> 6);
+    const uint64_t w = sv.bits[wi];
+    const uint32_t b = key & 63u;
+    if (!((w >> b) & 1ull)) return false;
+    const uint64_t below = b ? (w & ((1ull << b) - 1ull)) : 0ull;
+    g = (int64_t)sv.rank[wi] + __popcll(below);
+    return true;
+}
+
+// Level of a global node index (levels are contiguous ranges of noff).
+__device__ __forceinline__ int level_of(const SvoView &sv, int64_t g)
+{
+    int l = 0;
+    while (l < sv.depth && g >= sv.noff[l + 1]) ++l;
+    return l;
+}
+
+// DescendLeaf + AtomicAdd: the deepest existing node holding the quantized
+// position (its leaf when occupied); node_of[i] = its global index, or -1
+// for an empty SVO.
+__global__ void k_bin_count(SvoView sv, const float *__restrict__ pos, int64_t n, int32_t *node_of,
+                            uint32_t *count)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int D = sv.depth;
+    const uint32_t O0 = core::quantize_pos(pos[i]), O1 = core::quantize_pos(pos[n + i]),
+                   O2 = core::quantize_pos(pos[2 * n + i]);
+    uint32_t key = core::morton3(O0 >> (WFPG_FINE - D), O1 >> (WFPG_FINE - D), O2 >> (WFPG_FINE - D));
+    int64_t g = -1;
+    for (int l = D; l >= 0; --l, key >>= 3)
+        if (node_index(sv, l, key, g)) break;
+    node_of[i] = (int32_t)g;
+    if (g >= 0) atomicAdd(&count[g], 1u);
+}
+
+// Totals of level l (children's totals added to the node's own count, level
+// l + 1 already final) and the marks: T >= c_ray or l == l_min.
+__global__ void k_bin_level(SvoView sv, int l, int l_min, uint32_t c_ray, uint32_t *count, uint8_t *mark)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t g = sv.noff[l] + j;
+    if (g >= sv.noff[l + 1]) return;
+    uint32_t T = count[g];
+    if (l < sv.depth) {
+        const uint32_t key = sv.keys[g];
+        const uint32_t wi = woff(l + 1) + (key >> 3);
+        const uint64_t w = sv.bits[wi];
+        const uint32_t sh = 8u * (key & 7u);
+        const uint32_t kids = (uint32_t)((w >> sh) & 0xffull);
+        const int64_t base = (int64_t)sv.rank[wi] + (sh ? __popcll(w & ((1ull << sh) - 1ull)) : 0);
+        for (int c = 0; c < __popc(kids); ++c) T += count[base + c];
+        count[g] = T;
+    }
+    mark[g] = (T >= c_ray || l == l_min) ? 1 : 0;
+}
+
+// AscendAndFindMarked: bin = deepest marked node on the path from the query's
+// node up to level l_min (the node itself when it lies above l_min); the
+// bin's origin is the member with the smallest (hash, index).
+__global__ void k_bin_assign(SvoView sv, int l_min, int64_t n, uint64_t seed, uint32_t bounce,
+                             const int32_t *node_of, const uint8_t *mark, int32_t *bin_of,
+                             unsigned long long *origin_key)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g0 = node_of[i];
+    if (g0 < 0) {
+        bin_of[i] = -1;
+        return;
+    }
+    const int l0 = level_of(sv, g0);
+    const uint32_t k0 = sv.keys[g0];
+    int64_t bin = g0;
+    for (int m = l0; m >= l_min; --m) {
+        int64_t g = -1;
+        if (!node_index(sv, m, k0 >> (3 * (l0 - m)), g)) continue;   // (ancestors of a node exist)
+        if (mark[g]) {
+            bin = g;
+            break;
+        }
+    }
+    bin_of[i] = (int32_t)bin;
+    uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 1u};
+    core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    atomicMin(&origin_key[bin], ((unsigned long long)c[0] << 32) | (unsigned long long)(uint32_t)i);
+}
+
+// One slot per used bin, the slot's origin position (SoA, plane stride cap).
+__global__ void k_bin_slots(int64_t nodes, const unsigned long long *origin_key, const float *__restrict__ pos,
+                            int64_t n, int32_t *slot_of, int32_t *nbins, float *opos, int64_t cap)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nodes) return;
+    const unsigned long long k = origin_key[g];
+    if (k == ~0ull) return;
+    const int32_t s = atomicAdd(nbins, 1);
+    slot_of[g] = s;
+    if (s >= cap) return;   // never: cap bounds the used bins
+    const int64_t o = (int64_t)(uint32_t)(k & 0xffffffffull);
+    opos[s] = pos[o];
+    opos[cap + s] = pos[n + o];
+    opos[2 * cap + s] = pos[2 * n + o];
+}
+
+// Row CDFs (inclusive prefix within each field row v) and the marginal
+// (inclusive prefix of the row sums) of every bin's pdf; one thread per
+// (bin, row) for the rows, then the marginal from the row totals.
+template <int N>
+__global__ void k_bin_cdf(const float *__restrict__ pdf, const int32_t *nbins, float *rcdf, float *mcdf)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t b = t / N;
+    const int v = (int)(t % N);
+    if (b >= *nbins) return;
+    const float *p = pdf + b * N * N + v * N;
+    float *r = rcdf + b * N * N + v * N;
+    float acc = 0.f;
+    for (int u = 0; u < N; ++u) {
+        acc += p[u];
+        r[u] = acc;
+    }
+    if (v == 0) {   // marginal after the rows: recomputed from the pdf in row order
+        float m = 0.f;
+        for (int vv = 0; vv < N; ++vv) {
+            float rs = 0.f;
+            for (int u = 0; u < N; ++u) rs += pdf[b * N * N + vv * N + u];
+            m += rs;
+            mcdf[b * N + vv] = m;
+        }
+    }
+}
+
+__device__ __forceinline__ void oct_decode_f(float x, float y, float &dx, float &dy, float &dz)
+{
+    const float a = 2.f * x - 1.f, bb = 2.f * y - 1.f;
+    const float aa = fabsf(a), ab = fabsf(bb);
+    const float d = 1.f - (aa + ab);
+    const float r = 1.f - fabsf(d);
+    const float phi = r == 0.f ? 0.f : ((ab - aa) / r + 1.f) * 0.78539816339744831f;
+    const float z = (d >= 0.f ? 1.f : -1.f) * (1.f - r * r);
+    const float s = r * sqrtf(2.f - r * r);
+    float sn, cs;
+    sincosf(phi, &sn, &cs);
+    dx = (a >= 0.f ? cs : -cs) * s;
+    dy = (bb >= 0.f ? sn : -sn) * s;
+    dz = z;
+}
+
+// Every member samples its bin's field with its own uniforms (counter = its
+// queue index): row v = first with u1 * M[N-1] < M[v], column u = first with
+// u2 * R_v[N-1] < R_v[u] (clamped to N-1), direction = octahedral decode of
+// ((u + u3)/N, (v + u4)/N), pdf = the bin's pdf_b.
+template <int N>
+__global__ void k_bin_sample(int64_t n, uint64_t seed, uint32_t bounce, const int32_t *bin_of,
+                             const int32_t *slot_of, const float *__restrict__ pdf, const float *__restrict__ rcdf,
+                             const float *__restrict__ mcdf, float *dir_out, float *pdf_out, int32_t *bin_out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t bin = bin_of[i];
+    if (bin_out) bin_out[i] = bin;
+    if (bin < 0) {
+        dir_out[i] = 0.f;
+        dir_out[n + i] = 0.f;
+        dir_out[2 * n + i] = 0.f;
+        pdf_out[i] = 0.f;
+        return;
+    }
+    const int64_t s = slot_of[bin];
+    uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
+    core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
+    const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
+    const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
+    const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
+    const float *M = mcdf + s * N;
+    const float tv = u1 * M[N - 1];
+    int v = N - 1;
+    for (int k = N - 2; k >= 0; --k)
+        if (tv < M[k]) v = k;
+    const float *R = rcdf + s * N * N + v * N;
+    const float tu = u2 * R[N - 1];
+    int u = N - 1;
+    for (int k = N - 2; k >= 0; --k)
+        if (tu < R[k]) u = k;
+    const float inv = 1.f / (float)N;
+    float ox, oy, oz;
+    oct_decode_f((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
+    dir_out[i] = ox;
+    dir_out[n + i] = oy;
+    dir_out[2 * n + i] = oz;
+    pdf_out[i] = pdf[s * N * N + v * N + u];
+}
+
+// Queue index of each query's bin origin (-1 without a bin).
+__global__ void k_origin_of(int64_t n, const int32_t *bin_of, const unsigned long long *origin_key, int32_t *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = bin_of[i];
+    out[i] = b < 0 ? -1 : (int32_t)(uint32_t)(origin_key[b] & 0xffffffffull);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned nblk(int64_t n, unsigned t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+hipError_t grow(void *&p, size_t &have, size_t want)
+{
+    if (have >= want) return hipSuccess;
+    if (p) {
+        const hipError_t e = hipFree(p);
+        if (e != hipSuccess) return e;
+    }
+    p = nullptr;
+    have = 0;
+    const hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) have = want;
+    return e;
+}
+
+}  // namespace
+
+// Scratch of the binning path, owned by the SVO (grown on demand).
+struct BinWork {
+    void *count = nullptr, *mark = nullptr, *okey = nullptr, *slot = nullptr, *node_of = nullptr,
+         *bin_of = nullptr, *nbins = nullptr, *opos = nullptr, *pdf = nullptr, *rcdf = nullptr,
+         *mcdf = nullptr;
+    size_t s_count = 0, s_mark = 0, s_okey = 0, s_slot = 0, s_node = 0, s_bin = 0, s_nbins = 0, s_opos = 0,
+           s_pdf = 0, s_rcdf = 0, s_mcdf = 0;
+};
+
+void destroy_bin_work(void *w)
+{
+    BinWork *b = (BinWork *)w;
+    if (!b) return;
+    void *ps[] = {b->count, b->mark, b->okey, b->slot, b->node_of, b->bin_of, b->nbins, b->opos, b->pdf,
+                  b->rcdf, b->mcdf};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+// Partition-S on the device: bin_of (global node index per query) and the
+// origin keys; returns the number of used bins through *nbins_host when it is
+// not null (synchronizes then).
+hipError_t bin_partition(const wfpg_svo *svo, const float *pos, int64_t n, int c_ray, int l_min,
+                         uint64_t seed, uint32_t bounce, hipStream_t s, BinWork *&W)
+{
+    W = (BinWork *)svo->bin_work;
+    if (!W) {
+        W = new (std::nothrow) BinWork();
+        if (!W) return hipErrorOutOfMemory;
+        svo->bin_work = W;
+    }
+    const int64_t nodes = std::max<int64_t>(1, svo->total_nodes);
+    hipError_t e = grow(W->count, W->s_count, nodes * 4);
+    if (e == hipSuccess) e = grow(W->mark, W->s_mark, nodes);
+    if (e == hipSuccess) e = grow(W->okey, W->s_okey, nodes * 8);
+    if (e == hipSuccess) e = grow(W->slot, W->s_slot, nodes * 4);
+    if (e == hipSuccess) e = grow(W->node_of, W->s_node, n * 4);
+    if (e == hipSuccess) e = grow(W->bin_of, W->s_bin, n * 4);
+    if (e == hipSuccess) e = grow(W->nbins, W->s_nbins, 4);
+    if (e != hipSuccess) return e;
+    const SvoView v = svo->view();
+    uint32_t *count = (uint32_t *)W->count;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblk(nodes, 256)), dim3(256), 0, s, count, nodes, 0u);
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblk(nodes, 256)), dim3(256), 0, s, (unsigned long long *)W->okey, nodes,
+                       ~0ull);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t *)W->nbins, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk(n, 256)), dim3(256), 0, s, v, pos, n, (int32_t *)W->node_of, count);
+    for (int l = svo->depth; l >= l_min; --l) {
+        const int64_t m = svo->n[l];
+        if (m == 0) continue;
+        hipLaunchKernelGGL(k_bin_level, dim3(nblk(m, 256)), dim3(256), 0, s, v, l, l_min, (uint32_t)c_ray, count,
+                           (uint8_t *)W->mark);
+    }
+    hipLaunchKernelGGL(k_bin_assign, dim3(nblk(n, 256)), dim3(256), 0, s, v, l_min, n, seed, bounce,
+                       (const int32_t *)W->node_of, (const uint8_t *)W->mark, (int32_t *)W->bin_of,
+                       (unsigned long long *)W->okey);
+    return hipGetLastError();
+}
+
+}  // namespace wfpg
+
+using namespace wfpg;
+
+namespace {
+
+bool valid_bin_opts(const wfpg_svo *svo, const wfpg_bin_opts *o)
+{
+    return o && (o->N == 8 || o->N == 16 || o->N == 32) && std::isfinite(o->eps) && o->eps > 0.f &&
+           o->c_ray >= 1 && o->l_min >= 0 && o->l_min <= svo->depth;
+}
+
+wfpg_status st_of(hipError_t e, int line)
+{
+    if (e == hipSuccess) return WFPG_OK;
+    (void)note_error(e, __FILE__, line);
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? WFPG_ENOMEM : WFPG_EDEVICE;
+}
+
+template <int N>
+void launch_cdf_sample(int64_t cap, int64_t n, uint64_t seed, uint32_t bounce, BinWork *W, float *dir_out,
+                       float *pdf_out, int32_t *bin_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_cdf<N>, dim3(nblk(cap * N, 256)), dim3(256), 0, s, (const float *)W->pdf,
+                       (const int32_t *)W->nbins, (float *)W->rcdf, (float *)W->mcdf);
+    hipLaunchKernelGGL(k_bin_sample<N>, dim3(nblk(n, 256)), dim3(256), 0, s, n, seed, bounce,
+                       (const int32_t *)W->bin_of, (const int32_t *)W->slot, (const float *)W->pdf,
+                       (const float *)W->rcdf, (const float *)W->mcdf, dir_out, pdf_out, bin_out);
+}
+
+}  // namespace
+
+extern "C" {
+
+wfpg_bin_opts wfpg_default_bin_opts(void)
+{
+    wfpg_bin_opts o;
+    o.N = 16;
+    o.eps = 0.01f;
+    o.c_ray = 512;
+    o.l_min = 5;
+    return o;
+}
+
+wfpg_status wfpg_partition(const wfpg_svo *svo, const float *pos, int64_t n, int32_t c_ray, int32_t l_min,
+                           uint64_t seed, uint32_t bounce, int32_t *bin_out, int32_t *origin_out,
+                           void *hip_stream)
+{
+    if (!svo || n < 0 || n > 0x7fffffffLL || c_ray < 1 || l_min < 0 || l_min > svo->depth ||
+        (n > 0 && (!pos || !bin_out)))
+        return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    BinWork *W = nullptr;
+    hipError_t e = bin_partition(svo, pos, n, c_ray, l_min, seed, bounce, s, W);
+    if (e == hipSuccess) e = hipMemcpyAsync(bin_out, W->bin_of, n * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && origin_out) {
+        hipLaunchKernelGGL(k_origin_of, dim3(nblk(n, 256)), dim3(256), 0, s, n, (const int32_t *)W->bin_of,
+                           (const unsigned long long *)W->okey, origin_out);
+        e = hipGetLastError();
+    }
+    return st_of(e, __LINE__);
+}
+
+wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
+                                uint32_t bounce, const wfpg_bin_opts *opts, float *dir_out, float *pdf_out,
+                                int32_t *bin_out, void *hip_stream)
+{
+    if (!svo || n < 0 || n > 0x7fffffffLL || !valid_bin_opts(svo, opts) ||
+        (n > 0 && (!pos || !dir_out || !pdf_out)))
+        return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    BinWork *W = nullptr;
+    hipError_t e = bin_partition(svo, pos, n, opts->c_ray, opts->l_min, seed, bounce, s, W);
+    int32_t nb = 0;
+    // bins are nodes used by at least one query: at most min(n, nodes)
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(n, svo->total_nodes));
+    const int N = opts->N, NN = N * N;
+    if (e == hipSuccess) e = grow(W->opos, W->s_opos, cap * 3 * 4);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_bin_slots, dim3(nblk(std::max<int64_t>(1, svo->total_nodes), 256)), dim3(256), 0, s,
+                           svo->total_nodes, (const unsigned long long *)W->okey, pos, n, (int32_t *)W->slot,
+                           (int32_t *)W->nbins, (float *)W->opos, cap);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&nb, W->nbins, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (nb < 0 || nb > cap)) e = hipErrorUnknown;
+    const int64_t m = std::max<int32_t>(nb, 1);
+    if (e == hipSuccess) e = grow(W->pdf, W->s_pdf, m * NN * 4);
+    if (e == hipSuccess) e = grow(W->rcdf, W->s_rcdf, m * NN * 4);
+    if (e == hipSuccess) e = grow(W->mcdf, W->s_mcdf, m * N * 4);
+    if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
+        GuideArgs a;
+        std::memset(&a, 0, sizeof a);
+        const double pi = 3.14159265358979323846;
+        a.pos = (const float *)W->opos;
+        a.n = nb;
+        a.stride = cap;
+        a.eps = opts->eps;
+        a.omega = (float)(4.0 * pi / (double)NN);
+        a.pdf_scale = (float)((double)NN / (4.0 * pi));
+        a.dirtab = device_dirtab(N);
+        a.err = svo->d_err;
+        a.pdf_out = (float *)W->pdf;
+        e = a.dirtab ? launch_guide(svo, N, MODE_PDF, a, choose_tile(svo, N), s) : hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess) {
+        switch (N) {
+        case 8: launch_cdf_sample<8>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        case 16: launch_cdf_sample<16>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        default: launch_cdf_sample<32>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        }
+        e = hipGetLastError();
+    }
+    return st_of(e, __LINE__);
+}
+
+}  // extern "C"

@@ -124,6 +124,7 @@ TileConfig legalize_tile(TileConfig t, int N, int depth);
 
 int device_cu_count();
 void destroy_model(void *model);
+void destroy_bin_work(void *work);
 wfpg_status learned_sample(const struct ::wfpg_svo *svo, const float *pos, const float *nrm, int64_t n,
                            uint64_t seed, uint32_t bounce, const wfpg_opts *o, float *dir_out,
                            float *pdf_out, hipStream_t s);
@@ -158,6 +159,7 @@ struct wfpg_svo {
     int32_t *d_err = nullptr;
     unsigned long long *d_ctr = nullptr;   // pool of vertex-queue counters
     void *nn_model = nullptr;              // learned stand-in (nn.hip), created on demand
+    mutable void *bin_work = nullptr;      // scratch of the binned path (binning.hip)
     mutable std::atomic<unsigned> ctr_next{0};   // round-robin slot of the pool
     wfpg::SvoView view() const
     {
