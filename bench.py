@@ -234,7 +234,8 @@ def binned_section(w, svo, pos, n, args, march_ms):
     import numpy as np
     import torch
     out = {}
-    for N in (16, 32):
+    for N in (16, 32, 64, 128):
+        log(f"binned N={N}")
         o = w.bin_opts(N=N, c_ray=512, l_min=5)
         d_out = torch.empty((3, n), device=pos.device)
         p_out = torch.empty((n,), device=pos.device)

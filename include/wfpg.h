@@ -231,7 +231,7 @@ wfpg_status svo_export_accum(const wfpg_svo *svo, float *sums, uint32_t *counts,
 const char *wfpg_last_error(void);
 
 /* Host copy of the FP32 bin-centre direction table the kernels use for
- * resolution N (N*N*3 floats, AoS, bin b = v*N + u). */
+ * resolution N in {8, 16, 32, 64, 128} (N*N*3 floats, AoS, bin b = v*N + u). */
 wfpg_status wfpg_dir_table(int32_t N, float *out);
 
 /* Test-only: the traversal record of every (vertex, bin) pair, for
@@ -343,7 +343,7 @@ wfpg_status wfpg_march_counts(const wfpg_svo *svo, const float *pos, int64_t n,
  *  uniforms (counter (i_lo, i_hi, bounce, 0)) by the guide_sample rule.
  * ------------------------------------------------------------------- */
 typedef struct {
-    int32_t N;       /* 8, 16 or 32 (16) */
+    int32_t N;       /* 8, 16, 32, 64 or 128 (16); 64 and 128 as the paper's per-bin fields */
     float eps;       /* as wfpg_opts (0.01) */
     int32_t c_ray;   /* queries that make a bin, >= 1 (512) */
     int32_t l_min;   /* coarsest bin level, 0..depth (5) */

@@ -27,6 +27,7 @@
 #include <string.h>
 
 #define MAXD 10
+#define MAXN 128 /* largest field resolution (bins per side) */
 #define FINE 30 /* positions are quantized to 2^30 steps per unit length */
 
 typedef struct {
@@ -861,11 +862,12 @@ void orc_guide_pdf(const orc_svo *s, const float *pos, int64_t n, int32_t N, flo
     orc_dir_table(N, tab);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double L[4096], Lt[4096];
+        double *L = malloc(sizeof(double) * 2 * (size_t)NN), *Lt = L + NN;
         float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
         field_one(s, p, N, eps, tab, L, Lt);
         if (pdf) pdf_from_field(L, N, pdf + i * NN);
         if (pdf_truth) pdf_from_field(Lt, N, pdf_truth + i * NN);
+        free(L);
     }
     free(tab);
 }
@@ -876,7 +878,7 @@ static void sample_field(const double *L, int N, uint64_t seed, uint32_t bounce,
                          int64_t i, double *dir, double *pdf, int32_t *bin, double *margin)
 {
     int NN = N * N;
-    double M[64], rows[64], R[64];
+    double M[MAXN], rows[MAXN], R[MAXN];
     double tot = 0.0;
     for (int v = 0; v < N; v++) {
         double rs = 0.0;
@@ -927,10 +929,11 @@ void orc_guide_sample(const orc_svo *s, const float *pos, int64_t n, uint64_t se
     orc_dir_table(N, tab);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double L[4096];
+        double *L = malloc(sizeof(double) * (size_t)NN);
         float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
         field_one(s, p, N, eps, tab, L, NULL);
         sample_field(L, N, seed, bounce, counter ? counter[i] : i, n, i, dir, pdf, bin, margin);
+        free(L);
     }
     free(tab);
 }
@@ -946,7 +949,7 @@ void orc_pdf_eval(const orc_svo *s, const float *pos, const float *dir, int64_t 
     orc_dir_table(N, tab);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double L[4096], xy[2];
+        double *L = malloc(sizeof(double) * (size_t)NN), xy[2];
         float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
         orc_oct_encode(dir[i], dir[n + i], dir[2 * n + i], xy);
         int u = (int)floor(xy[0] * N), v = (int)floor(xy[1] * N);
@@ -964,6 +967,7 @@ void orc_pdf_eval(const orc_svo *s, const float *pos, const float *dir, int64_t 
             double ex = fabs(fx - rint(fx)), ey = fabs(fy - rint(fy));
             edge[i] = fmin(ex, ey);
         }
+        free(L);
     }
     free(tab);
 }
@@ -1146,7 +1150,26 @@ void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_
     }
     float *tab = malloc(sizeof(float) * 3 * (size_t)NN);
     orc_dir_table(N, tab);
-#pragma omp parallel for schedule(dynamic, 16)
+    /* the field of each bin, once, at its origin */
+    int64_t nb = 0;
+    int64_t *slot[MAXD + 1];
+    for (int l = 0; l <= D; l++) {
+        size_t m = (size_t)(s->n[l] ? s->n[l] : 1);
+        slot[l] = malloc(sizeof(int64_t) * m);
+        for (size_t k = 0; k < m; k++) slot[l][k] = best[l][k] >= 0 ? nb++ : -1;
+    }
+    double *fields = malloc(sizeof(double) * (size_t)(nb ? nb : 1) * (size_t)NN);
+    int64_t *forig = malloc(sizeof(int64_t) * (size_t)(nb ? nb : 1));
+    for (int l = 0; l <= D; l++)
+        for (int64_t k = 0; k < s->n[l]; k++)
+            if (slot[l][k] >= 0) forig[slot[l][k]] = best[l][k];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nb; b++) {
+        int64_t o = forig[b];
+        float p[3] = {pos[o], pos[n + o], pos[2 * n + o]};
+        field_one(s, p, N, eps, tab, fields + b * NN, NULL);
+    }
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; i++) {
         int l = bin_level[i];
         if (l < 0) {
@@ -1157,13 +1180,11 @@ void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_
             if (margin) margin[2 * i] = margin[2 * i + 1] = 0.0;
             continue;
         }
-        int64_t o = best[l][bin_index[i]];
-        origin[i] = o;
-        double L[4096];
-        float p[3] = {pos[o], pos[n + o], pos[2 * n + o]};
-        field_one(s, p, N, eps, tab, L, NULL);
-        sample_field(L, N, seed, bounce, i, n, i, dir, pdf, bin, margin);
+        origin[i] = best[l][bin_index[i]];
+        sample_field(fields + slot[l][bin_index[i]] * NN, N, seed, bounce, i, n, i, dir, pdf, bin, margin);
     }
     free(tab);
-    for (int l = 0; l <= D; l++) { free(best[l]); free(besth[l]); }
+    free(fields);
+    free(forig);
+    for (int l = 0; l <= D; l++) { free(best[l]); free(besth[l]); free(slot[l]); }
 }

@@ -69,10 +69,13 @@ void host_dir_table(int N, float *out)
 const float *device_dirtab(int N)
 {
     static std::mutex mu;
-    static float *tabs[64][3] = {};
+    static float *tabs[64][5] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    const int slot = N == 8 ? 0 : (N == 16 ? 1 : 2);
+    int slot = -1;   // N = 8, 16, 32, 64, 128
+    for (int k = 0; k < 5; ++k)
+        if (N == (8 << k)) slot = k;
+    if (slot < 0) return nullptr;
     std::lock_guard<std::mutex> g(mu);
     if (!tabs[dev][slot]) {
         std::vector<float> h((size_t)N * N * 3);
@@ -410,7 +413,7 @@ const char *wfpg_last_error(void)
 
 wfpg_status wfpg_dir_table(int32_t N, float *out)
 {
-    if (!out || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
+    if (!out || (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)) return WFPG_EINVAL;
     host_dir_table(N, out);
     return WFPG_OK;
 }

@@ -11,6 +11,7 @@
 // occupancy bitmap), so all per-node state is a flat array over the SVO's
 // nodes; no sort or partition of the queue is needed: members read their
 // bin's CDF in place.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +37,21 @@ __device__ __forceinline__ void core_philox(uint32_t c[4], uint32_t k0, uint32_t
         const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
     }
+}
+
+// 16-bit storage formats of the exitance and the field bins (as the guide
+// kernels store them): RNE rounding and unpacking.
+__device__ __forceinline__ float round16_bin(float f, int fmt)
+{
+    if (fmt == WFPG_FP16) return __half2float(__float2half_rn(f));
+    uint32_t u = __float_as_uint(f);
+    return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
+}
+__device__ __forceinline__ float unpack16_bin(uint32_t v, int side, int fmt)
+{
+    const uint32_t h = side ? (v >> 16) : (v & 0xffffu);
+    if (fmt == WFPG_FP16) return __half2float(__ushort_as_half((unsigned short)h));
+    return __uint_as_float(h << 16);
 }
 
 __device__ __forceinline__ bool node_index(const SvoView &sv, int l, uint32_t key, int64_t &g)
@@ -244,6 +260,80 @@ __global__ void k_origin_of(int64_t n, const int32_t *bin_of, const unsigned lon
     out[i] = b < 0 ? -1 : (int32_t)(uint32_t)(origin_key[b] & 0xffffffffull);
 }
 
+// Per-bin fields of N >= 32 (up to the paper's depth-1 128 x 128): one
+// workgroup of min(N*N, 1024) threads per bin, as the paper's block per bin.
+// Threads march cones c = tid + B j from the bin's origin with the exact
+// march, take the
+// footprint node, side and exitance as the guide kernels do, keep their
+// values in registers, reduce the field total over the block (pairwise: lane
+// sums, wave butterflies, then the 16 wave totals) and write
+// pdf_c = (L_c / total) * N^2 / (4 pi).
+template <int N>
+constexpr int bin_field_threads() { return N * N < 1024 ? N * N : 1024; }
+
+template <int N>
+__global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
+    SvoView sv, const float *__restrict__ opos, int64_t cap, const int32_t *nbins, const float *__restrict__ dirtab,
+    float eps, float omega, float pdf_scale, int lds_levels, float *pdf, int32_t *err)
+{
+    constexpr int NN = N * N, B = bin_field_threads<N>(), PER = NN / B;
+    extern __shared__ uint64_t lbits[];
+    __shared__ float wsum[16];
+    const int64_t b = blockIdx.x;
+    if (b >= *nbins) return;   // uniform over the block
+    const uint32_t nlw = woff(lds_levels);
+    for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
+    __syncthreads();
+    const uint64_t *gbits = sv.bits;
+    auto bits = [gbits, lds_levels](int lvl, uint32_t wi) -> uint64_t {
+        return lvl < lds_levels ? lbits[wi] : gbits[wi];
+    };
+    const int D = sv.depth, fmt = sv.fmt;
+    const uint32_t O[3] = {core::quantize_pos(opos[b]), core::quantize_pos(opos[cap + b]),
+                           core::quantize_pos(opos[2 * cap + b])};
+    float vals[PER];
+    float local = 0.f;
+    for (int j = 0; j < PER; ++j) {
+        const int c = threadIdx.x + B * j;
+        const float dx = dirtab[3 * c], dy = dirtab[3 * c + 1], dz = dirtab[3 * c + 2];
+        int vis = 0;
+        core::Hit h = {-1, 0u, 0u};
+        const int res = core::march(O, core::quantize_dir(dx), core::quantize_dir(dy), core::quantize_dir(dz), D,
+                                    bits, 0, vis, h);
+        if (res < 0) atomicOr(err, 1);
+        float val = fmt == WFPG_FP32 ? eps : round16_bin(eps, fmt);
+        if (res > 0) {
+            const float dsel = h.axis == 0 ? dx : (h.axis == 1 ? dy : dz);
+            const int k = core::footprint_levels(h.delta, fabsf(dsel), D, omega);
+            const int lf = D - k;
+            const uint32_t node = h.key >> (3 * k);
+            int64_t g = -1;
+            node_index(sv, lf, node, g);   // the footprint node is an ancestor of the hit leaf
+            const float4 Nn = sv.nrm[g];
+            const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
+            if (fmt == WFPG_FP32) {
+                const float2 e = sv.e32[g];
+                val = (side ? e.y : e.x) + eps;
+            } else {
+                const uint32_t pk = sv.e16[g];
+                val = round16_bin(unpack16_bin(pk, side, fmt) + eps, fmt);
+            }
+        }
+        vals[j] = val;
+        local += val;
+    }
+    for (int d = 32; d >= 1; d >>= 1) local += __shfl_xor(local, d);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+    __syncthreads();
+    float total = 0.f;
+    if (B / 64 == 1) {
+        total = wsum[0];
+    } else {
+        for (int w = 0; w < B / 64; w += 2) total += wsum[w] + wsum[w + 1];
+    }
+    for (int j = 0; j < PER; ++j) pdf[b * NN + threadIdx.x + B * j] = (vals[j] / total) * pdf_scale;
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -341,7 +431,8 @@ namespace {
 
 bool valid_bin_opts(const wfpg_svo *svo, const wfpg_bin_opts *o)
 {
-    return o && (o->N == 8 || o->N == 16 || o->N == 32) && std::isfinite(o->eps) && o->eps > 0.f &&
+    return o && (o->N == 8 || o->N == 16 || o->N == 32 || o->N == 64 || o->N == 128) && std::isfinite(o->eps) &&
+           o->eps > 0.f &&
            o->c_ray >= 1 && o->l_min >= 0 && o->l_min <= svo->depth;
 }
 
@@ -427,7 +518,28 @@ wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n
     if (e == hipSuccess) e = grow(W->pdf, W->s_pdf, m * NN * 4);
     if (e == hipSuccess) e = grow(W->rcdf, W->s_rcdf, m * NN * 4);
     if (e == hipSuccess) e = grow(W->mcdf, W->s_mcdf, m * N * 4);
-    if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
+    if (e == hipSuccess && nb > 0 && N >= 32) {   // one workgroup per bin field
+        const double pi = 3.14159265358979323846;
+        const float *tab = device_dirtab(N);
+        const int lds_levels = std::min(6, svo->depth + 1);
+        const size_t lds = (size_t)level_woff(lds_levels) * 8;
+        const SvoView v = svo->view();
+        const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
+        if (!tab) e = hipErrorOutOfMemory;
+        else if (N == 32)
+            hipLaunchKernelGGL(k_bin_field<32>, dim3((unsigned)nb), dim3(bin_field_threads<32>()), lds, s, v,
+                               (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, opts->eps, omega, scale,
+                               lds_levels, (float *)W->pdf, svo->d_err);
+        else if (N == 64)
+            hipLaunchKernelGGL(k_bin_field<64>, dim3((unsigned)nb), dim3(bin_field_threads<64>()), lds, s, v, (const float *)W->opos, cap,
+                               (const int32_t *)W->nbins, tab, opts->eps, omega, scale, lds_levels, (float *)W->pdf,
+                               svo->d_err);
+        else
+            hipLaunchKernelGGL(k_bin_field<128>, dim3((unsigned)nb), dim3(bin_field_threads<128>()), lds, s, v, (const float *)W->opos, cap,
+                               (const int32_t *)W->nbins, tab, opts->eps, omega, scale, lds_levels, (float *)W->pdf,
+                               svo->d_err);
+        if (e == hipSuccess) e = hipGetLastError();
+    } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
         GuideArgs a;
         std::memset(&a, 0, sizeof a);
         const double pi = 3.14159265358979323846;
@@ -446,7 +558,9 @@ wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n
         switch (N) {
         case 8: launch_cdf_sample<8>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
         case 16: launch_cdf_sample<16>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
-        default: launch_cdf_sample<32>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        case 32: launch_cdf_sample<32>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        case 64: launch_cdf_sample<64>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        default: launch_cdf_sample<128>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
         }
         e = hipGetLastError();
     }

@@ -72,10 +72,10 @@ def test_partition_bitexact(c1, w, torch_dev, c_ray, l_min):
     assert np.array_equal(org.cpu().numpy().astype(np.int64), r["origin"])
 
 
-@pytest.mark.parametrize("N", [8, 16])
-def test_binned_sample_matches_oracle(c1, w, torch_dev, N):
+@pytest.mark.parametrize("N,c_ray,l_min", [(8, 64, 3), (16, 64, 3), (32, 256, 2), (64, 256, 2), (128, 1024, 1)])
+def test_binned_sample_matches_oracle(c1, w, torch_dev, N, c_ray, l_min):
     o, g, pos = c1["o"], c1["g"], c1["pos"]
-    c_ray, l_min, seed, bounce = 64, 3, 21, 2
+    seed, bounce = 21, 2
     d, p, b = w.guide_sample_binned(g, dev(torch_dev, pos), w.bin_opts(N=N, c_ray=c_ray, l_min=l_min), seed,
                                     bounce, bins=True)
     d, p = d.cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64)

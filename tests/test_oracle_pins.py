@@ -344,7 +344,7 @@ def test_footprint_closed_form(orc):
 
 
 # ------------------------------------------- closed-form PDFs and invariants --
-@pytest.mark.parametrize("D,N", [(4, 8), (5, 16), (6, 8)])
+@pytest.mark.parametrize("D,N", [(4, 8), (5, 16), (6, 8), (5, 64), (4, 128)])
 def test_uniform_enclosure(orc, D, N):
     s = orc.SVO(closed_box(), D)
     s.set_uniform_exitance(1.0)
