@@ -22,6 +22,12 @@
 #include "march_core.h"
 #include "wfpg_internal.h"
 
+// Smallest field resolution generated one workgroup per bin (smaller ones go
+// through the guide kernel over the list of bin origins).
+#ifndef WFPG_BIN_FIELD_MIN_N
+#define WFPG_BIN_FIELD_MIN_N 16
+#endif
+
 namespace wfpg {
 namespace {
 
@@ -291,36 +297,71 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     const int D = sv.depth, fmt = sv.fmt;
     const uint32_t O[3] = {core::quantize_pos(opos[b]), core::quantize_pos(opos[cap + b]),
                            core::quantize_pos(opos[2 * cap + b])};
-    float vals[PER];
+    const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D), O[2] >> (WFPG_FINE - D));
+    const bool occ = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
+    float *L = reinterpret_cast<float *>(lbits + nlw);   // the bin's field values
+    // each lane marches its cones c = tid + B j one after another, a few
+    // occupancy tests at a time, so a wave waits for its busiest lane's total
+    // rather than for the longest ray of every round
+    int j = 0, it = 0;
+    bool act = false;
+    float dx = 0.f, dy = 0.f, dz = 0.f;
+    core::MicroState st;
     float local = 0.f;
-    for (int j = 0; j < PER; ++j) {
-        const int c = threadIdx.x + B * j;
-        const float dx = dirtab[3 * c], dy = dirtab[3 * c + 1], dz = dirtab[3 * c + 2];
-        int vis = 0;
+    while (true) {
+        if (!act && j < PER) {
+            const int c = threadIdx.x + B * j;
+            dx = dirtab[3 * c];
+            dy = dirtab[3 * c + 1];
+            dz = dirtab[3 * c + 2];
+            uint32_t a0, a1, a2;
+            int s0, s1, s2;
+            core::split_dir(core::quantize_dir(dx), a0, s0);
+            core::split_dir(core::quantize_dir(dy), a1, s1);
+            core::split_dir(core::quantize_dir(dz), a2, s2);
+            int vis = 0;
+            core::micro_begin(st, O, okey, occ, a0, a1, a2, s0, s1, s2, D, 0, vis);
+            act = true;
+            it = 0;
+        }
+        if (__ballot(act) == 0ull) break;   // this wave has marched all its cones
+        int res = core::STEP_CONTINUE;
         core::Hit h = {-1, 0u, 0u};
-        const int res = core::march(O, core::quantize_dir(dx), core::quantize_dir(dy), core::quantize_dir(dz), D,
-                                    bits, 0, vis, h);
-        if (res < 0) atomicOr(err, 1);
-        float val = fmt == WFPG_FP32 ? eps : round16_bin(eps, fmt);
-        if (res > 0) {
-            const float dsel = h.axis == 0 ? dx : (h.axis == 1 ? dy : dz);
-            const int k = core::footprint_levels(h.delta, fabsf(dsel), D, omega);
-            const int lf = D - k;
-            const uint32_t node = h.key >> (3 * k);
-            int64_t g = -1;
-            node_index(sv, lf, node, g);   // the footprint node is an ancestor of the hit leaf
-            const float4 Nn = sv.nrm[g];
-            const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
-            if (fmt == WFPG_FP32) {
-                const float2 e = sv.e32[g];
-                val = (side ? e.y : e.x) + eps;
-            } else {
-                const uint32_t pk = sv.e16[g];
-                val = round16_bin(unpack16_bin(pk, side, fmt) + eps, fmt);
+        if (act) {
+            int vis = 0;
+            for (int m = 0; m < 4; ++m) {
+                res = core::micro_step(st, D, bits, 0, vis, h);
+                if (res != core::STEP_CONTINUE) break;
+            }
+            if (res == core::STEP_CONTINUE && (it += 4) >= core::kMaxTests) {
+                atomicOr(err, 1);
+                res = core::STEP_MISS;
             }
         }
-        vals[j] = val;
-        local += val;
+        if (act && res != core::STEP_CONTINUE) {
+            float val = fmt == WFPG_FP32 ? eps : round16_bin(eps, fmt);
+            if (res == core::STEP_HIT) {
+                const float dsel = h.axis == 0 ? dx : (h.axis == 1 ? dy : dz);
+                const int k = core::footprint_levels(h.delta, fabsf(dsel), D, omega);
+                const int lf = D - k;
+                const uint32_t node = h.key >> (3 * k);
+                int64_t g = -1;
+                node_index(sv, lf, node, g);   // the footprint node is an ancestor of the hit leaf
+                const float4 Nn = sv.nrm[g];
+                const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
+                if (fmt == WFPG_FP32) {
+                    const float2 e = sv.e32[g];
+                    val = (side ? e.y : e.x) + eps;
+                } else {
+                    const uint32_t pk = sv.e16[g];
+                    val = round16_bin(unpack16_bin(pk, side, fmt) + eps, fmt);
+                }
+            }
+            L[threadIdx.x + B * j] = val;
+            local += val;
+            ++j;
+            act = false;
+        }
     }
     for (int d = 32; d >= 1; d >>= 1) local += __shfl_xor(local, d);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
@@ -331,7 +372,10 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     } else {
         for (int w = 0; w < B / 64; w += 2) total += wsum[w] + wsum[w + 1];
     }
-    for (int j = 0; j < PER; ++j) pdf[b * NN + threadIdx.x + B * j] = (vals[j] / total) * pdf_scale;
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + B * q;
+        pdf[b * NN + c] = (L[c] / total) * pdf_scale;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
@@ -371,6 +415,16 @@ struct BinWork {
     size_t s_count = 0, s_mark = 0, s_okey = 0, s_slot = 0, s_node = 0, s_bin = 0, s_nbins = 0, s_opos = 0,
            s_pdf = 0, s_rcdf = 0, s_mcdf = 0;
 };
+
+// One workgroup per bin: the field of each bin origin into W->pdf.
+template <int N>
+void launch_bin_field(int32_t nb, size_t lds, hipStream_t s, const SvoView &v, const BinWork *W, int64_t cap,
+                      const float *tab, float eps, float omega, float scale, int lds_levels, const wfpg_svo *svo)
+{
+    hipLaunchKernelGGL(k_bin_field<N>, dim3((unsigned)nb), dim3(bin_field_threads<N>()), lds, s, v,
+                       (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, eps, omega, scale, lds_levels,
+                       (float *)W->pdf, svo->d_err);
+}
 
 void destroy_bin_work(void *w)
 {
@@ -518,26 +572,18 @@ wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n
     if (e == hipSuccess) e = grow(W->pdf, W->s_pdf, m * NN * 4);
     if (e == hipSuccess) e = grow(W->rcdf, W->s_rcdf, m * NN * 4);
     if (e == hipSuccess) e = grow(W->mcdf, W->s_mcdf, m * N * 4);
-    if (e == hipSuccess && nb > 0 && N >= 32) {   // one workgroup per bin field
+    if (e == hipSuccess && nb > 0 && N >= WFPG_BIN_FIELD_MIN_N) {   // one workgroup per bin field
         const double pi = 3.14159265358979323846;
         const float *tab = device_dirtab(N);
         const int lds_levels = std::min(6, svo->depth + 1);
-        const size_t lds = (size_t)level_woff(lds_levels) * 8;
+        const size_t lds = (size_t)level_woff(lds_levels) * 8 + (size_t)NN * 4;   // bitmap words, field
         const SvoView v = svo->view();
         const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
         if (!tab) e = hipErrorOutOfMemory;
-        else if (N == 32)
-            hipLaunchKernelGGL(k_bin_field<32>, dim3((unsigned)nb), dim3(bin_field_threads<32>()), lds, s, v,
-                               (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, opts->eps, omega, scale,
-                               lds_levels, (float *)W->pdf, svo->d_err);
-        else if (N == 64)
-            hipLaunchKernelGGL(k_bin_field<64>, dim3((unsigned)nb), dim3(bin_field_threads<64>()), lds, s, v, (const float *)W->opos, cap,
-                               (const int32_t *)W->nbins, tab, opts->eps, omega, scale, lds_levels, (float *)W->pdf,
-                               svo->d_err);
-        else
-            hipLaunchKernelGGL(k_bin_field<128>, dim3((unsigned)nb), dim3(bin_field_threads<128>()), lds, s, v, (const float *)W->opos, cap,
-                               (const int32_t *)W->nbins, tab, opts->eps, omega, scale, lds_levels, (float *)W->pdf,
-                               svo->d_err);
+        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
         if (e == hipSuccess) e = hipGetLastError();
     } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
         GuideArgs a;
