@@ -74,7 +74,11 @@ def lib():
             "orc_pdf_eval": (None, [vp, vp, vp, i64, i32, f32, vp, vp, vp]),
             "orc_partition": (None, [vp, vp, i64, i32, i32, vp, vp]),
             "orc_binned_sample": (None, [vp, vp, i64, i32, i32, u64, u32, i32, f32, vp, vp, vp, vp, vp, vp,
-                                         vp]),
+                                         vp, vp, vp]),
+            "orc_product_fields": (None, [vp, i64, i64, i32, vp, vp, u64, u32, vp, vp, vp, vp, vp]),
+            "orc_product_pdf_fields": (None, [vp, i64, i32, vp, vp, vp, vp]),
+            "orc_product_sample": (None, [vp, vp, vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp]),
+            "orc_product_pdf_eval": (None, [vp, vp, vp, vp, vp, i64, i32, f32, vp, vp, vp]),
             "orc_march_one": (None, [vp, vp, vp, i32, i32, vp]),
             "orc_quantize": (None, [vp, vp, vp, vp]),
             "orc_round_fmt_array": (None, [vp, vp, i64, i32]),
@@ -316,10 +320,12 @@ class SVO:
         return lv, ix
 
     def binned_sample(self, pos, c_ray: int, l_min: int, N: int, seed: int, bounce: int,
-                      eps: float = 0.01):
-        """Per-bin fields and member samples (Alg. 2 + Alg. 3)."""
+                      eps: float = 0.01, nrm=None, bsdf=None):
+        """Per-bin fields and member samples (Alg. 2 + Alg. 3); with nrm or
+        bsdf every member draws a product sample (Sec. 3.6) instead."""
         pos = _soa(pos)
         n = pos.shape[1]
+        nv, bv = _product_inputs(nrm, bsdf, n)
         d = np.zeros((3, n))
         pdf = np.zeros(n)
         b = np.zeros((n, 2), np.int32)
@@ -328,8 +334,34 @@ class SVO:
         ix = np.zeros(n, np.int64)
         org = np.zeros(n, np.int64)
         lib().orc_binned_sample(self._h, _p(pos), n, c_ray, l_min, seed, bounce, N, eps, _p(d), _p(pdf),
-                                _p(b), _p(m), _p(lv), _p(ix), _p(org))
+                                _p(b), _p(m), _p(lv), _p(ix), _p(org), _opt(nv), _opt(bv))
         return dict(dir=d, pdf=pdf, bin=b, margin=m, level=lv, index=ix, origin=org)
+
+    def product_sample(self, pos, N: int, seed: int, bounce: int, nrm=None, bsdf=None, eps: float = 0.01):
+        """Product guiding (Sec. 3.6) of each vertex's own field; nrm (3 x n,
+        Lambertian cosine table) or bsdf (n x 64 table)."""
+        pos = _soa(pos)
+        n = pos.shape[1]
+        nv, bv = _product_inputs(nrm, bsdf, n, need=True)
+        d = np.zeros((3, n))
+        pdf = np.zeros(n)
+        b = np.zeros((n, 2), np.int32)
+        m = np.zeros((n, 2))
+        lib().orc_product_sample(self._h, _p(pos), _opt(nv), _opt(bv), n, seed, bounce, N, eps, _p(d), _p(pdf),
+                                 _p(b), _p(m))
+        return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+    def product_pdf_eval(self, pos, dirs, N: int, nrm=None, bsdf=None, eps: float = 0.01):
+        pos = _soa(pos)
+        dirs = _soa(dirs)
+        n = pos.shape[1]
+        nv, bv = _product_inputs(nrm, bsdf, n, need=True)
+        pdf = np.zeros(n)
+        b = np.zeros((n, 2), np.int32)
+        e = np.zeros(n)
+        lib().orc_product_pdf_eval(self._h, _p(pos), _opt(nv), _opt(bv), _p(dirs), n, N, eps, _p(pdf), _p(b),
+                                   _p(e))
+        return dict(pdf=pdf, bin=b, edge=e)
 
     def pdf_eval(self, pos, dirs, N: int, eps: float = 0.01):
         pos = _soa(pos)
@@ -340,6 +372,50 @@ class SVO:
         e = np.zeros(n)
         lib().orc_pdf_eval(self._h, _p(pos), _p(dirs), n, N, eps, _p(pdf), _p(b), _p(e))
         return dict(pdf=pdf, bin=b, edge=e)
+
+
+def _opt(a):
+    return None if a is None else _p(a)
+
+
+def _product_inputs(nrm, bsdf, n, need=False):
+    if nrm is not None and bsdf is not None:
+        raise ValueError("give nrm or bsdf, not both")
+    if need and nrm is None and bsdf is None:
+        raise ValueError("product guiding needs nrm or bsdf")
+    nv = None if nrm is None else _soa(nrm)
+    bv = None if bsdf is None else np.ascontiguousarray(bsdf, np.float32).reshape(n, 64)
+    assert nv is None or nv.shape[1] == n
+    return nv, bv
+
+
+def product_sample_fields(L, N: int, seed: int, bounce: int, nrm=None, bsdf=None, counter=None, n=None):
+    """Product sample (Sec. 3.6) from given fields L (n x N*N, rows v); a
+    single row with n given is one field shared by n queries."""
+    L = np.ascontiguousarray(L, np.float64).reshape(-1, N * N)
+    shared = n is not None and L.shape[0] == 1
+    n = L.shape[0] if n is None else n
+    assert (shared or L.shape[0] == n) and N % 8 == 0
+    nv, bv = _product_inputs(nrm, bsdf, n, need=True)
+    ctr = None if counter is None else np.ascontiguousarray(counter, np.int64)
+    d = np.zeros((3, n))
+    pdf = np.zeros(n)
+    b = np.zeros((n, 2), np.int32)
+    m = np.zeros((n, 2))
+    lib().orc_product_fields(_p(L), 0 if shared else N * N, n, N, _opt(nv), _opt(bv), seed, bounce, _opt(ctr),
+                             _p(d), _p(pdf), _p(b), _p(m))
+    return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+
+def product_pdf_fields(L, N: int, dirs, nrm=None, bsdf=None):
+    """Product pdf of directions (3 x n) under fields L (n x N*N)."""
+    L = np.ascontiguousarray(L, np.float64)
+    n = L.shape[0]
+    nv, bv = _product_inputs(nrm, bsdf, n, need=True)
+    d = np.ascontiguousarray(dirs, np.float64)
+    pdf = np.zeros(n)
+    lib().orc_product_pdf_fields(_p(L), n, N, _opt(nv), _opt(bv), _p(d), _p(pdf))
+    return pdf
 
 
 # ---------------------------------------------------------------- learned --

@@ -1116,16 +1116,24 @@ static uint32_t origin_hash(uint64_t seed, uint32_t bounce, int64_t i)
     return o[0];
 }
 
+static void product_table(const float *nrm, const float *bsdf, int64_t n, int64_t i, const float *tab8,
+                          double *f);
+static void product_one(const double *L, int N, const double *f, uint64_t seed, uint32_t bounce, int64_t ctr,
+                        int64_t n, int64_t i, double *dir, double *pdf, int32_t *bin, double *margin);
+
 /* Binned guiding (Alg. 2 then Alg. 3): partition the queue, take each bin's
  * origin, generate the N x N field once per bin at its origin (as
  * orc_guide_pdf does for a vertex), and sample every member from its bin's
  * field with the member's own uniforms (counter = its index i). Outputs as
  * orc_guide_sample, plus the bin (level, index) and the queue index of the
- * bin's origin per member. Queries without a bin (empty SVO) get pdf 0. */
+ * bin's origin per member. Queries without a bin (empty SVO) get pdf 0.
+ * With nrm or bsdf given, every member draws a product sample (below) from
+ * its bin's field and its own BSDF table, as the paper's product variant does
+ * per ray over the shared bin field. */
 void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_ray, int32_t l_min,
                        uint64_t seed, uint32_t bounce, int32_t N, float eps, double *dir, double *pdf,
                        int32_t *bin, double *margin, int32_t *bin_level, int64_t *bin_index,
-                       int64_t *origin)
+                       int64_t *origin, const float *nrm, const float *bsdf)
 {
     int D = s->depth, NN = N * N;
     orc_partition(s, pos, n, c_ray, l_min, bin_level, bin_index);
@@ -1181,10 +1189,270 @@ void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_
             continue;
         }
         origin[i] = best[l][bin_index[i]];
-        sample_field(fields + slot[l][bin_index[i]] * NN, N, seed, bounce, i, n, i, dir, pdf, bin, margin);
+        if (nrm || bsdf) {   /* product guiding: the member's own table times its bin's field */
+            double f[64];
+            float tab8[3 * 64];
+            orc_dir_table(8, tab8);
+            product_table(nrm, bsdf, n, i, tab8, f);
+            product_one(fields + slot[l][bin_index[i]] * NN, N, f, seed, bounce, i, n, i, dir, pdf, bin, margin);
+        } else {
+            sample_field(fields + slot[l][bin_index[i]] * NN, N, seed, bounce, i, n, i, dir, pdf, bin, margin);
+        }
     }
     free(tab);
     free(fields);
     free(forig);
     for (int l = 0; l <= D; l++) { free(best[l]); free(besth[l]); free(slot[l]); }
+}
+
+/* ------------------------------------------------ product guiding ------- */
+/* Product path guiding (Sec. 3.6, after the two-level product sampler of
+ * Estevez and Kulla that the paper adopts). The upper level is the N x N field
+ * subsampled to the 8 x 8 resolution of the BSDF table: cell C = (U, V) holds
+ * the s x s fine bins u in [U s, U s + s), v in [V s, V s + s), s = N / 8, and
+ * its value F_C is their sum (rows dv outer, columns du inner). The BSDF
+ * table f_C lives on the same octahedral 8 x 8 cells; it is either given per
+ * query or, for a Lambertian surface with normal n, the cosine factor
+ * max(0, n . d_C) at the cell centre d_C (the N = 8 bin-centre table). That
+ * dot product decides which cells can be sampled, so it is taken in FP32 as
+ * (n_x d_x + n_y d_y) + n_z d_z without contraction; a table entry that is
+ * not > 0 (negative, zero, NaN) counts as 0.
+ *
+ * Sampling: the cell from the product P_C = F_C f_C (marginal over rows V,
+ * then the row's CDF over U; uniforms w1, w2 = the first two words of
+ * Philox-4x32-10 at counter (i_lo, i_hi, bounce, 2)), then the fine bin inside
+ * the cell from the field restricted to it (row dv, column du; uniforms u1, u2
+ * of the plain sampler, counter word 0), then the in-bin offset (u3, u4).
+ * pdf = P_C / sum(P) * L_b / F_C * N^2 / (4 pi), i.e. the normalized product of
+ * the field with the table held constant over each cell. A row or column is
+ * the first whose inclusive CDF exceeds the target; if none does (a target
+ * rounded up to the total), the last one with positive mass. A product that
+ * sums to zero or to a non-finite value (zero or non-finite normal) is
+ * replaced by f = 1, which is plain guiding. */
+#define PCELLS 8
+
+static void product_uniforms(uint64_t seed, uint32_t bounce, int64_t i, double w[2])
+{
+    uint32_t ctr[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 2};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    orc_philox(ctr, key, o);
+    for (int k = 0; k < 2; k++) w[k] = (double)(o[k] >> 8) * (1.0 / 16777216.0);
+}
+
+/* f[64] of query i: table row i of bsdf (n x 64) or the cosine factor of the
+ * normal (SoA 3 x n); tab8 = the FP32 bin-centre table of N = 8. */
+static void product_table(const float *nrm, const float *bsdf, int64_t n, int64_t i, const float *tab8,
+                          double *f)
+{
+    for (int c = 0; c < PCELLS * PCELLS; c++) {
+        float x;
+        if (bsdf) {
+            x = bsdf[i * 64 + c];
+        } else {
+            float nv[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
+            x = dot3f(nv, tab8 + 3 * c);
+        }
+        f[c] = x > 0.0f ? (double)x : 0.0;
+    }
+}
+
+typedef struct {
+    double F[64], P[64], rows[8], M[8], total;
+} product_upper;
+
+static void product_upper_level(const double *L, int N, const double *f, product_upper *q)
+{
+    int s = N / PCELLS;
+    for (int V = 0; V < PCELLS; V++)
+        for (int U = 0; U < PCELLS; U++) {
+            double F = 0.0;
+            for (int dv = 0; dv < s; dv++)
+                for (int du = 0; du < s; du++) F += L[(V * s + dv) * N + U * s + du];
+            q->F[V * PCELLS + U] = F;
+        }
+    for (int pass = 0; pass < 2; pass++) {
+        double tot = 0.0;
+        for (int V = 0; V < PCELLS; V++) {
+            double rs = 0.0;
+            for (int U = 0; U < PCELLS; U++) {
+                int c = V * PCELLS + U;
+                q->P[c] = q->F[c] * (pass ? 1.0 : f[c]);
+                rs += q->P[c];
+            }
+            q->rows[V] = rs;
+            tot += rs;
+            q->M[V] = tot;
+        }
+        q->total = tot;
+        if (tot > 0.0 && isfinite(tot)) break;   /* else: f = 1 (plain guiding) */
+    }
+}
+
+/* first k with t < cdf[k]; else the last k with mass[k] > 0; else m - 1 */
+static int pick(const double *cdf, const double *mass, int m, double t)
+{
+    for (int k = 0; k < m; k++)
+        if (t < cdf[k]) return k;
+    for (int k = m - 1; k >= 0; k--)
+        if (mass[k] > 0.0) return k;
+    return m - 1;
+}
+
+static double rel_margin(const double *cdf, int k, double t, double scale)
+{
+    double lo = k > 0 ? cdf[k - 1] : 0.0, hi = cdf[k];
+    return fmin(fabs(t - lo), fabs(hi - t)) / scale;
+}
+
+static void product_one(const double *L, int N, const double *f, uint64_t seed, uint32_t bounce, int64_t ctr,
+                        int64_t n, int64_t i, double *dir, double *pdf, int32_t *bin, double *margin)
+{
+    int s = N / PCELLS, NN = N * N;
+    product_upper q;
+    product_upper_level(L, N, f, &q);
+    double w[2], u[4];
+    product_uniforms(seed, bounce, ctr, w);
+    uniforms(seed, bounce, ctr, u);
+    /* upper level: the cell */
+    double tv = w[0] * q.total;
+    int V = pick(q.M, q.rows, PCELLS, tv);
+    double R[PCELLS], acc = 0.0;
+    for (int U = 0; U < PCELLS; U++) { acc += q.P[V * PCELLS + U]; R[U] = acc; }
+    double tu = w[1] * q.rows[V];
+    int U = pick(R, q.P + V * PCELLS, PCELLS, tu);
+    int c = V * PCELLS + U;
+    /* lower level: the fine bin inside the cell */
+    double br[MAXN / PCELLS], BM[MAXN / PCELLS], bt = 0.0;
+    for (int dv = 0; dv < s; dv++) {
+        double rs = 0.0;
+        for (int du = 0; du < s; du++) rs += L[(V * s + dv) * N + U * s + du];
+        br[dv] = rs;
+        bt += rs;
+        BM[dv] = bt;
+    }
+    double t2 = u[0] * bt;
+    int dv = pick(BM, br, s, t2);
+    double BR[MAXN / PCELLS], bv[MAXN / PCELLS];
+    acc = 0.0;
+    for (int du = 0; du < s; du++) {
+        bv[du] = L[(V * s + dv) * N + U * s + du];
+        acc += bv[du];
+        BR[du] = acc;
+    }
+    double t3 = u[1] * br[dv];
+    int du = pick(BR, bv, s, t3);
+    int fu = U * s + du, fv = V * s + dv;
+    double d[3];
+    orc_oct_decode((fu + u[2]) / N, (fv + u[3]) / N, d);
+    for (int k = 0; k < 3; k++) dir[k * n + i] = d[k];
+    pdf[i] = q.P[c] / q.total * (L[fv * N + fu] / q.F[c]) * (double)NN / (4.0 * M_PI);
+    bin[2 * i] = fu;
+    bin[2 * i + 1] = fv;
+    if (margin) {
+        margin[2 * i] = fmin(rel_margin(q.M, V, tv, q.total), rel_margin(R, U, tu, q.rows[V]));
+        margin[2 * i + 1] = fmin(rel_margin(BM, dv, t2, bt), rel_margin(BR, du, t3, br[dv]));
+    }
+}
+
+static double product_pdf_one(const double *L, int N, const double *f, int fu, int fv)
+{
+    int s = N / PCELLS;
+    product_upper q;
+    product_upper_level(L, N, f, &q);
+    int c = (fv / s) * PCELLS + fu / s;
+    return q.P[c] / q.total * (L[fv * N + fu] / q.F[c]) * (double)(N * N) / (4.0 * M_PI);
+}
+
+static void dir_bin(double dx, double dy, double dz, int N, int *u, int *v, double *edge)
+{
+    double xy[2];
+    orc_oct_encode(dx, dy, dz, xy);
+    int a = (int)floor(xy[0] * N), b = (int)floor(xy[1] * N);
+    *u = a < 0 ? 0 : (a > N - 1 ? N - 1 : a);
+    *v = b < 0 ? 0 : (b > N - 1 ? N - 1 : b);
+    if (edge) {
+        double fx = xy[0] * N, fy = xy[1] * N;
+        *edge = fmin(fabs(fx - rint(fx)), fabs(fy - rint(fy)));
+    }
+}
+
+/* Product sampling from given fields: query i uses L + i * lstride (N*N,
+ * rows v; lstride 0 shares one field); nrm (SoA 3 x n) or bsdf (n x 64)
+ * gives each query's table. Outputs as orc_guide_sample. */
+void orc_product_fields(const double *L, int64_t lstride, int64_t n, int32_t N, const float *nrm,
+                        const float *bsdf,
+                        uint64_t seed, uint32_t bounce, const int64_t *counter, double *dir, double *pdf,
+                        int32_t *bin, double *margin)
+{
+    float tab8[3 * 64];
+    orc_dir_table(PCELLS, tab8);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        double f[64];
+        product_table(nrm, bsdf, n, i, tab8, f);
+        product_one(L + i * lstride, N, f, seed, bounce, counter ? counter[i] : i, n, i, dir, pdf, bin, margin);
+    }
+}
+
+/* Product pdf of directions dir (SoA 3 x n) under fields L (n x N*N). */
+void orc_product_pdf_fields(const double *L, int64_t n, int32_t N, const float *nrm, const float *bsdf,
+                            const double *dir, double *pdf)
+{
+    float tab8[3 * 64];
+    orc_dir_table(PCELLS, tab8);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        double f[64];
+        int u, v;
+        product_table(nrm, bsdf, n, i, tab8, f);
+        dir_bin(dir[i], dir[n + i], dir[2 * n + i], N, &u, &v, NULL);
+        pdf[i] = product_pdf_one(L + i * (int64_t)N * N, N, f, u, v);
+    }
+}
+
+/* Product guiding of a queue: each vertex's own field (as orc_guide_sample),
+ * then the two-level product sample above. */
+void orc_product_sample(const orc_svo *s, const float *pos, const float *nrm, const float *bsdf, int64_t n,
+                        uint64_t seed, uint32_t bounce, int32_t N, float eps, double *dir, double *pdf,
+                        int32_t *bin, double *margin)
+{
+    int NN = N * N;
+    float *tab = malloc(sizeof(float) * 3 * (size_t)NN), tab8[3 * 64];
+    orc_dir_table(N, tab);
+    orc_dir_table(PCELLS, tab8);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double *L = malloc(sizeof(double) * (size_t)NN), f[64];
+        float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        field_one(s, p, N, eps, tab, L, NULL);
+        product_table(nrm, bsdf, n, i, tab8, f);
+        product_one(L, N, f, seed, bounce, i, n, i, dir, pdf, bin, margin);
+        free(L);
+    }
+    free(tab);
+}
+
+/* Product pdf of arbitrary directions at the queue's vertices (MIS). */
+void orc_product_pdf_eval(const orc_svo *s, const float *pos, const float *nrm, const float *bsdf,
+                          const float *dir, int64_t n, int32_t N, float eps, double *pdf, int32_t *bin,
+                          double *edge)
+{
+    int NN = N * N;
+    float *tab = malloc(sizeof(float) * 3 * (size_t)NN), tab8[3 * 64];
+    orc_dir_table(N, tab);
+    orc_dir_table(PCELLS, tab8);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double *L = malloc(sizeof(double) * (size_t)NN), f[64];
+        float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        int u, v;
+        dir_bin(dir[i], dir[n + i], dir[2 * n + i], N, &u, &v, edge ? edge + i : NULL);
+        field_one(s, p, N, eps, tab, L, NULL);
+        product_table(nrm, bsdf, n, i, tab8, f);
+        pdf[i] = product_pdf_one(L, N, f, u, v);
+        if (bin) { bin[2 * i] = u; bin[2 * i + 1] = v; }
+        free(L);
+    }
+    free(tab);
 }
