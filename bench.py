@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
-    ap.add_argument("--sections", default="binned,learned,batching,precision",
+    ap.add_argument("--sections", default="binned,product,learned,batching,precision",
                     help="comma-separated extra sections after the headline march step "
                          "(binned, learned, batching, precision; empty for none)")
     ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
@@ -192,12 +192,15 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
-    unknown = sections - {"binned", "learned", "batching", "precision"}
+    unknown = sections - {"binned", "product", "learned", "batching", "precision"}
     if unknown:
         raise SystemExit(f"unknown sections: {sorted(unknown)}")
     if "binned" in sections:
         log("binned section")
         out["binned"] = binned_section(w, svo, pos, n, args, gs_avg)
+    if "product" in sections:
+        log("product section")
+        out["product"] = product_section(w, svo, pos, cnrm, n, args, gs_avg)
     if "learned" in sections:
         log("learned section")
         out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
@@ -249,6 +252,32 @@ def binned_section(w, svo, pos, n, args, march_ms):
                        "rays_per_bin": n / max(nb, 1), "field_cone_traces": nb * N * N}
     out["c_ray"], out["l_min"] = 512, 5
     out["speedup_vs_per_vertex_march_N16"] = march_ms / out["16"]["guide_sample_binned_ms"]
+    return out
+
+
+def product_section(w, svo, pos, cnrm, n, args, march_ms):
+    """Product path guiding (Sec. 3.6) with the Lambertian table of each
+    vertex's camera-facing normal: per vertex (own field, N = 16) and over
+    the positional bins (c_ray = 512, l_min = 5), one wave per member."""
+    import torch
+    nrm = torch.from_numpy(cnrm).to(pos.device)
+    d_out = torch.empty((3, n), device=pos.device)
+    p_out = torch.empty((n,), device=pos.device)
+    out = {}
+    log("product per vertex N=16")
+    opts = w.make_opts(N=16)
+    ms = _timed(lambda: w.guide_sample_product(svo, pos, opts, 5, 0, nrm=nrm, dir_out=d_out, pdf_out=p_out),
+                args.steps, args.warmup)
+    assert torch.isfinite(p_out).all() and (p_out > 0).all()
+    out["per_vertex_16"] = {"guide_sample_product_ms": ms, "samples_per_s": n / (ms * 1e-3),
+                            "cost_vs_plain": ms / march_ms}
+    for N in (16, 32, 64, 128):
+        log(f"product binned N={N}")
+        o = w.bin_opts(N=N, c_ray=512, l_min=5)
+        ms = _timed(lambda: w.guide_sample_binned_product(svo, pos, o, 5, 0, nrm=nrm, dir_out=d_out,
+                                                          pdf_out=p_out), args.steps, args.warmup)
+        assert torch.isfinite(p_out).all() and (p_out > 0).all()
+        out[f"binned_{N}"] = {"guide_sample_binned_product_ms": ms, "samples_per_s": n / (ms * 1e-3)}
     return out
 
 

@@ -202,6 +202,50 @@ wfpg_status pdf_eval(const wfpg_svo *svo, const float *pos, const float *dir,
                      int64_t n, const wfpg_opts *opts, float *pdf_out,
                      void *hip_stream);
 
+/* ---------------------------------------------------------------------
+ * guide_sample_product -- product path guiding (Sec. 3.6): the vertex's
+ * field (as guide_pdf, never written to memory) times an 8 x 8 BSDF table,
+ * sampled in two levels after the hierarchical product sampler the paper
+ * adopts (Estevez and Kulla).
+ *
+ *  - Upper level: cell C = 8 V + U (rows V, the same octahedral square cut
+ *    into 8 x 8) holds the s x s fine bins u in [U s, U s + s), v in
+ *    [V s, V s + s), s = N / 8; F_C = their sum; P_C = F_C * f_C.
+ *  - Table f_C: row i of bsdf (DEVICE n x 64 FP32, row-major [i][V][U]), or,
+ *    when bsdf is NULL, the Lambertian cosine factor max(0, n_i . d_C) of the
+ *    normal nrm (DEVICE 3 x n) and the cell-centre direction d_C (the N = 8
+ *    bin centres), computed in FP32 as (n_x d_x + n_y d_y) + n_z d_z. Entries
+ *    that are not > 0 count as 0. The normal should face the side the path
+ *    continues on; it need not be unit length.
+ *  - Uniforms: w1, w2 = words 0 and 1 of Philox-4x32-10 at counter (i_lo,
+ *    i_hi, bounce, 2); u1..u4 as guide_sample (counter word 0).
+ *  - Cell: row V from the product's row sums (target w1 * total), column U
+ *    within the row (target w2 * rowsum); then the fine row dv and column du
+ *    inside the cell from the field values (targets u1 * cell sum, u2 *
+ *    row sum); each pick is the first entry whose inclusive CDF exceeds the
+ *    target, else the last entry with positive mass. Direction = decode of
+ *    ((U s + du + u3)/N, (V s + dv + u4)/N).
+ *  - pdf = P_C / sum(P) * L_b / F_C * N^2 / (4 pi) (1/sr), the normalized
+ *    product of the field with the table held constant over each cell.
+ *  - A product whose total is 0 or not finite (zero or non-finite normal,
+ *    all-zero table) is sampled with f = 1: plain guiding.
+ * Exactly one of nrm, bsdf is given. dir_out DEVICE 3 x n, pdf_out DEVICE n.
+ * Errors: as guide_pdf; EINVAL when both or neither of nrm, bsdf is given.
+ * ------------------------------------------------------------------- */
+wfpg_status guide_sample_product(const wfpg_svo *svo, const float *pos, const float *nrm,
+                                 const float *bsdf, int64_t n, uint64_t seed, uint32_t bounce,
+                                 const wfpg_opts *opts, float *dir_out, float *pdf_out,
+                                 void *hip_stream);
+
+/* pdf_eval_product -- the product pdf of given directions (for MIS): the
+ * direction's fine bin (u, v), its cell C = (u / s, v / s), and the pdf of
+ * guide_sample_product for that bin (bit-identical to what that call
+ * returns for a direction it sampled). Arguments and errors as
+ * guide_sample_product and pdf_eval. */
+wfpg_status pdf_eval_product(const wfpg_svo *svo, const float *pos, const float *nrm,
+                             const float *bsdf, const float *dir, int64_t n,
+                             const wfpg_opts *opts, float *pdf_out, void *hip_stream);
+
 /* ------------------------------------------------------------ auxiliaries */
 
 /* Occupied leaves, all nodes and dropped splats so far; error_flags != 0
@@ -369,6 +413,17 @@ wfpg_status wfpg_partition(const wfpg_svo *svo, const float *pos, int64_t n, int
 wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
                                 uint32_t bounce, const wfpg_bin_opts *opts, float *dir_out,
                                 float *pdf_out, int32_t *bin_out, void *hip_stream);
+
+/* Binned product guiding (Sec. 3.6 over the bins of Alg. 2): every member
+ * draws a product sample (as guide_sample_product) from its bin's field,
+ * generated once at the bin origin, and its own table (nrm DEVICE 3 x n or
+ * bsdf DEVICE n x 64; exactly one). One wave per member, as the paper
+ * assigns one warp to a ray. Outputs and errors as guide_sample_binned;
+ * EINVAL when both or neither of nrm, bsdf is given. */
+wfpg_status guide_sample_binned_product(const wfpg_svo *svo, const float *pos, const float *nrm,
+                                        const float *bsdf, int64_t n, uint64_t seed, uint32_t bounce,
+                                        const wfpg_bin_opts *opts, float *dir_out, float *pdf_out,
+                                        int32_t *bin_out, void *hip_stream);
 
 /* ---------------------------------------------------------------------
  * Learned stand-in for the march (guide_sample with opts->mode == 1).

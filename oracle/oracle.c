@@ -878,7 +878,7 @@ static void sample_field(const double *L, int N, uint64_t seed, uint32_t bounce,
                          int64_t i, double *dir, double *pdf, int32_t *bin, double *margin)
 {
     int NN = N * N;
-    double M[MAXN], rows[MAXN], R[MAXN];
+    double M[MAXN] = {0}, rows[MAXN] = {0}, R[MAXN] = {0};
     double tot = 0.0;
     for (int v = 0; v < N; v++) {
         double rs = 0.0;
@@ -1323,7 +1323,7 @@ static void product_one(const double *L, int N, const double *f, uint64_t seed, 
     int U = pick(R, q.P + V * PCELLS, PCELLS, tu);
     int c = V * PCELLS + U;
     /* lower level: the fine bin inside the cell */
-    double br[MAXN / PCELLS], BM[MAXN / PCELLS], bt = 0.0;
+    double br[MAXN / PCELLS] = {0}, BM[MAXN / PCELLS] = {0}, bt = 0.0;
     for (int dv = 0; dv < s; dv++) {
         double rs = 0.0;
         for (int du = 0; du < s; du++) rs += L[(V * s + dv) * N + U * s + du];

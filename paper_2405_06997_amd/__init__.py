@@ -35,6 +35,7 @@ EXPORTS = [
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
     "wfpg_default_bin_opts", "wfpg_partition", "guide_sample_binned",
+    "guide_sample_product", "pdf_eval_product", "guide_sample_binned_product",
     "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
     "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
@@ -125,6 +126,10 @@ def lib():
         "wfpg_default_bin_opts": (BinOpts, []),
         "wfpg_partition": (i32, [vp, vp, i64, i32, i32, u64, u32, vp, vp, vp]),
         "guide_sample_binned": (i32, [vp, vp, i64, u64, u32, C.POINTER(BinOpts), vp, vp, vp, vp]),
+        "guide_sample_product": (i32, [vp, vp, vp, vp, i64, u64, u32, C.POINTER(Opts), vp, vp, vp]),
+        "pdf_eval_product": (i32, [vp, vp, vp, vp, vp, i64, C.POINTER(Opts), vp, vp]),
+        "guide_sample_binned_product": (i32, [vp, vp, vp, vp, i64, u64, u32, C.POINTER(BinOpts), vp, vp, vp,
+                                              vp]),
         "wfpg_default_train_cfg": (TrainCfg, []),
         "guide_train": (i32, [vp, vp, vp, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp]),
         "wfpg_nn_param_count": (i64, [vp]),
@@ -287,6 +292,47 @@ def pdf_eval(svo: SVO, pos, dirs, opts: Opts, out=None, stream=None):
         out = torch.empty((n,), dtype=torch.float32, device=pos.device)
     _check("pdf_eval", lib().pdf_eval(svo.handle, _dptr(pos, 3, "pos"), _dptr(dirs, 3, "dirs"), n,
                                       C.byref(opts), _dptr(out, name="out"), _stream(stream)))
+    return out
+
+
+def _table_ptrs(n, nrm, bsdf):
+    """(nrm, bsdf) pointers of a product call: normals (3, n) or tables (n, 64)."""
+    if bsdf is not None and bsdf.numel() != 64 * n:
+        raise ValueError("bsdf must hold n*64 floats")
+    return (_dptr(nrm, 3, "nrm") if nrm is not None else None,
+            _dptr(bsdf, name="bsdf") if bsdf is not None else None)
+
+
+def guide_sample_product(svo: SVO, pos, opts: Opts, seed: int, bounce: int, nrm=None, bsdf=None, dir_out=None,
+                         pdf_out=None, stream=None):
+    """Product guiding (Sec. 3.6): the vertex field times a BSDF table given
+    by normals nrm (3, n; Lambertian) or tables bsdf (n, 64)."""
+    import torch
+    n = pos.shape[1]
+    if dir_out is None:
+        dir_out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+    if pdf_out is None:
+        pdf_out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    if dir_out.shape != (3, n) or pdf_out.numel() != n:
+        raise ValueError("output shapes must be (3, n) and (n,)")
+    pn, pb = _table_ptrs(n, nrm, bsdf)
+    _check("guide_sample_product", lib().guide_sample_product(
+        svo.handle, _dptr(pos, 3, "pos"), pn, pb, n, seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"),
+        _dptr(pdf_out, name="pdf_out"), _stream(stream)))
+    return dir_out, pdf_out
+
+
+def pdf_eval_product(svo: SVO, pos, dirs, opts: Opts, nrm=None, bsdf=None, out=None, stream=None):
+    import torch
+    n = pos.shape[1]
+    if dirs.shape != pos.shape:
+        raise ValueError("dirs must match pos")
+    if out is None:
+        out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    pn, pb = _table_ptrs(n, nrm, bsdf)
+    _check("pdf_eval_product", lib().pdf_eval_product(svo.handle, _dptr(pos, 3, "pos"), pn, pb,
+                                                      _dptr(dirs, 3, "dirs"), n, C.byref(opts),
+                                                      _dptr(out, name="out"), _stream(stream)))
     return out
 
 
@@ -497,5 +543,22 @@ def guide_sample_binned(svo: SVO, pos, opts: BinOpts, seed: int, bounce: int, di
     b = torch.empty((n,), dtype=torch.int32, device=pos.device) if bins else None
     _check("guide_sample_binned", lib().guide_sample_binned(
         svo.handle, _dptr(pos, 3, "pos"), n, seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"),
+        _dptr(pdf_out, name="pdf_out"), _dptr(b, name="bin") if bins else None, _stream(stream)))
+    return (dir_out, pdf_out, b) if bins else (dir_out, pdf_out)
+
+
+def guide_sample_binned_product(svo: SVO, pos, opts: BinOpts, seed: int, bounce: int, nrm=None, bsdf=None,
+                                dir_out=None, pdf_out=None, bins: bool = False, stream=None):
+    """Binned product guiding: every member's table times its bin's field."""
+    import torch
+    n = pos.shape[1]
+    if dir_out is None:
+        dir_out = torch.empty((3, n), dtype=torch.float32, device=pos.device)
+    if pdf_out is None:
+        pdf_out = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    b = torch.empty((n,), dtype=torch.int32, device=pos.device) if bins else None
+    pn, pb = _table_ptrs(n, nrm, bsdf)
+    _check("guide_sample_binned_product", lib().guide_sample_binned_product(
+        svo.handle, _dptr(pos, 3, "pos"), pn, pb, n, seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"),
         _dptr(pdf_out, name="pdf_out"), _dptr(b, name="bin") if bins else None, _stream(stream)))
     return (dir_out, pdf_out, b) if bins else (dir_out, pdf_out)

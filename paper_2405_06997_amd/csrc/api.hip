@@ -318,6 +318,50 @@ wfpg_status pdf_eval(const wfpg_svo *svo, const float *pos, const float *dir, in
     return guide_common(svo, MODE_EVAL, opts, a, hip_stream);
 }
 
+// Exactly one BSDF source: normals (Lambertian table) or explicit tables.
+static bool one_table(const float *nrm, const float *bsdf) { return (nrm != nullptr) != (bsdf != nullptr); }
+
+wfpg_status guide_sample_product(const wfpg_svo *svo, const float *pos, const float *nrm, const float *bsdf,
+                                 int64_t n, uint64_t seed, uint32_t bounce, const wfpg_opts *opts, float *dir_out,
+                                 float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || opts->mode != 0 ||
+        (n > 0 && (!pos || !dir_out || !pdf_out || !one_table(nrm, bsdf))))
+        return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.n = n;
+    a.seed = seed;
+    a.bounce = bounce;
+    a.dir_out = dir_out;
+    a.pdf_out = pdf_out;
+    a.nrm_in = nrm;
+    a.bsdf_in = bsdf;
+    a.dirtab8 = device_dirtab(8);
+    if (!a.dirtab8) return WFPG_ENOMEM;
+    return guide_common(svo, MODE_PRODUCT, opts, a, hip_stream);
+}
+
+wfpg_status pdf_eval_product(const wfpg_svo *svo, const float *pos, const float *nrm, const float *bsdf,
+                             const float *dir, int64_t n, const wfpg_opts *opts, float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || opts->mode != 0 ||
+        (n > 0 && (!pos || !dir || !pdf_out || !one_table(nrm, bsdf))))
+        return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    GuideArgs a = base_args(svo, opts);
+    a.pos = pos;
+    a.dir_in = dir;
+    a.n = n;
+    a.pdf_out = pdf_out;
+    a.nrm_in = nrm;
+    a.bsdf_in = bsdf;
+    a.dirtab8 = device_dirtab(8);
+    if (!a.dirtab8) return WFPG_ENOMEM;
+    return guide_common(svo, MODE_PEVAL, opts, a, hip_stream);
+}
+
 wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n, const wfpg_opts *opts,
                              int32_t *out, int32_t *visits, void *hip_stream)
 {

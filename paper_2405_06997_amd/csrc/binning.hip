@@ -20,6 +20,7 @@
 #include <new>
 
 #include "march_core.h"
+#include "product_core.h"
 #include "wfpg_internal.h"
 
 // Smallest field resolution generated one workgroup per bin (smaller ones go
@@ -121,33 +122,50 @@ __global__ void k_bin_level(SvoView sv, int l, int l_min, uint32_t c_ray, uint32
 
 // AscendAndFindMarked: bin = deepest marked node on the path from the query's
 // node up to level l_min (the node itself when it lies above l_min); the
-// bin's origin is the member with the smallest (hash, index).
-__global__ void k_bin_assign(SvoView sv, int l_min, int64_t n, uint64_t seed, uint32_t bounce,
-                             const int32_t *node_of, const uint8_t *mark, int32_t *bin_of,
-                             unsigned long long *origin_key)
+// bin's origin is the member with the smallest (hash, index). Neighbouring
+// queue entries mostly share a bin, so each wave first folds the keys of equal
+// bins (every partial minimum is over members of one bin, so any subset is
+// correct) and only the first lane of each run of equal bins issues the
+// atomic; the run head's fold covers its whole run.
+__global__ void __launch_bounds__(256) k_bin_assign(SvoView sv, int l_min, int64_t n, uint64_t seed,
+                                                    uint32_t bounce, const int32_t *node_of, const uint8_t *mark,
+                                                    int32_t *bin_of, unsigned long long *origin_key)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t g0 = node_of[i];
-    if (g0 < 0) {
-        bin_of[i] = -1;
-        return;
-    }
-    const int l0 = level_of(sv, g0);
-    const uint32_t k0 = sv.keys[g0];
-    int64_t bin = g0;
-    for (int m = l0; m >= l_min; --m) {
-        int64_t g = -1;
-        if (!node_index(sv, m, k0 >> (3 * (l0 - m)), g)) continue;   // (ancestors of a node exist)
-        if (mark[g]) {
-            bin = g;
-            break;
+    const int lane = threadIdx.x & 63;
+    int32_t bin = -1;
+    unsigned long long key = ~0ull;
+    if (i < n) {
+        const int32_t g0 = node_of[i];
+        if (g0 >= 0) {
+            const int l0 = level_of(sv, g0);
+            const uint32_t k0 = sv.keys[g0];
+            int64_t b = g0;
+            for (int m = l0; m >= l_min; --m) {
+                int64_t g = -1;
+                if (!node_index(sv, m, k0 >> (3 * (l0 - m)), g)) continue;   // (ancestors of a node exist)
+                if (mark[g]) {
+                    b = g;
+                    break;
+                }
+            }
+            bin = (int32_t)b;
+            uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 1u};
+            core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+            key = ((unsigned long long)c[0] << 32) | (unsigned long long)(uint32_t)i;
         }
+        bin_of[i] = bin;
     }
-    bin_of[i] = (int32_t)bin;
-    uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 1u};
-    core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    atomicMin(&origin_key[bin], ((unsigned long long)c[0] << 32) | (unsigned long long)(uint32_t)i);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t lo = __shfl_down((uint32_t)key, off);
+        const uint32_t hi = __shfl_down((uint32_t)(key >> 32), off);
+        const int32_t ob = __shfl_down(bin, off);
+        const unsigned long long ok = ((unsigned long long)hi << 32) | lo;
+        if (lane + off < 64 && ob == bin && ok < key) key = ok;
+    }
+    const int32_t prev = __shfl_up(bin, 1);
+    if (bin >= 0 && (lane == 0 || prev != bin)) atomicMin(&origin_key[bin], key);
 }
 
 // One slot per used bin, the slot's origin position (SoA, plane stride cap).
@@ -255,6 +273,79 @@ __global__ void k_bin_sample(int64_t n, uint64_t seed, uint32_t bounce, const in
     dir_out[n + i] = oy;
     dir_out[2 * n + i] = oz;
     pdf_out[i] = pdf[s * N * N + v * N + u];
+}
+
+// Upper-level cell sums of every bin field for product guiding (thread per
+// (bin, cell)), rows dv outer and columns du inner as the per-vertex path.
+template <int N>
+__global__ void k_bin_coarse(const float *__restrict__ pdf, const int32_t *nbins, float *coarse)
+{
+    constexpr int SB = N / prod::kCells;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t b = t >> 6;
+    if (b >= *nbins) return;
+    const int c = (int)(t & 63), V = c >> 3, U = c & 7;
+    const float *p = pdf + b * N * N + (V * SB) * N + U * SB;
+    float F = 0.f;
+    for (int dv = 0; dv < SB; ++dv)
+        for (int du = 0; du < SB; ++du) F += p[dv * N + du];
+    coarse[t] = F;
+}
+
+// Product sample of every member (Sec. 3.6), one wave per member as the paper
+// gives a warp to a ray: lane C takes cell C's sum of the member's bin field
+// and the member's table entry, the wave picks the cell, then the fine bin
+// inside it from the bin field. Grid-stride over members.
+template <int N>
+__global__ void __launch_bounds__(256) k_bin_product(int64_t n, uint64_t seed, uint32_t bounce,
+                                                     const int32_t *bin_of, const int32_t *slot_of,
+                                                     const float *__restrict__ pdf, const float *__restrict__ coarse,
+                                                     const float *nrm, const float *bsdf, const float *tab8,
+                                                     float scale, float *dir_out, float *pdf_out, int32_t *bin_out)
+{
+    constexpr int SB = N / prod::kCells;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += waves) {
+        const int32_t bin = bin_of[i];   // wave-uniform: one member per wave
+        if (lane == 0 && bin_out) bin_out[i] = bin;
+        if (bin < 0) {
+            if (lane == 0) {
+                dir_out[i] = 0.f;
+                dir_out[n + i] = 0.f;
+                dir_out[2 * n + i] = 0.f;
+                pdf_out[i] = 0.f;
+            }
+            continue;
+        }
+        const int64_t sl = slot_of[bin];
+        prod::Upper q;
+        prod::upper_level(coarse[sl * 64 + lane], prod::table_entry(nrm, bsdf, i, n, tab8, lane), lane, q);
+        uint32_t w[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 2u};
+        core_philox(w, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const int c = prod::pick_cell(q, (float)(w[0] >> 8) * 5.9604644775390625e-8f,
+                                      (float)(w[1] >> 8) * 5.9604644775390625e-8f, lane);
+        uint32_t r[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
+        core_philox(r, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const int V = c >> 3, U = c & 7;
+        const float *blk = pdf + sl * N * N + (V * SB) * N + U * SB;
+        int dv = 0, du = 0;
+        const float Lb = prod::pick_fine<SB>([&](int y, int x) { return blk[y * N + x]; },
+                                             (float)(r[0] >> 8) * 5.9604644775390625e-8f,
+                                             (float)(r[1] >> 8) * 5.9604644775390625e-8f, lane, dv, du);
+        const float Pc = __shfl(q.P, c), Fc = __shfl(q.F, c);
+        if (lane == 0) {
+            const float inv = 1.f / (float)N;
+            const float u3 = (float)(r[2] >> 8) * 5.9604644775390625e-8f;
+            const float u4 = (float)(r[3] >> 8) * 5.9604644775390625e-8f;
+            float ox, oy, oz;
+            oct_decode_f((float)(U * SB + du) * inv + u3 * inv, (float)(V * SB + dv) * inv + u4 * inv, ox, oy, oz);
+            dir_out[i] = ox;
+            dir_out[n + i] = oy;
+            dir_out[2 * n + i] = oz;
+            pdf_out[i] = (Pc / q.total) * (Lb / Fc) * scale;
+        }
+    }
 }
 
 // Queue index of each query's bin origin (-1 without a bin).
@@ -411,9 +502,9 @@ hipError_t grow(void *&p, size_t &have, size_t want)
 struct BinWork {
     void *count = nullptr, *mark = nullptr, *okey = nullptr, *slot = nullptr, *node_of = nullptr,
          *bin_of = nullptr, *nbins = nullptr, *opos = nullptr, *pdf = nullptr, *rcdf = nullptr,
-         *mcdf = nullptr;
+         *mcdf = nullptr, *coarse = nullptr;
     size_t s_count = 0, s_mark = 0, s_okey = 0, s_slot = 0, s_node = 0, s_bin = 0, s_nbins = 0, s_opos = 0,
-           s_pdf = 0, s_rcdf = 0, s_mcdf = 0;
+           s_pdf = 0, s_rcdf = 0, s_mcdf = 0, s_coarse = 0;
 };
 
 // One workgroup per bin: the field of each bin origin into W->pdf.
@@ -431,7 +522,7 @@ void destroy_bin_work(void *w)
     BinWork *b = (BinWork *)w;
     if (!b) return;
     void *ps[] = {b->count, b->mark, b->okey, b->slot, b->node_of, b->bin_of, b->nbins, b->opos, b->pdf,
-                  b->rcdf, b->mcdf};
+                  b->rcdf, b->mcdf, b->coarse};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete b;
@@ -509,6 +600,74 @@ void launch_cdf_sample(int64_t cap, int64_t n, uint64_t seed, uint32_t bounce, B
                        (const float *)W->rcdf, (const float *)W->mcdf, dir_out, pdf_out, bin_out);
 }
 
+template <int N>
+void launch_product(int64_t m, int64_t n, uint64_t seed, uint32_t bounce, const BinWork *W, const float *nrm,
+                    const float *bsdf, const float *tab8, float *dir_out, float *pdf_out, int32_t *bin_out,
+                    hipStream_t s)
+{
+    const double pi = 3.14159265358979323846;
+    hipLaunchKernelGGL(k_bin_coarse<N>, dim3(nblk(m * 64, 256)), dim3(256), 0, s, (const float *)W->pdf,
+                       (const int32_t *)W->nbins, (float *)W->coarse);
+    const int64_t blocks = std::min<int64_t>(nblk(n, 4), (int64_t)1 << 20);   // 4 members per block
+    hipLaunchKernelGGL(k_bin_product<N>, dim3((unsigned)blocks), dim3(256), 0, s, n, seed, bounce,
+                       (const int32_t *)W->bin_of, (const int32_t *)W->slot, (const float *)W->pdf,
+                       (const float *)W->coarse, nrm, bsdf, tab8, (float)((double)(N * N) / (4.0 * pi)), dir_out,
+                       pdf_out, bin_out);
+}
+
+// Partition-S, bin slots and one field per used bin (normalized pdf values in
+// W->pdf, slot-major); m = max(1, used bins). Synchronizes once.
+hipError_t binned_fields(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed, uint32_t bounce,
+                         const wfpg_bin_opts *opts, hipStream_t s, BinWork *&W, int64_t &m)
+{
+    hipError_t e = bin_partition(svo, pos, n, opts->c_ray, opts->l_min, seed, bounce, s, W);
+    int32_t nb = 0;
+    // bins are nodes used by at least one query: at most min(n, nodes)
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(n, svo->total_nodes));
+    const int N = opts->N, NN = N * N;
+    if (e == hipSuccess) e = grow(W->opos, W->s_opos, cap * 3 * 4);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_bin_slots, dim3(nblk(std::max<int64_t>(1, svo->total_nodes), 256)), dim3(256), 0, s,
+                           svo->total_nodes, (const unsigned long long *)W->okey, pos, n, (int32_t *)W->slot,
+                           (int32_t *)W->nbins, (float *)W->opos, cap);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&nb, W->nbins, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (nb < 0 || nb > cap)) e = hipErrorUnknown;
+    m = std::max<int32_t>(nb, 1);
+    if (e == hipSuccess) e = grow(W->pdf, W->s_pdf, m * NN * 4);
+    if (e == hipSuccess && nb > 0 && N >= WFPG_BIN_FIELD_MIN_N) {   // one workgroup per bin field
+        const double pi = 3.14159265358979323846;
+        const float *tab = device_dirtab(N);
+        const int lds_levels = std::min(6, svo->depth + 1);
+        const size_t lds = (size_t)level_woff(lds_levels) * 8 + (size_t)NN * 4;   // bitmap words, field
+        const SvoView v = svo->view();
+        const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
+        if (!tab) e = hipErrorOutOfMemory;
+        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        if (e == hipSuccess) e = hipGetLastError();
+    } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
+        GuideArgs a;
+        std::memset(&a, 0, sizeof a);
+        const double pi = 3.14159265358979323846;
+        a.pos = (const float *)W->opos;
+        a.n = nb;
+        a.stride = cap;
+        a.eps = opts->eps;
+        a.omega = (float)(4.0 * pi / (double)NN);
+        a.pdf_scale = (float)((double)NN / (4.0 * pi));
+        a.dirtab = device_dirtab(N);
+        a.err = svo->d_err;
+        a.pdf_out = (float *)W->pdf;
+        e = a.dirtab ? launch_guide(svo, N, MODE_PDF, a, choose_tile(svo, N), s) : hipErrorOutOfMemory;
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -553,53 +712,11 @@ wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n
     if (n == 0) return WFPG_OK;
     hipStream_t s = (hipStream_t)hip_stream;
     BinWork *W = nullptr;
-    hipError_t e = bin_partition(svo, pos, n, opts->c_ray, opts->l_min, seed, bounce, s, W);
-    int32_t nb = 0;
-    // bins are nodes used by at least one query: at most min(n, nodes)
-    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(n, svo->total_nodes));
-    const int N = opts->N, NN = N * N;
-    if (e == hipSuccess) e = grow(W->opos, W->s_opos, cap * 3 * 4);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_bin_slots, dim3(nblk(std::max<int64_t>(1, svo->total_nodes), 256)), dim3(256), 0, s,
-                           svo->total_nodes, (const unsigned long long *)W->okey, pos, n, (int32_t *)W->slot,
-                           (int32_t *)W->nbins, (float *)W->opos, cap);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(&nb, W->nbins, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess && (nb < 0 || nb > cap)) e = hipErrorUnknown;
-    const int64_t m = std::max<int32_t>(nb, 1);
-    if (e == hipSuccess) e = grow(W->pdf, W->s_pdf, m * NN * 4);
-    if (e == hipSuccess) e = grow(W->rcdf, W->s_rcdf, m * NN * 4);
+    int64_t m = 1;
+    const int N = opts->N;
+    hipError_t e = binned_fields(svo, pos, n, seed, bounce, opts, s, W, m);
+    if (e == hipSuccess) e = grow(W->rcdf, W->s_rcdf, m * N * N * 4);
     if (e == hipSuccess) e = grow(W->mcdf, W->s_mcdf, m * N * 4);
-    if (e == hipSuccess && nb > 0 && N >= WFPG_BIN_FIELD_MIN_N) {   // one workgroup per bin field
-        const double pi = 3.14159265358979323846;
-        const float *tab = device_dirtab(N);
-        const int lds_levels = std::min(6, svo->depth + 1);
-        const size_t lds = (size_t)level_woff(lds_levels) * 8 + (size_t)NN * 4;   // bitmap words, field
-        const SvoView v = svo->view();
-        const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
-        if (!tab) e = hipErrorOutOfMemory;
-        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        if (e == hipSuccess) e = hipGetLastError();
-    } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
-        GuideArgs a;
-        std::memset(&a, 0, sizeof a);
-        const double pi = 3.14159265358979323846;
-        a.pos = (const float *)W->opos;
-        a.n = nb;
-        a.stride = cap;
-        a.eps = opts->eps;
-        a.omega = (float)(4.0 * pi / (double)NN);
-        a.pdf_scale = (float)((double)NN / (4.0 * pi));
-        a.dirtab = device_dirtab(N);
-        a.err = svo->d_err;
-        a.pdf_out = (float *)W->pdf;
-        e = a.dirtab ? launch_guide(svo, N, MODE_PDF, a, choose_tile(svo, N), s) : hipErrorOutOfMemory;
-    }
     if (e == hipSuccess) {
         switch (N) {
         case 8: launch_cdf_sample<8>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
@@ -607,6 +724,36 @@ wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n
         case 32: launch_cdf_sample<32>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
         case 64: launch_cdf_sample<64>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
         default: launch_cdf_sample<128>(m, n, seed, bounce, W, dir_out, pdf_out, bin_out, s); break;
+        }
+        e = hipGetLastError();
+    }
+    return st_of(e, __LINE__);
+}
+
+wfpg_status guide_sample_binned_product(const wfpg_svo *svo, const float *pos, const float *nrm,
+                                        const float *bsdf, int64_t n, uint64_t seed, uint32_t bounce,
+                                        const wfpg_bin_opts *opts, float *dir_out, float *pdf_out,
+                                        int32_t *bin_out, void *hip_stream)
+{
+    if (!svo || n < 0 || n > 0x7fffffffLL || !valid_bin_opts(svo, opts) ||
+        (n > 0 && (!pos || !dir_out || !pdf_out || (nrm != nullptr) == (bsdf != nullptr))))
+        return WFPG_EINVAL;
+    if (n == 0) return WFPG_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    BinWork *W = nullptr;
+    int64_t m = 1;
+    const int N = opts->N;
+    const float *tab8 = device_dirtab(8);
+    if (!tab8) return WFPG_ENOMEM;
+    hipError_t e = binned_fields(svo, pos, n, seed, bounce, opts, s, W, m);
+    if (e == hipSuccess) e = grow(W->coarse, W->s_coarse, m * 64 * 4);
+    if (e == hipSuccess) {
+        switch (N) {
+        case 8: launch_product<8>(m, n, seed, bounce, W, nrm, bsdf, tab8, dir_out, pdf_out, bin_out, s); break;
+        case 16: launch_product<16>(m, n, seed, bounce, W, nrm, bsdf, tab8, dir_out, pdf_out, bin_out, s); break;
+        case 32: launch_product<32>(m, n, seed, bounce, W, nrm, bsdf, tab8, dir_out, pdf_out, bin_out, s); break;
+        case 64: launch_product<64>(m, n, seed, bounce, W, nrm, bsdf, tab8, dir_out, pdf_out, bin_out, s); break;
+        default: launch_product<128>(m, n, seed, bounce, W, nrm, bsdf, tab8, dir_out, pdf_out, bin_out, s); break;
         }
         e = hipGetLastError();
     }

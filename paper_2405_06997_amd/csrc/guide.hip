@@ -13,6 +13,7 @@
 #include <atomic>
 
 #include "march_core.h"
+#include "product_core.h"
 #include "wfpg_internal.h"
 
 namespace wfpg {
@@ -113,7 +114,7 @@ constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
 // lane (for the count mode).
 template <int N, int MODE>
 __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, const float *ldir,
-                                         const uint32_t *rec, int64_t i, int64_t ps, int lane,
+                                         uint32_t *rec, int64_t i, int64_t ps, int lane,
                                          int vis_lane)
 {
     constexpr int NN = N * N;
@@ -187,6 +188,60 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
             a.dbg_out[2 * i] = vt;
             a.dbg_out[2 * i + 1] = hit_sum;
         }
+        return;
+    }
+    if constexpr (MODE == MODE_PRODUCT || MODE == MODE_PEVAL) {
+        // the slot's records are consumed: its LDS holds the field for the two levels
+        constexpr int SB = N / prod::kCells;
+        float *lv = reinterpret_cast<float *>(rec);
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) lv[j * 64 + lane] = L[j];
+        wave_lds_fence();
+        const int cv = lane >> 3, cu = lane & 7;
+        float F = 0.f;
+#pragma unroll
+        for (int dv = 0; dv < SB; ++dv)
+#pragma unroll
+            for (int du = 0; du < SB; ++du) F += lv[(cv * SB + dv) * N + cu * SB + du];
+        prod::Upper q;
+        prod::upper_level(F, prod::table_entry(a.nrm_in, a.bsdf_in, i, ps, a.dirtab8, lane), lane, q);
+        int c, fu, fv;
+        float Lb;
+        if constexpr (MODE == MODE_PRODUCT) {
+            uint32_t w[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 2u};
+            philox(w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            c = prod::pick_cell(q, (float)(w[0] >> 8) * 5.9604644775390625e-8f,
+                                (float)(w[1] >> 8) * 5.9604644775390625e-8f, lane);
+            uint32_t r[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
+            philox(r, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            const float u1 = (float)(r[0] >> 8) * 5.9604644775390625e-8f;
+            const float u2 = (float)(r[1] >> 8) * 5.9604644775390625e-8f;
+            const int V = c >> 3, U = c & 7;
+            int dv = 0, du = 0;
+            Lb = prod::pick_fine<SB>([&](int y, int x) { return lv[(V * SB + y) * N + U * SB + x]; }, u1, u2,
+                                     lane, dv, du);
+            fu = U * SB + du;
+            fv = V * SB + dv;
+            if (lane == 0) {
+                const float inv = 1.f / (float)N;
+                const float u3 = (float)(r[2] >> 8) * 5.9604644775390625e-8f;
+                const float u4 = (float)(r[3] >> 8) * 5.9604644775390625e-8f;
+                float ox, oy, oz;
+                oct_decode((float)fu * inv + u3 * inv, (float)fv * inv + u4 * inv, ox, oy, oz);
+                a.dir_out[i] = ox;
+                a.dir_out[ps + i] = oy;
+                a.dir_out[2 * ps + i] = oz;
+            }
+        } else {
+            float ex, ey;
+            oct_encode(a.dir_in[i], a.dir_in[ps + i], a.dir_in[2 * ps + i], ex, ey);
+            fu = min(max((int)floorf(ex * (float)N), 0), N - 1);
+            fv = min(max((int)floorf(ey * (float)N), 0), N - 1);
+            c = (fv / SB) * prod::kCells + fu / SB;
+            Lb = lv[fv * N + fu];
+        }
+        const float Pc = __shfl(q.P, c), Fc = __shfl(q.F, c);
+        if (lane == 0) a.pdf_out[i] = (Pc / q.total) * (Lb / Fc) * a.pdf_scale;
         return;
     }
     // row CDFs (segmented inclusive scans), marginal CDF over the row sums
@@ -485,8 +540,8 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     const size_t lds = guide_lds_bytes(N, t, mode);
     if (lds > guide_max_lds()) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {   // opt in to the device's whole LDS once per kernel
-        static std::atomic<bool> opted[5];
-        const int m = mode < 0 || mode > 4 ? MODE_DEBUG : mode;
+        static std::atomic<bool> opted[MODE_COUNT_OF_MODES];
+        const int m = mode < 0 || mode >= MODE_COUNT_OF_MODES ? MODE_DEBUG : mode;
         if (!opted[m].load()) {
             const void *fn = nullptr;
             switch (m) {
@@ -494,6 +549,8 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
             case MODE_PDF: fn = (const void *)&k_guide<N, MODE_PDF>; break;
             case MODE_EVAL: fn = (const void *)&k_guide<N, MODE_EVAL>; break;
             case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT>; break;
+            case MODE_PRODUCT: fn = (const void *)&k_guide<N, MODE_PRODUCT>; break;
+            case MODE_PEVAL: fn = (const void *)&k_guide<N, MODE_PEVAL>; break;
             default: fn = (const void *)&k_guide<N, MODE_DEBUG>; break;
             }
             const hipError_t e =
@@ -510,6 +567,8 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     case MODE_PDF: hipLaunchKernelGGL((k_guide<N, MODE_PDF>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     case MODE_EVAL: hipLaunchKernelGGL((k_guide<N, MODE_EVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     case MODE_COUNT: hipLaunchKernelGGL((k_guide<N, MODE_COUNT>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    case MODE_PRODUCT: hipLaunchKernelGGL((k_guide<N, MODE_PRODUCT>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
+    case MODE_PEVAL: hipLaunchKernelGGL((k_guide<N, MODE_PEVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     default: hipLaunchKernelGGL((k_guide<N, MODE_DEBUG>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
     }
     return hipGetLastError();

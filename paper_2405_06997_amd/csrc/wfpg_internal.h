@@ -67,7 +67,12 @@ hipError_t launch_accumulate(struct ::wfpg_svo *svo, const float *pos, const flo
                              const float *rgb, int64_t n, hipStream_t s);
 hipError_t launch_propagate(struct ::wfpg_svo *svo, hipStream_t s);
 
-enum GuideMode { MODE_SAMPLE = 0, MODE_PDF = 1, MODE_EVAL = 2, MODE_DEBUG = 3, MODE_COUNT = 4 };
+enum GuideMode {
+    MODE_SAMPLE = 0, MODE_PDF = 1, MODE_EVAL = 2, MODE_DEBUG = 3, MODE_COUNT = 4,
+    MODE_PRODUCT = 5,   // product guiding sample (Sec. 3.6)
+    MODE_PEVAL = 6,     // product guiding pdf of given directions
+    MODE_COUNT_OF_MODES = 7
+};
 
 struct GuideArgs {
     const float *pos;
@@ -88,6 +93,9 @@ struct GuideArgs {
     int32_t *err;             // device error flags
     unsigned long long *queue_ctr;   // vertex queue counter (reset before each launch)
     const int32_t *gate;             // optional: the kernel does nothing unless *gate != 0
+    const float *nrm_in;      // product modes: SoA normals (Lambertian table) or NULL
+    const float *bsdf_in;     // product modes: n x 64 BSDF tables or NULL
+    const float *dirtab8;     // product modes: the 8 x 8 cell-centre directions
 };
 
 struct TileConfig {          // launch shape chosen by the autotuner
