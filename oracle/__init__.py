@@ -74,7 +74,11 @@ def lib():
             "orc_pdf_eval": (None, [vp, vp, vp, i64, i32, f32, vp, vp, vp]),
             "orc_partition": (None, [vp, vp, i64, i32, i32, vp, vp]),
             "orc_binned_sample": (None, [vp, vp, i64, i32, i32, u64, u32, i32, f32, vp, vp, vp, vp, vp, vp,
-                                         vp, vp, vp]),
+                                         vp, vp, vp, i32, u32, i32]),
+            "orc_jitter_table": (None, [i32, u32, vp]),
+            "orc_blur": (None, [vp, i32, vp]),
+            "orc_field_aa": (None, [vp, vp, i64, i32, f32, i32, u32, i32, vp]),
+            "orc_sample_fields": (None, [vp, i64, i64, i32, u64, u32, vp, vp, vp, vp, vp]),
             "orc_product_fields": (None, [vp, i64, i64, i32, vp, vp, u64, u32, vp, vp, vp, vp, vp]),
             "orc_product_pdf_fields": (None, [vp, i64, i32, vp, vp, vp, vp]),
             "orc_product_sample": (None, [vp, vp, vp, vp, i64, u64, u32, i32, f32, vp, vp, vp, vp]),
@@ -320,9 +324,10 @@ class SVO:
         return lv, ix
 
     def binned_sample(self, pos, c_ray: int, l_min: int, N: int, seed: int, bounce: int,
-                      eps: float = 0.01, nrm=None, bsdf=None):
+                      eps: float = 0.01, nrm=None, bsdf=None, jitter_key=None, blur: bool = False):
         """Per-bin fields and member samples (Alg. 2 + Alg. 3); with nrm or
-        bsdf every member draws a product sample (Sec. 3.6) instead."""
+        bsdf every member draws a product sample (Sec. 3.6) instead;
+        jitter_key / blur: the field antialiasing of field_aa."""
         pos = _soa(pos)
         n = pos.shape[1]
         nv, bv = _product_inputs(nrm, bsdf, n)
@@ -334,8 +339,19 @@ class SVO:
         ix = np.zeros(n, np.int64)
         org = np.zeros(n, np.int64)
         lib().orc_binned_sample(self._h, _p(pos), n, c_ray, l_min, seed, bounce, N, eps, _p(d), _p(pdf),
-                                _p(b), _p(m), _p(lv), _p(ix), _p(org), _opt(nv), _opt(bv))
+                                _p(b), _p(m), _p(lv), _p(ix), _p(org), _opt(nv), _opt(bv),
+                                int(jitter_key is not None), 0 if jitter_key is None else jitter_key, int(blur))
         return dict(dir=d, pdf=pdf, bin=b, margin=m, level=lv, index=ix, origin=org)
+
+    def field_aa(self, pos, N: int, jitter_key=None, blur: bool = False, eps: float = 0.01):
+        """Fields (n x N*N) with directional jitter (jitter_key not None)
+        and/or the Gaussian blur (Sec. 4)."""
+        pos = _soa(pos)
+        n = pos.shape[1]
+        L = np.zeros((n, N * N))
+        lib().orc_field_aa(self._h, _p(pos), n, N, eps, int(jitter_key is not None),
+                           0 if jitter_key is None else jitter_key, int(blur), _p(L))
+        return L
 
     def product_sample(self, pos, N: int, seed: int, bounce: int, nrm=None, bsdf=None, eps: float = 0.01):
         """Product guiding (Sec. 3.6) of each vertex's own field; nrm (3 x n,
@@ -404,6 +420,38 @@ def product_sample_fields(L, N: int, seed: int, bounce: int, nrm=None, bsdf=None
     m = np.zeros((n, 2))
     lib().orc_product_fields(_p(L), 0 if shared else N * N, n, N, _opt(nv), _opt(bv), seed, bounce, _opt(ctr),
                              _p(d), _p(pdf), _p(b), _p(m))
+    return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+
+def jitter_table(N: int, key: int) -> np.ndarray:
+    """FP32 jittered cone directions (N*N, 3) for jitter key `key`."""
+    out = np.zeros((N * N, 3), np.float32)
+    lib().orc_jitter_table(N, key, _p(out))
+    return out
+
+
+def blur(L, N: int) -> np.ndarray:
+    """The 3 x 3 binomial blur of fields L (... x N*N) with edge folding."""
+    L = np.ascontiguousarray(L, np.float64)
+    flat = L.reshape(-1, N * N)
+    out = np.zeros_like(flat)
+    for k in range(flat.shape[0]):
+        lib().orc_blur(_p(flat[k]), N, _p(out[k]))
+    return out.reshape(L.shape)
+
+
+def sample_fields(L, N: int, seed: int, bounce: int, counter=None, n=None):
+    """guide_sample's rule on given fields (n x N*N; one shared row with n)."""
+    L = np.ascontiguousarray(L, np.float64).reshape(-1, N * N)
+    shared = n is not None and L.shape[0] == 1
+    n = L.shape[0] if n is None else n
+    ctr = None if counter is None else np.ascontiguousarray(counter, np.int64)
+    d = np.zeros((3, n))
+    pdf = np.zeros(n)
+    b = np.zeros((n, 2), np.int32)
+    m = np.zeros((n, 2))
+    lib().orc_sample_fields(_p(L), 0 if shared else N * N, n, N, seed, bounce, _opt(ctr), _p(d), _p(pdf), _p(b),
+                            _p(m))
     return dict(dir=d, pdf=pdf, bin=b, margin=m)
 
 

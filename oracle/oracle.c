@@ -1121,6 +1121,9 @@ static void product_table(const float *nrm, const float *bsdf, int64_t n, int64_
 static void product_one(const double *L, int N, const double *f, uint64_t seed, uint32_t bounce, int64_t ctr,
                         int64_t n, int64_t i, double *dir, double *pdf, int32_t *bin, double *margin);
 
+void orc_jitter_table(int32_t N, uint32_t jitter_key, float *out);
+void orc_blur(const double *L, int32_t N, double *out);
+
 /* Binned guiding (Alg. 2 then Alg. 3): partition the queue, take each bin's
  * origin, generate the N x N field once per bin at its origin (as
  * orc_guide_pdf does for a vertex), and sample every member from its bin's
@@ -1129,11 +1132,13 @@ static void product_one(const double *L, int N, const double *f, uint64_t seed, 
  * bin's origin per member. Queries without a bin (empty SVO) get pdf 0.
  * With nrm or bsdf given, every member draws a product sample (below) from
  * its bin's field and its own BSDF table, as the paper's product variant does
- * per ray over the shared bin field. */
+ * per ray over the shared bin field. jitter/jitter_key/blur: the field
+ * antialiasing options of orc_field_aa, applied to every bin field. */
 void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_ray, int32_t l_min,
                        uint64_t seed, uint32_t bounce, int32_t N, float eps, double *dir, double *pdf,
                        int32_t *bin, double *margin, int32_t *bin_level, int64_t *bin_index,
-                       int64_t *origin, const float *nrm, const float *bsdf)
+                       int64_t *origin, const float *nrm, const float *bsdf, int32_t jitter,
+                       uint32_t jitter_key, int32_t blur)
 {
     int D = s->depth, NN = N * N;
     orc_partition(s, pos, n, c_ray, l_min, bin_level, bin_index);
@@ -1157,7 +1162,8 @@ void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_
         }
     }
     float *tab = malloc(sizeof(float) * 3 * (size_t)NN);
-    orc_dir_table(N, tab);
+    if (jitter) orc_jitter_table(N, jitter_key, tab);
+    else orc_dir_table(N, tab);
     /* the field of each bin, once, at its origin */
     int64_t nb = 0;
     int64_t *slot[MAXD + 1];
@@ -1176,6 +1182,12 @@ void orc_binned_sample(const orc_svo *s, const float *pos, int64_t n, int32_t c_
         int64_t o = forig[b];
         float p[3] = {pos[o], pos[n + o], pos[2 * n + o]};
         field_one(s, p, N, eps, tab, fields + b * NN, NULL);
+        if (blur) {
+            double *t = malloc(sizeof(double) * (size_t)NN);
+            orc_blur(fields + b * NN, N, t);
+            memcpy(fields + b * NN, t, sizeof(double) * (size_t)NN);
+            free(t);
+        }
     }
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; i++) {
@@ -1455,4 +1467,90 @@ void orc_product_pdf_eval(const orc_svo *s, const float *pos, const float *nrm, 
         free(L);
     }
     free(tab);
+}
+
+/* ------------------------------------------- field antialiasing (Sec. 4) - */
+/* Directional jitter: instead of the bin centre, the cone of bin b = v N + u
+ * runs along the decode of ((u + j_u) / N, (v + j_v) / N), with (j_u, j_v) the
+ * first two words of Philox-4x32-10 at counter (b, 0, 0, 3) and key
+ * (jitter_key, 0), each as (bits >> 8) * 2^-24. The caller draws a new key
+ * on the iterations it jitters. Decoded in FP64, rounded to FP32 (as the
+ * bin-centre table). */
+void orc_jitter_table(int32_t N, uint32_t jitter_key, float *out)
+{
+    for (int v = 0; v < N; v++)
+        for (int u = 0; u < N; u++) {
+            int b = v * N + u;
+            uint32_t ctr[4] = {(uint32_t)b, 0, 0, 3}, key[2] = {jitter_key, 0}, o[4];
+            orc_philox(ctr, key, o);
+            double ju = (double)(o[0] >> 8) * (1.0 / 16777216.0), jv = (double)(o[1] >> 8) * (1.0 / 16777216.0);
+            double d[3];
+            orc_oct_decode((u + ju) / N, (v + jv) / N, d);
+            for (int k = 0; k < 3; k++) out[3 * b + k] = (float)d[k];
+        }
+}
+
+/* Neighbour bins across the edge of the octahedral square: the map sends the
+ * points (1, b) and (1, -b) of the edge a = 1 to the same direction (and
+ * likewise on the other three edges), so bin (N, v) is bin (N - 1, N - 1 - v)
+ * and bin (u, N) is bin (N - 1 - u, N - 1); a corner folds twice. */
+static void fold_bin(int N, int *u, int *v)
+{
+    if (*u < 0) { *u = 0; *v = N - 1 - *v; }
+    else if (*u >= N) { *u = N - 1; *v = N - 1 - *v; }
+    if (*v < 0) { *v = 0; *u = N - 1 - *u; }
+    else if (*v >= N) { *v = N - 1; *u = N - 1 - *u; }
+}
+
+/* Gaussian blur of a field (Sec. 4, "to make the generated radiance field
+ * plausible for all the rays in the bin"): the 3 x 3 binomial kernel
+ * (1/4, 1/2, 1/4) in each direction over the bins, neighbours folded across
+ * the square's edges. FP64. */
+void orc_blur(const double *L, int32_t N, double *out)
+{
+    static const double w[3] = {0.25, 0.5, 0.25};
+    for (int v = 0; v < N; v++)
+        for (int u = 0; u < N; u++) {
+            double acc = 0.0;
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int uu = u + dx, vv = v + dy;
+                    fold_bin(N, &uu, &vv);
+                    acc += w[dy + 1] * w[dx + 1] * L[vv * N + uu];
+                }
+            out[v * N + u] = acc;
+        }
+}
+
+/* Fields with the antialiasing options: the cone directions of the jittered
+ * table when jitter != 0, then the blur when blur != 0. L: n x N*N. */
+void orc_field_aa(const orc_svo *s, const float *pos, int64_t n, int32_t N, float eps, int32_t jitter,
+                  uint32_t jitter_key, int32_t blur, double *L)
+{
+    int NN = N * N;
+    float *tab = malloc(sizeof(float) * 3 * (size_t)NN);
+    if (jitter) orc_jitter_table(N, jitter_key, tab);
+    else orc_dir_table(N, tab);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        double *Li = L + i * NN;
+        field_one(s, p, N, eps, tab, Li, NULL);
+        if (blur) {
+            double *t = malloc(sizeof(double) * (size_t)NN);
+            orc_blur(Li, N, t);
+            memcpy(Li, t, sizeof(double) * (size_t)NN);
+            free(t);
+        }
+    }
+    free(tab);
+}
+
+/* Plain guide_sample rule on given fields (query i uses L + i * lstride). */
+void orc_sample_fields(const double *L, int64_t lstride, int64_t n, int32_t N, uint64_t seed, uint32_t bounce,
+                       const int64_t *counter, double *dir, double *pdf, int32_t *bin, double *margin)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++)
+        sample_field(L + i * lstride, N, seed, bounce, counter ? counter[i] : i, n, i, dir, pdf, bin, margin);
 }
