@@ -78,16 +78,34 @@ typedef struct {
  *              (requires guide_train first).
  *  kl_bound -- fallback threshold in nats for mode 1 (default 0.05).
  *  probe_stride -- every probe_stride-th vertex is also marched to judge the
- *              learned model in mode 1 (default 256). */
+ *              learned model in mode 1 (default 256).
+ *  jitter, jitter_key -- field antialiasing (Sec. 4, "aliasing"): with
+ *              jitter = 1 the cone of bin b = v*N + u runs along the decode
+ *              of ((u + j_u)/N, (v + j_v)/N) instead of the bin centre, with
+ *              (j_u, j_v) = words 0 and 1 of Philox-4x32-10 at counter
+ *              (b, 0, 0, 3), key (jitter_key, 0), each (bits >> 8) * 2^-24,
+ *              decoded in FP64 and rounded to FP32. The caller picks a new
+ *              key on the iterations it jitters; pdf_eval with the same
+ *              options regenerates the same field. 0 or 1 (default 0).
+ *  blur     -- 1: the field L (eps included) is blurred before the CDF with
+ *              the 3 x 3 binomial kernel (1/4, 1/2, 1/4) per axis over the
+ *              bins, in FP32, rows outer; neighbours across the edge of the
+ *              octahedral square are the mirrored bins ((N, v) is
+ *              (N - 1, N - 1 - v), (u, N) is (N - 1 - u, N - 1)), as the map
+ *              joins them on the sphere. 0 or 1 (default 0).
+ *  Mode 1 takes neither jitter nor blur (EINVAL). */
 typedef struct {
     int32_t N;
     float eps;
     int32_t mode;
     float kl_bound;
     int32_t probe_stride;
+    int32_t jitter;
+    uint32_t jitter_key;
+    int32_t blur;
 } wfpg_opts;
 
-/* Default options {16, 0.01f, 0, 0.05f, 256}. */
+/* Default options {16, 0.01f, 0, 0.05f, 256, 0, 0, 0}. */
 wfpg_opts wfpg_default_opts(void);
 
 const char *wfpg_status_string(wfpg_status s);
@@ -278,6 +296,11 @@ const char *wfpg_last_error(void);
  * resolution N in {8, 16, 32, 64, 128} (N*N*3 floats, AoS, bin b = v*N + u). */
 wfpg_status wfpg_dir_table(int32_t N, float *out);
 
+/* Host copy of the jittered cone directions the kernels compute for
+ * jitter_key (see wfpg_opts.jitter), same layout as wfpg_dir_table.
+ * Synchronizes the device. */
+wfpg_status wfpg_dir_table_jitter(int32_t N, uint32_t jitter_key, float *out);
+
 /* Test-only: the traversal record of every (vertex, bin) pair, for
  * bit-exact comparison with an independent implementation.
  * out: DEVICE n * N*N * 8 int32 = {hit, entry axis, leaf key, |B - O| of
@@ -391,6 +414,9 @@ typedef struct {
     float eps;       /* as wfpg_opts (0.01) */
     int32_t c_ray;   /* queries that make a bin, >= 1 (512) */
     int32_t l_min;   /* coarsest bin level, 0..depth (5) */
+    int32_t jitter;       /* as wfpg_opts: jittered cone directions of every bin field (0) */
+    uint32_t jitter_key;  /* (0) */
+    int32_t blur;         /* as wfpg_opts: blur every bin field before its CDF (0) */
 } wfpg_bin_opts;
 
 wfpg_bin_opts wfpg_default_bin_opts(void);

@@ -35,7 +35,7 @@ EXPORTS = [
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
     "wfpg_default_bin_opts", "wfpg_partition", "guide_sample_binned",
-    "guide_sample_product", "pdf_eval_product", "guide_sample_binned_product",
+    "guide_sample_product", "pdf_eval_product", "guide_sample_binned_product", "wfpg_dir_table_jitter",
     "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
     "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
@@ -61,11 +61,13 @@ class Tile(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("mode", C.c_int32),
-                ("kl_bound", C.c_float), ("probe_stride", C.c_int32)]
+                ("kl_bound", C.c_float), ("probe_stride", C.c_int32), ("jitter", C.c_int32),
+                ("jitter_key", C.c_uint32), ("blur", C.c_int32)]
 
 
 class BinOpts(C.Structure):
-    _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("c_ray", C.c_int32), ("l_min", C.c_int32)]
+    _fields_ = [("N", C.c_int32), ("eps", C.c_float), ("c_ray", C.c_int32), ("l_min", C.c_int32),
+                ("jitter", C.c_int32), ("jitter_key", C.c_uint32), ("blur", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -76,8 +78,11 @@ class TrainCfg(C.Structure):
 
 
 def make_opts(N: int = 16, eps: float = 0.01, mode: int = 0, kl_bound: float = 0.05,
-              probe_stride: int = 256) -> Opts:
-    return Opts(N, eps, mode, kl_bound, probe_stride)
+              probe_stride: int = 256, jitter_key=None, blur: bool = False) -> Opts:
+    """Guiding options; jitter_key (not None) turns on the directional jitter
+    with that key, blur the Gaussian blur of the field."""
+    return Opts(N, eps, mode, kl_bound, probe_stride, int(jitter_key is not None),
+                0 if jitter_key is None else jitter_key, int(blur))
 
 
 _lib = None
@@ -111,6 +116,7 @@ def lib():
         "svo_export_level": (i32, [vp, i32, vp, vp, vp, vp]),
         "svo_export_accum": (i32, [vp, vp, vp, vp]),
         "wfpg_dir_table": (i32, [i32, vp]),
+        "wfpg_dir_table_jitter": (i32, [i32, u32, vp]),
         "wfpg_last_error": (C.c_char_p, []),
         "wfpg_march_counts": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
         "wfpg_get_tile": (i32, [vp, i32, C.POINTER(Tile)]),
@@ -175,6 +181,13 @@ def dir_table(N: int) -> np.ndarray:
     """FP32 bin-centre directions used by the kernels, (N*N, 3)."""
     out = np.zeros((N * N, 3), np.float32)
     _check("wfpg_dir_table", lib().wfpg_dir_table(N, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def dir_table_jitter(N: int, key: int) -> np.ndarray:
+    """FP32 jittered cone directions the kernels use for key, (N*N, 3)."""
+    out = np.zeros((N * N, 3), np.float32)
+    _check("wfpg_dir_table_jitter", lib().wfpg_dir_table_jitter(N, key, out.ctypes.data_as(C.c_void_p)))
     return out
 
 
@@ -515,8 +528,10 @@ def learned_stats(svo: SVO) -> dict:
 
 # ------------------------------------------------------ positional binning
 
-def bin_opts(N: int = 16, eps: float = 0.01, c_ray: int = 512, l_min: int = 5) -> BinOpts:
-    return BinOpts(N, eps, c_ray, l_min)
+def bin_opts(N: int = 16, eps: float = 0.01, c_ray: int = 512, l_min: int = 5, jitter_key=None,
+             blur: bool = False) -> BinOpts:
+    return BinOpts(N, eps, c_ray, l_min, int(jitter_key is not None), 0 if jitter_key is None else jitter_key,
+                   int(blur))
 
 
 def partition(svo: SVO, pos, c_ray: int, l_min: int, seed: int = 0, bounce: int = 0, stream=None):

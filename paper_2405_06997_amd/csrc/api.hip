@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "antialias_core.h"
 #include "wfpg_internal.h"
 
 using namespace wfpg;
@@ -95,6 +96,14 @@ const float *device_dirtab(int N)
 
 namespace {
 
+// The jittered cone directions the kernels use for one key (FP32, 3 per bin).
+__global__ void k_jitter_table(int N, uint32_t key, float *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= N * N) return;
+    wfpg::aa::jitter_dir(N, b, key, out[3 * b], out[3 * b + 1], out[3 * b + 2]);
+}
+
 wfpg_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return WFPG_OK;
@@ -123,6 +132,8 @@ bool valid_opts(const wfpg_opts *o)
     if (o->N != 8 && o->N != 16 && o->N != 32) return false;
     if (!std::isfinite(o->eps) || !(o->eps > 0.f)) return false;
     if (o->mode != 0 && o->mode != 1) return false;
+    if ((o->jitter != 0 && o->jitter != 1) || (o->blur != 0 && o->blur != 1)) return false;
+    if (o->mode == 1 && (o->jitter || o->blur)) return false;   // the learned stand-in has no field to filter
     return true;
 }
 
@@ -136,6 +147,9 @@ GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o)
     a.pdf_scale = (float)((double)(o->N * o->N) / (4.0 * pi));
     a.dirtab = device_dirtab(o->N);
     a.err = svo->d_err;
+    a.jitter = o->jitter;
+    a.jitter_key = o->jitter_key;
+    a.blur = o->blur;
     return a;
 }
 
@@ -163,6 +177,9 @@ wfpg_opts wfpg_default_opts(void)
     o.mode = 0;
     o.kl_bound = 0.05f;
     o.probe_stride = 256;
+    o.jitter = 0;
+    o.jitter_key = 0;
+    o.blur = 0;
     return o;
 }
 
@@ -460,6 +477,20 @@ wfpg_status wfpg_dir_table(int32_t N, float *out)
     if (!out || (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)) return WFPG_EINVAL;
     host_dir_table(N, out);
     return WFPG_OK;
+}
+
+wfpg_status wfpg_dir_table_jitter(int32_t N, uint32_t jitter_key, float *out)
+{
+    if (!out || (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)) return WFPG_EINVAL;
+    const size_t bytes = (size_t)N * N * 3 * sizeof(float);
+    float *d = nullptr;
+    hipError_t e = hipMalloc((void **)&d, bytes);
+    if (e != hipSuccess) return from_hip(e);
+    hipLaunchKernelGGL(k_jitter_table, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, 0, N, jitter_key, d);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(out, d, bytes, hipMemcpyDeviceToHost);
+    const hipError_t f = hipFree(d);
+    return from_hip(e != hipSuccess ? e : f);
 }
 
 }  // extern "C"

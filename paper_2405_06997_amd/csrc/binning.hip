@@ -21,6 +21,7 @@
 
 #include "march_core.h"
 #include "product_core.h"
+#include "antialias_core.h"
 #include "wfpg_internal.h"
 
 // Smallest field resolution generated one workgroup per bin (smaller ones go
@@ -33,18 +34,6 @@ namespace wfpg {
 namespace {
 
 using core::woff;
-
-// Philox-4x32-10 (Salmon et al., SC'11), the generator of the guide kernels.
-__device__ __forceinline__ void core_philox(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-    for (int r = 0; r < 10; ++r) {
-        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    }
-}
 
 // 16-bit storage formats of the exitance and the field bins (as the guide
 // kernels store them): RNE rounding and unpacking.
@@ -151,7 +140,7 @@ __global__ void __launch_bounds__(256) k_bin_assign(SvoView sv, int l_min, int64
             }
             bin = (int32_t)b;
             uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 1u};
-            core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+            core::philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
             key = ((unsigned long long)c[0] << 32) | (unsigned long long)(uint32_t)i;
         }
         bin_of[i] = bin;
@@ -251,7 +240,7 @@ __global__ void k_bin_sample(int64_t n, uint64_t seed, uint32_t bounce, const in
     }
     const int64_t s = slot_of[bin];
     uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
-    core_philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    core::philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
     const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
     const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
@@ -322,11 +311,11 @@ __global__ void __launch_bounds__(256) k_bin_product(int64_t n, uint64_t seed, u
         prod::Upper q;
         prod::upper_level(coarse[sl * 64 + lane], prod::table_entry(nrm, bsdf, i, n, tab8, lane), lane, q);
         uint32_t w[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 2u};
-        core_philox(w, (uint32_t)seed, (uint32_t)(seed >> 32));
+        core::philox(w, (uint32_t)seed, (uint32_t)(seed >> 32));
         const int c = prod::pick_cell(q, (float)(w[0] >> 8) * 5.9604644775390625e-8f,
                                       (float)(w[1] >> 8) * 5.9604644775390625e-8f, lane);
         uint32_t r[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
-        core_philox(r, (uint32_t)seed, (uint32_t)(seed >> 32));
+        core::philox(r, (uint32_t)seed, (uint32_t)(seed >> 32));
         const int V = c >> 3, U = c & 7;
         const float *blk = pdf + sl * N * N + (V * SB) * N + U * SB;
         int dv = 0, du = 0;
@@ -371,7 +360,8 @@ constexpr int bin_field_threads() { return N * N < 1024 ? N * N : 1024; }
 template <int N>
 __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     SvoView sv, const float *__restrict__ opos, int64_t cap, const int32_t *nbins, const float *__restrict__ dirtab,
-    float eps, float omega, float pdf_scale, int lds_levels, float *pdf, int32_t *err)
+    float eps, float omega, float pdf_scale, int lds_levels, int jitter, uint32_t jitter_key, int blur, float *pdf,
+    int32_t *err)
 {
     constexpr int NN = N * N, B = bin_field_threads<N>(), PER = NN / B;
     extern __shared__ uint64_t lbits[];
@@ -402,9 +392,13 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     while (true) {
         if (!act && j < PER) {
             const int c = threadIdx.x + B * j;
-            dx = dirtab[3 * c];
-            dy = dirtab[3 * c + 1];
-            dz = dirtab[3 * c + 2];
+            if (jitter) {
+                aa::jitter_dir(N, c, jitter_key, dx, dy, dz);
+            } else {
+                dx = dirtab[3 * c];
+                dy = dirtab[3 * c + 1];
+                dz = dirtab[3 * c + 2];
+            }
             uint32_t a0, a1, a2;
             int s0, s1, s2;
             core::split_dir(core::quantize_dir(dx), a0, s0);
@@ -452,6 +446,20 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
             local += val;
             ++j;
             act = false;
+        }
+    }
+    if (blur) {   // uniform over the block: blur the whole field, then re-total
+        float t[PER];
+        __syncthreads();
+        for (int q = 0; q < PER; ++q) {
+            const int c = threadIdx.x + B * q;
+            t[q] = aa::blur_at(N, c % N, c / N, [&](int k) { return L[k]; });
+        }
+        __syncthreads();
+        local = 0.f;
+        for (int q = 0; q < PER; ++q) {
+            L[threadIdx.x + B * q] = t[q];
+            local += t[q];
         }
     }
     for (int d = 32; d >= 1; d >>= 1) local += __shfl_xor(local, d);
@@ -510,11 +518,12 @@ struct BinWork {
 // One workgroup per bin: the field of each bin origin into W->pdf.
 template <int N>
 void launch_bin_field(int32_t nb, size_t lds, hipStream_t s, const SvoView &v, const BinWork *W, int64_t cap,
-                      const float *tab, float eps, float omega, float scale, int lds_levels, const wfpg_svo *svo)
+                      const float *tab, const wfpg_bin_opts *o, float omega, float scale, int lds_levels,
+                      const wfpg_svo *svo)
 {
     hipLaunchKernelGGL(k_bin_field<N>, dim3((unsigned)nb), dim3(bin_field_threads<N>()), lds, s, v,
-                       (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, eps, omega, scale, lds_levels,
-                       (float *)W->pdf, svo->d_err);
+                       (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, o->eps, omega, scale, lds_levels,
+                       (int)o->jitter, o->jitter_key, (int)o->blur, (float *)W->pdf, svo->d_err);
 }
 
 void destroy_bin_work(void *w)
@@ -577,8 +586,8 @@ namespace {
 bool valid_bin_opts(const wfpg_svo *svo, const wfpg_bin_opts *o)
 {
     return o && (o->N == 8 || o->N == 16 || o->N == 32 || o->N == 64 || o->N == 128) && std::isfinite(o->eps) &&
-           o->eps > 0.f &&
-           o->c_ray >= 1 && o->l_min >= 0 && o->l_min <= svo->depth;
+           o->eps > 0.f && o->c_ray >= 1 && o->l_min >= 0 && o->l_min <= svo->depth &&
+           (o->jitter == 0 || o->jitter == 1) && (o->blur == 0 || o->blur == 1);
 }
 
 wfpg_status st_of(hipError_t e, int line)
@@ -645,10 +654,10 @@ hipError_t binned_fields(const wfpg_svo *svo, const float *pos, int64_t n, uint6
         const SvoView v = svo->view();
         const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
         if (!tab) e = hipErrorOutOfMemory;
-        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
-        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts->eps, omega, scale, lds_levels, svo);
+        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
+        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
+        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
+        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
         if (e == hipSuccess) e = hipGetLastError();
     } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
         GuideArgs a;
@@ -663,6 +672,9 @@ hipError_t binned_fields(const wfpg_svo *svo, const float *pos, int64_t n, uint6
         a.dirtab = device_dirtab(N);
         a.err = svo->d_err;
         a.pdf_out = (float *)W->pdf;
+        a.jitter = opts->jitter;
+        a.jitter_key = opts->jitter_key;
+        a.blur = opts->blur;
         e = a.dirtab ? launch_guide(svo, N, MODE_PDF, a, choose_tile(svo, N), s) : hipErrorOutOfMemory;
     }
     return e;
@@ -679,6 +691,9 @@ wfpg_bin_opts wfpg_default_bin_opts(void)
     o.eps = 0.01f;
     o.c_ray = 512;
     o.l_min = 5;
+    o.jitter = 0;
+    o.jitter_key = 0;
+    o.blur = 0;
     return o;
 }
 

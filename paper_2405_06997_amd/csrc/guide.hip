@@ -14,6 +14,7 @@
 
 #include "march_core.h"
 #include "product_core.h"
+#include "antialias_core.h"
 #include "wfpg_internal.h"
 
 namespace wfpg {
@@ -33,19 +34,6 @@ __device__ __forceinline__ float unpack16(uint32_t v, int side, int fmt)
     uint32_t h = side ? (v >> 16) : (v & 0xffffu);
     if (fmt == WFPG_FP16) return __half2float(__ushort_as_half((unsigned short)h));
     return __uint_as_float(h << 16);
-}
-
-// Philox-4x32-10 (Salmon et al., SC'11).
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    }
 }
 
 // Equal-area concentric octahedral map (Clarberg 2008), FP32.
@@ -112,7 +100,7 @@ constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
 // of every bin from the hit records in `rec`, then the row / marginal CDFs
 // and the mode's output for vertex i. Returns the number of hit bins of this
 // lane (for the count mode).
-template <int N, int MODE>
+template <int N, int MODE, bool BLUR>
 __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, const float *ldir,
                                          uint32_t *rec, int64_t i, int64_t ps, int lane,
                                          int vis_lane)
@@ -190,6 +178,18 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
         }
         return;
     }
+    if constexpr (BLUR) {   // the slot's records are consumed: its LDS holds the field
+        float *lv = reinterpret_cast<float *>(rec);
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) lv[j * 64 + lane] = L[j];
+        wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            const int b = j * 64 + lane;
+            L[j] = aa::blur_at(N, b % N, b / N, [&](int k) { return lv[k]; });
+        }
+        wave_lds_fence();
+    }
     if constexpr (MODE == MODE_PRODUCT || MODE == MODE_PEVAL) {
         // the slot's records are consumed: its LDS holds the field for the two levels
         constexpr int SB = N / prod::kCells;
@@ -209,11 +209,11 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
         float Lb;
         if constexpr (MODE == MODE_PRODUCT) {
             uint32_t w[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 2u};
-            philox(w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            core::philox(w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
             c = prod::pick_cell(q, (float)(w[0] >> 8) * 5.9604644775390625e-8f,
                                 (float)(w[1] >> 8) * 5.9604644775390625e-8f, lane);
             uint32_t r[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
-            philox(r, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            core::philox(r, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
             const float u1 = (float)(r[0] >> 8) * 5.9604644775390625e-8f;
             const float u2 = (float)(r[1] >> 8) * 5.9604644775390625e-8f;
             const int V = c >> 3, U = c & 7;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
             a.pdf_out[(size_t)i * NN + j * 64 + lane] = (L[j] / total) * a.pdf_scale;
     } else if constexpr (MODE == MODE_SAMPLE) {
         uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), a.bounce, 0u};
-        philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        core::philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
         const float u1 = (float)(c[0] >> 8) * 5.9604644775390625e-8f;
         const float u2 = (float)(c[1] >> 8) * 5.9604644775390625e-8f;
         const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
@@ -339,7 +339,9 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 // wave (values, CDF, sample) and freed. Slot bookkeeping is wave-uniform and
 // lives in scalar registers; the arrays below are only ever indexed by
 // unrolled constants.
-template <int N, int MODE>
+// BLUR: the field is blurred before its CDF (a variant of its own: the blur's
+// registers would lower the occupancy of the unblurred kernel).
+template <int N, int MODE, bool BLUR>
 __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds_levels)
 {
     constexpr int NN = N * N;
@@ -357,11 +359,21 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
     uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * RW * NN + (size_t)wave * S;
     for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
-    for (int t = threadIdx.x; t < 3 * NN; t += blockDim.x) {
-        const float d = a.dirtab[t];
-        ldir[t] = d;
-        const int q = core::quantize_dir(d);
-        lq[t] = (uint32_t)(q < 0 ? -q : q) | (q < 0 ? 0x80000000u : 0u);
+    for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+        float d[3];
+        if (a.jitter) {
+            aa::jitter_dir(N, t, a.jitter_key, d[0], d[1], d[2]);
+        } else {
+            d[0] = a.dirtab[3 * t];
+            d[1] = a.dirtab[3 * t + 1];
+            d[2] = a.dirtab[3 * t + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ldir[3 * t + k] = d[k];
+            const int q = core::quantize_dir(d[k]);
+            lq[3 * t + k] = (uint32_t)(q < 0 ? -q : q) | (q < 0 ? 0x80000000u : 0u);
+        }
     }
     __syncthreads();
 
@@ -398,7 +410,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
             if (done < 0) break;
             wave_lds_fence();
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
-            finalize<N, MODE>(sv, a, ldir, recs + done * RW * NN, vd, ps, lane, vl);
+            finalize<N, MODE, BLUR>(sv, a, ldir, recs + done * RW * NN, vd, ps, lane, vl);
             wave_lds_fence();
 #pragma unroll
             for (int k = 0; k < S; ++k)
@@ -539,38 +551,37 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
     const size_t lds = guide_lds_bytes(N, t, mode);
     if (lds > guide_max_lds()) return hipErrorInvalidValue;
+    const dim3 blk(64 * W);
+    const wfpg::SvoView v = svo->view();
+    const bool blur = a.blur != 0 && mode != MODE_DEBUG && mode != MODE_COUNT;
+    const void *fn = nullptr;
+#define WFPG_PICK(M)                                                                      \
+    fn = blur ? (const void *)&k_guide<N, M, true> : (const void *)&k_guide<N, M, false>
+    switch (mode) {
+    case MODE_SAMPLE: WFPG_PICK(MODE_SAMPLE); break;
+    case MODE_PDF: WFPG_PICK(MODE_PDF); break;
+    case MODE_EVAL: WFPG_PICK(MODE_EVAL); break;
+    case MODE_PRODUCT: WFPG_PICK(MODE_PRODUCT); break;
+    case MODE_PEVAL: WFPG_PICK(MODE_PEVAL); break;
+    case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT, false>; break;
+    default: fn = (const void *)&k_guide<N, MODE_DEBUG, false>; break;
+    }
+#undef WFPG_PICK
     if (lds > 64 * 1024) {   // opt in to the device's whole LDS once per kernel
-        static std::atomic<bool> opted[MODE_COUNT_OF_MODES];
-        const int m = mode < 0 || mode >= MODE_COUNT_OF_MODES ? MODE_DEBUG : mode;
+        static std::atomic<bool> opted[2 * MODE_COUNT_OF_MODES];
+        const int m = (mode < 0 || mode >= MODE_COUNT_OF_MODES ? MODE_DEBUG : mode) * 2 + (blur ? 1 : 0);
         if (!opted[m].load()) {
-            const void *fn = nullptr;
-            switch (m) {
-            case MODE_SAMPLE: fn = (const void *)&k_guide<N, MODE_SAMPLE>; break;
-            case MODE_PDF: fn = (const void *)&k_guide<N, MODE_PDF>; break;
-            case MODE_EVAL: fn = (const void *)&k_guide<N, MODE_EVAL>; break;
-            case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT>; break;
-            case MODE_PRODUCT: fn = (const void *)&k_guide<N, MODE_PRODUCT>; break;
-            case MODE_PEVAL: fn = (const void *)&k_guide<N, MODE_PEVAL>; break;
-            default: fn = (const void *)&k_guide<N, MODE_DEBUG>; break;
-            }
             const hipError_t e =
                 hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)guide_max_lds());
             if (e != hipSuccess) return e;
             opted[m].store(true);
         }
     }
-    const dim3 blk(64 * W);
-    const wfpg::SvoView v = svo->view();
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.queue_ctr);
-    switch (mode) {
-    case MODE_SAMPLE: hipLaunchKernelGGL((k_guide<N, MODE_SAMPLE>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    case MODE_PDF: hipLaunchKernelGGL((k_guide<N, MODE_PDF>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    case MODE_EVAL: hipLaunchKernelGGL((k_guide<N, MODE_EVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    case MODE_COUNT: hipLaunchKernelGGL((k_guide<N, MODE_COUNT>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    case MODE_PRODUCT: hipLaunchKernelGGL((k_guide<N, MODE_PRODUCT>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    case MODE_PEVAL: hipLaunchKernelGGL((k_guide<N, MODE_PEVAL>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    default: hipLaunchKernelGGL((k_guide<N, MODE_DEBUG>), dim3(grid), blk, lds, s, v, a, tc.lds_levels); break;
-    }
+    int levels = tc.lds_levels;
+    void *args[] = {(void *)&v, (void *)&a, (void *)&levels};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), blk, args, lds, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

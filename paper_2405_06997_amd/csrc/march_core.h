@@ -280,6 +280,25 @@ WFPG_HD int footprint_levels(uint32_t delta, float dabs, int D, float omega)
     return k;
 }
 
+// Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), the counter-based
+// generator of every random draw of the library: ten rounds of two 32 x 32
+// -> 64-bit products with a Weyl key schedule.
+WFPG_HD void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    WFPG_UNROLL
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+    }
+}
+
 // dot(N, d) in FP32 as (x*x' + y*y') + z*z', each product rounded.
 WFPG_HD float dot3(float ax, float ay, float az, float bx, float by, float bz)
 {

@@ -20,6 +20,7 @@
 #include <new>
 #include <vector>
 
+#include "march_core.h"
 #include "wfpg_internal.h"
 
 namespace wfpg {
@@ -377,18 +378,6 @@ __global__ void k_gather_rows(const float *__restrict__ src, int64_t n, int64_t 
     for (int k = 0; k < 3; ++k) dst[k * m + i] = src[k * stride + s];
 }
 
-// Philox-4x32-10 (Salmon et al., SC'11), as in the march kernels.
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-    for (int r = 0; r < 10; ++r) {
-        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    }
-}
-
 __device__ __forceinline__ void oct_decode(float x, float y, float &dx, float &dy, float &dz)
 {
     const float a = 2.f * x - 1.f, b = 2.f * y - 1.f;
@@ -581,7 +570,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_nn_infer(InferArgs A)
             const uint64_t i = (uint64_t)(r0 + u);
             cu[0] = (uint32_t)i;
             cu[1] = (uint32_t)(i >> 32);
-            philox(cu, (uint32_t)A.seed, (uint32_t)(A.seed >> 32));
+            core::philox(cu, (uint32_t)A.seed, (uint32_t)(A.seed >> 32));
         }
 #pragma unroll 1
         for (int r = 0; r < 4; ++r) {   // one row of the lane group at a time (register pressure)
@@ -688,7 +677,7 @@ __global__ void k_init(float *p, int64_t count, MlpLayout lay, int64_t table_off
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= count) return;
     uint32_t c[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), 0x5eedu, 0u};
-    philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    core::philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float u = (float)(c[0] >> 8) * 5.9604644775390625e-8f * 2.f - 1.f;   // [-1, 1)
     float val = 0.f;
     if (i >= table_off) {

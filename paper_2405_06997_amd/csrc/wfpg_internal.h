@@ -96,6 +96,9 @@ struct GuideArgs {
     const float *nrm_in;      // product modes: SoA normals (Lambertian table) or NULL
     const float *bsdf_in;     // product modes: n x 64 BSDF tables or NULL
     const float *dirtab8;     // product modes: the 8 x 8 cell-centre directions
+    int32_t jitter;           // cone directions jittered in their bins (key jitter_key)
+    uint32_t jitter_key;
+    int32_t blur;             // Gaussian blur of the field before the CDF
 };
 
 struct TileConfig {          // launch shape chosen by the autotuner
