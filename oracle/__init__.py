@@ -76,6 +76,7 @@ def lib():
             "orc_binned_sample": (None, [vp, vp, i64, i32, i32, u64, u32, i32, f32, vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp, i32, u32, i32]),
             "orc_jitter_table": (None, [i32, u32, vp]),
+            "orc_path_splats": (i64, [vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, i64]),
             "orc_blur": (None, [vp, i32, vp]),
             "orc_field_aa": (None, [vp, vp, i64, i32, f32, i32, u32, i32, vp]),
             "orc_sample_fields": (None, [vp, i64, i64, i32, u64, u32, vp, vp, vp, vp, vp]),
@@ -421,6 +422,24 @@ def product_sample_fields(L, N: int, seed: int, bounce: int, nrm=None, bsdf=None
     lib().orc_product_fields(_p(L), 0 if shared else N * N, n, N, _opt(nv), _opt(bv), seed, bounce, _opt(ctr),
                              _p(d), _p(pdf), _p(b), _p(m))
     return dict(dir=d, pdf=pdf, bin=b, margin=m)
+
+
+def path_splats(pos, T, eye, hit, Le):
+    """Eq. 5 splats of a wavefront: pos, T (d, 3, P), eye, Le (3, P), hit (P,)
+    -> (spos, swo, srgb) each 3 x m, depth-major."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    d, _, P = pos.shape
+    eye = _soa(eye)
+    Le = _soa(Le)
+    hit = np.ascontiguousarray(hit, np.int32)
+    cap = max(1, d * P)
+    sp = np.zeros((3, cap), np.float32)
+    sw = np.zeros((3, cap), np.float32)
+    sr = np.zeros((3, cap), np.float32)
+    m = lib().orc_path_splats(_p(pos), _p(T), _p(eye), _p(hit), _p(Le), P, d, _p(sp), _p(sw), _p(sr), cap)
+    assert m >= 0
+    return (np.ascontiguousarray(sp[:, :m]), np.ascontiguousarray(sw[:, :m]), np.ascontiguousarray(sr[:, :m]))
 
 
 def jitter_table(N: int, key: int) -> np.ndarray:

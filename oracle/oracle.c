@@ -1554,3 +1554,39 @@ void orc_sample_fields(const double *L, int64_t lstride, int64_t n, int32_t N, u
     for (int64_t i = 0; i < n; i++)
         sample_field(L + i * lstride, N, seed, bounce, counter ? counter[i] : i, n, i, dir, pdf, bin, margin);
 }
+
+/* ------------------------------------ exitance extraction (Eq. 5) ------ */
+/* Local radiance along a path (Sec. 3.2, Eq. 5): a path stores, for every
+ * depth k = 1..d, its vertex p_k and the throughput T_k of its first k
+ * vertices (RGB); p_0 is its eye point. When the path reaches an emitter at
+ * depth n with emitted radiance L_e toward p_{n-1}, the radiance leaving p_k
+ * toward p_{k-1} is (T_n / T_k) L_e for every k = 1..n (k = n: L_e itself).
+ * Each becomes one splat: position p_k, outgoing direction p_{k-1} - p_k
+ * (only its sign against the leaf normal is used), rgb (T_n / T_k) L_e per
+ * channel in FP32 (a zero T_k channel gives 0: T_n is then 0 as well).
+ * Layout: pos, T = d planes of 3 x P SoA, plane k-1 at offset (k-1) * 3 * P;
+ * eye, Le = 3 x P; hit[i] = n (1..d), anything else = no emitter. The splats
+ * come out depth-major (k outer, path inner), at most d * P of them; returns
+ * their number. */
+int64_t orc_path_splats(const float *pos, const float *T, const float *eye, const int32_t *hit, const float *Le,
+                        int64_t P, int32_t d, float *spos, float *swo, float *srgb, int64_t cap)
+{
+    int64_t m = 0;
+    for (int k = 1; k <= d; k++)
+        for (int64_t i = 0; i < P; i++) {
+            int n = hit[i];
+            if (n < 1 || n > d || k > n) continue;
+            const float *pk = pos + (int64_t)(k - 1) * 3 * P, *pp = k > 1 ? pos + (int64_t)(k - 2) * 3 * P : eye;
+            const float *Tk = T + (int64_t)(k - 1) * 3 * P, *Tn = T + (int64_t)(n - 1) * 3 * P;
+            if (m >= cap) return -1;
+            for (int c = 0; c < 3; c++) {
+                float tk = Tk[c * P + i], tn = Tn[c * P + i];
+                float ratio = tk == 0.0f ? 0.0f : tn / tk;
+                spos[c * cap + m] = pk[c * P + i];
+                swo[c * cap + m] = pp[c * P + i] - pk[c * P + i];
+                srgb[c * cap + m] = ratio * Le[c * P + i];
+            }
+            m++;
+        }
+    return m;
+}

@@ -285,3 +285,27 @@ def bounce_queues(rects: np.ndarray, q0_pos: np.ndarray, q0_nrm: np.ndarray,
         p, nn, _ = area_points(rects, sizes[b], seed * 1000 + b)
         out.append((p, nn))
     return out, sizes
+
+
+def path_wavefront(rects: np.ndarray, P: int, d: int = 8, seed: int = 21, hit_prob: float = 0.7,
+                   eye=(0.5, 0.02, 0.5)):
+    """Synthetic path memory of a wavefront of P paths of up to d vertices:
+    vertex k of every path uniform by area over the rectangles; throughputs
+    T_1 ~ U[0.3, 1] per channel, T_k = T_{k-1} * U[0.2, 0.9] (FP32); with
+    probability hit_prob a path reaches an emitter at a depth uniform in 1..d
+    emitting (12, 11, 9) * U[0.5, 1.5] toward its previous vertex, otherwise
+    none (depth -1, zero radiance). Returns (pos (d, 3, P), T (d, 3, P),
+    eye (3, P), hit (P,) int32, Le (3, P)), float32 SoA."""
+    rng = np.random.default_rng(seed)
+    pos = np.empty((d, 3, P), np.float32)
+    for k in range(d):
+        pos[k] = area_points(rects, P, int(rng.integers(1 << 62)))[0]
+    T = np.empty((d, 3, P), np.float32)
+    T[0] = rng.uniform(0.3, 1.0, (3, P)).astype(np.float32)
+    for k in range(1, d):
+        T[k] = T[k - 1] * rng.uniform(0.2, 0.9, (3, P)).astype(np.float32)
+    hit = np.where(rng.random(P) < hit_prob, rng.integers(1, d + 1, P), -1).astype(np.int32)
+    Le = (np.array([12.0, 11.0, 9.0])[:, None] * rng.uniform(0.5, 1.5, P)[None, :]).astype(np.float32)
+    Le[:, hit < 1] = 0.0
+    eyes = np.ascontiguousarray(np.tile(np.asarray(eye, np.float32)[:, None], (1, P)))
+    return pos, T, eyes, hit, np.ascontiguousarray(Le)
