@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
-    ap.add_argument("--sections", default="binned,product,learned,batching,precision",
+    ap.add_argument("--sections", default="binned,product,extract,learned,batching,precision",
                     help="comma-separated extra sections after the headline march step "
                          "(binned, learned, batching, precision; empty for none)")
     ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
@@ -192,7 +192,7 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
-    unknown = sections - {"binned", "product", "learned", "batching", "precision"}
+    unknown = sections - {"binned", "product", "extract", "learned", "batching", "precision"}
     if unknown:
         raise SystemExit(f"unknown sections: {sorted(unknown)}")
     if "binned" in sections:
@@ -201,6 +201,9 @@ def main():
     if "product" in sections:
         log("product section")
         out["product"] = product_section(w, svo, pos, cnrm, n, args, gs_avg)
+    if "extract" in sections:
+        log("extract section")
+        out["extract"] = extract_section(w, room, args)
     if "learned" in sections:
         log("learned section")
         out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
@@ -279,6 +282,32 @@ def product_section(w, svo, pos, cnrm, n, args, march_ms):
         assert torch.isfinite(p_out).all() and (p_out > 0).all()
         out[f"binned_{N}"] = {"guide_sample_binned_product_ms": ms, "samples_per_s": n / (ms * 1e-3)}
     return out
+
+
+def extract_section(w, room, args):
+    """Exitance extraction (Eq. 5) from the path memory of a frame-sized
+    wavefront: 2,073,600 paths of up to 8 vertices, 70 % reaching an emitter,
+    splatted and propagated into a fresh room SVO (depth 10)."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda:0")
+    P, d = 2073600, 8
+    log("extract: generating path memory")
+    pos, T, eye, hit, Le = synth.path_wavefront(room, P, d, seed=31)
+    splats = int(hit[hit >= 1].sum())
+    args_d = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (pos, T, eye, hit, Le)]
+    del pos, T
+    g = w.svo_build(room, 10)
+    ms = _timed(lambda: w.svo_accumulate_paths(g, *args_d), args.steps, args.warmup)
+    # algorithmic bytes: per path-depth thread, hit (4 B); per splat, p_k, T_k,
+    # T_n, p_{k-1}, Le (5 x 12 B) plus the leaf word, rank and normal reads and
+    # the 8 B of atomics, taken as 60 + 8 + 4 + 16 + 8 B
+    alg = P * d * 4 + splats * (60 + 8 + 4 + 16 + 8)
+    return {"paths": P, "depths": d, "splats": splats, "svo_accumulate_paths_ms": ms,
+            "splats_per_s": splats / (ms * 1e-3), "paths_per_s": P / (ms * 1e-3),
+            "alg_bytes": alg, "alg_gbs": alg / (ms * 1e-3) / 1e9, "includes": "splat + bottom-up propagation"}
 
 
 def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
@@ -396,7 +425,25 @@ def batching_section(w, svo, room, cam, cnrm, args):
         ms = _timed(Gn.launch, max(3, K // 4), 1)
         fixed[str(N)] = {"graph_ms": ms, "samples_per_s": sum(sizes) / (ms * 1e-3)}
         del Gn
+    # the paper's decaying resolution: N halved per bounce (down to 8)
+    log("depth-halving N")
+    halving = [max(8, 32 >> b) for b in range(len(sizes))]
+    Gh = w.BounceGraph(svo, qpos, n_dev, halving, seed=7)
+    h_ms = _timed(Gh.launch, max(3, K // 4), 1)
+    del Gh
+    bhalving = [max(8, 128 >> b) for b in range(len(sizes))]
+
+    def binned_halving():
+        for b, q in enumerate(qpos):
+            w.guide_sample_binned(svo, q, w.bin_opts(N=bhalving[b], c_ray=512, l_min=5), 7, b,
+                                  dir_out=G.dirs[b], pdf_out=G.pdfs[b])
+    bh_ms = _timed(binned_halving, max(3, K // 4), 1)
+    depth_halving = {"per_vertex": {"N_per_bounce": halving, "graph_ms": h_ms,
+                                    "samples_per_s": sum(sizes) / (h_ms * 1e-3)},
+                     "binned": {"N_per_bounce": bhalving, "c_ray": 512, "l_min": 5, "ms": bh_ms,
+                                "samples_per_s": sum(sizes) / (bh_ms * 1e-3)}}
     return {"bounces": len(sizes), "queue_sizes": sizes, "vertices": sum(sizes),
+            "depth_halving": depth_halving,
             "budget_ns_per_vertex": args.budget_ns, "N_per_bounce": Ns,
             "tuned": [{"bounce": b, "N": p["N"], "tile": p["tile"],
                        "queue_ms_per_N": {str(k): v for k, v in p["ms_per_N"].items()}}

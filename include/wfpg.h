@@ -167,6 +167,32 @@ wfpg_status svo_accumulate(wfpg_svo *svo, const float *pos, const float *wo,
                            const float *rgb, int64_t n, void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * svo_accumulate_paths -- UpdateExitance from path memory (Eq. 5): the
+ * local radiance at every depth of the paths that reached an emitter,
+ * splatted as svo_accumulate does, then averaged bottom-up.
+ *
+ * A wavefront of P paths stores, for each depth k = 1..d, the path vertex
+ * p_k and the throughput T_k of its first k vertices (RGB):
+ *   pos, T: DEVICE d planes of 3 x P FP32 SoA (plane k-1 at offset
+ *           (k-1) * 3 * P);
+ *   eye:    DEVICE 3 x P, p_0 of each path (its camera point);
+ *   hit:    DEVICE P int32, the depth n in 1..d at which the path reached
+ *           an emitter (any other value: no emitter, no splat);
+ *   Le:     DEVICE 3 x P, the radiance that emitter sends toward p_{n-1}.
+ * For k = 1..n the splat is: position p_k; outgoing direction
+ * p_{k-1} - p_k (FP32, only its sign against the leaf normal matters);
+ * rgb = (T_n / T_k) * Le per channel, FP32 correctly rounded, 0 where the
+ * channel of T_k is 0. Drop rules, accumulation and propagation as
+ * svo_accumulate. A path that reaches several emitters is passed once per
+ * emitter.
+ * Errors: EINVAL for NULL svo, P < 0, d < 1 or d > 64, or NULL arrays with
+ * P > 0.
+ * ------------------------------------------------------------------- */
+wfpg_status svo_accumulate_paths(wfpg_svo *svo, const float *pos, const float *T, const float *eye,
+                                 const int32_t *hit, const float *Le, int64_t P, int32_t d,
+                                 void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * guide_pdf -- the per-vertex guiding PDF (Alg. 3, ConeTrace for every
  * direction patch, then GeneratePDF-CDF), written out in full.
  *

@@ -36,6 +36,7 @@ EXPORTS = [
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
     "wfpg_default_bin_opts", "wfpg_partition", "guide_sample_binned",
     "guide_sample_product", "pdf_eval_product", "guide_sample_binned_product", "wfpg_dir_table_jitter",
+    "svo_accumulate_paths",
     "wfpg_default_train_cfg", "guide_train", "wfpg_nn_param_count", "wfpg_nn_params",
     "wfpg_nn_forward", "wfpg_nn_grad", "wfpg_learned_stats",
 ]
@@ -108,6 +109,7 @@ def lib():
         "svo_build": (i32, [vp, i64, i32, i32, vp, C.POINTER(vp)]),
         "svo_destroy": (None, [vp]),
         "svo_accumulate": (i32, [vp, vp, vp, vp, i64, vp]),
+        "svo_accumulate_paths": (i32, [vp, vp, vp, vp, vp, vp, i64, i32, vp]),
         "guide_pdf": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
         "guide_sample": (i32, [vp, vp, vp, i64, u64, u32, C.POINTER(Opts), vp, vp, vp]),
         "pdf_eval": (i32, [vp, vp, vp, i64, C.POINTER(Opts), vp, vp]),
@@ -264,6 +266,18 @@ def svo_accumulate(svo: SVO, pos, wo, rgb, stream=None):
             raise ValueError(f"{nm} must match pos")
     _check("svo_accumulate", lib().svo_accumulate(svo.handle, _dptr(pos, 3, "pos"), _dptr(wo, 3, "wo"),
                                                   _dptr(rgb, 3, "rgb"), n, _stream(stream)))
+
+
+def svo_accumulate_paths(svo: SVO, pos, T, eye, hit, Le, stream=None):
+    """Eq. 5 extraction: pos, T (d, 3, P), eye, Le (3, P), hit (P,) int32."""
+    if pos.dim() != 3 or pos.shape[1] != 3 or T.shape != pos.shape:
+        raise ValueError("pos and T must have shape (d, 3, P)")
+    d, _, P = pos.shape
+    if eye.shape != (3, P) or Le.shape != (3, P) or hit.shape != (P,):
+        raise ValueError("eye, Le must be (3, P) and hit (P,)")
+    _check("svo_accumulate_paths", lib().svo_accumulate_paths(
+        svo.handle, _dptr(pos, name="pos"), _dptr(T, name="T"), _dptr(eye, 3, "eye"), _dptr(hit, name="hit"),
+        _dptr(Le, 3, "Le"), P, d, _stream(stream)))
 
 
 def guide_pdf(svo: SVO, pos, opts: Opts, out=None, stream=None):

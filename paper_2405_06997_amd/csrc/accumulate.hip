@@ -35,58 +35,94 @@ __device__ __forceinline__ uint32_t to_f16(float f)
     return (uint32_t)__half_as_ushort(__float2half_rn(f));
 }
 
-// One thread per splat. Luminance y = (0.2126 r + 0.7152 g) + 0.0722 b in
-// FP32; the leaf of pos; side 0 iff dot(N_leaf, wo) >= 0; FP32/uint32 atomic
-// accumulation. Invalid or unplaceable splats are counted as dropped.
-__global__ void k_splat(SvoView sv, const float *__restrict__ pos, const float *__restrict__ wo,
-                        const float *__restrict__ rgb, int64_t n, float2 *sum, uint2 *cnt,
-                        unsigned long long *dropped)
+// One splat (position p, outgoing direction w, rgb c): luminance y =
+// (0.2126 r + 0.7152 g) + 0.0722 b in FP32; the leaf of p; side 0 iff
+// dot(N_leaf, w) >= 0; FP32/uint32 atomic accumulation. Returns false for an
+// invalid or unplaceable splat (counted as dropped by the caller).
+__device__ __forceinline__ bool splat_one(const SvoView &sv, const float p[3], const float w[3], const float c[3],
+                                          float2 *sum, uint2 *cnt)
 {
     const int D = sv.depth;
     const float R = (float)(1 << D);
     const uint64_t woffD = level_woff(D);
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool active = i < n;
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite(p[k]) && isfinite(w[k]) && isfinite(c[k]);
+    const float y = __fadd_rn(__fadd_rn(__fmul_rn(0.2126f, c[0]), __fmul_rn(0.7152f, c[1])),
+                              __fmul_rn(0.0722f, c[2]));
+    ok = ok && (y >= 0.f) && isfinite(y);
+    uint32_t cell[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        ok = ok && p[k] >= 0.f && p[k] <= 1.f;
+        const int v = ok ? (int)floorf(__fmul_rn(p[k], R)) : 0;
+        cell[k] = (uint32_t)min(v, (1 << D) - 1);
+    }
+    if (!ok) return false;
+    const uint32_t key = part1by2(cell[0]) | (part1by2(cell[1]) << 1) | (part1by2(cell[2]) << 2);
+    const uint64_t word = sv.bits[woffD + (key >> 6)];
+    if (!((word >> (key & 63)) & 1ull)) return false;
+    const uint64_t m = (key & 63) ? (word & ((1ull << (key & 63)) - 1)) : 0ull;
+    const int64_t g = (int64_t)sv.rank[woffD + (key >> 6)] + __popcll(m);
+    const int64_t leaf = g - sv.noff[D];
+    const float4 N = sv.nrm[g];
+    const int side = dot3(N.x, N.y, N.z, w[0], w[1], w[2]) >= 0.f ? 0 : 1;
+    unsafeAtomicAdd(side ? &sum[leaf].y : &sum[leaf].x, y);
+    atomicAdd(side ? &cnt[leaf].y : &cnt[leaf].x, 1u);
+    return true;
+}
+
+// One thread per splat.
+__global__ void k_splat(SvoView sv, const float *__restrict__ pos, const float *__restrict__ wo,
+                        const float *__restrict__ rgb, int64_t n, float2 *sum, uint2 *cnt,
+                        unsigned long long *dropped)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     bool drop = false;
-    if (active) {
+    if (i < n) {
         float p[3], w[3], c[3];
         for (int k = 0; k < 3; ++k) {
             p[k] = pos[k * n + i];
             w[k] = wo[k * n + i];
             c[k] = rgb[k * n + i];
         }
-        bool ok = true;
-        for (int k = 0; k < 3; ++k) ok = ok && isfinite(p[k]) && isfinite(w[k]) && isfinite(c[k]);
-        float y = __fadd_rn(__fadd_rn(__fmul_rn(0.2126f, c[0]), __fmul_rn(0.7152f, c[1])),
-                            __fmul_rn(0.0722f, c[2]));
-        ok = ok && (y >= 0.f) && isfinite(y);
-        uint32_t cell[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k) {
-            ok = ok && p[k] >= 0.f && p[k] <= 1.f;
-            int v = ok ? (int)floorf(__fmul_rn(p[k], R)) : 0;
-            cell[k] = (uint32_t)min(v, (1 << D) - 1);
-        }
-        if (ok) {
-            uint32_t key = part1by2(cell[0]) | (part1by2(cell[1]) << 1) | (part1by2(cell[2]) << 2);
-            uint64_t word = sv.bits[woffD + (key >> 6)];
-            if ((word >> (key & 63)) & 1ull) {
-                uint64_t m = (key & 63) ? (word & ((1ull << (key & 63)) - 1)) : 0ull;
-                int64_t g = (int64_t)sv.rank[woffD + (key >> 6)] + __popcll(m);
-                int64_t leaf = g - sv.noff[D];
-                float4 N = sv.nrm[g];
-                int side = dot3(N.x, N.y, N.z, w[0], w[1], w[2]) >= 0.f ? 0 : 1;
-                float *sp = side ? &sum[leaf].y : &sum[leaf].x;
-                unsigned *cp = side ? &cnt[leaf].y : &cnt[leaf].x;
-                unsafeAtomicAdd(sp, y);
-                atomicAdd(cp, 1u);
-            } else {
-                drop = true;
+        drop = !splat_one(sv, p, w, c, sum, cnt);
+    }
+    const uint64_t b = __ballot(drop);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(dropped, (unsigned long long)__popcll(b));
+}
+
+// Exitance extraction (Eq. 5), one thread per (depth k, path i), depth-major
+// so a wave reads consecutive paths of one depth plane: when path i reached an
+// emitter at depth n = hit[i] (1..d) with radiance Le toward p_{n-1}, every
+// k <= n splats (T_n / T_k) Le (per channel, FP32; 0 where T_k is 0) at p_k
+// with outgoing direction p_{k-1} - p_k (p_0 = the path's eye point).
+__global__ void k_splat_paths(SvoView sv, const float *__restrict__ pos, const float *__restrict__ T,
+                              const float *__restrict__ eye, const int32_t *__restrict__ hit,
+                              const float *__restrict__ Le, int64_t P, int d, bool place, float2 *sum,
+                              uint2 *cnt, unsigned long long *dropped)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool drop = false;
+    if (t < P * d) {
+        const int k = (int)(t / P) + 1;
+        const int64_t i = t - (int64_t)(k - 1) * P;
+        const int n = hit[i];
+        if (n >= 1 && n <= d && k <= n) {
+            const float *pk = pos + (int64_t)(k - 1) * 3 * P;
+            const float *pp = k > 1 ? pos + (int64_t)(k - 2) * 3 * P : eye;
+            const float *Tk = T + (int64_t)(k - 1) * 3 * P;
+            const float *Tn = T + (int64_t)(n - 1) * 3 * P;
+            float p[3], w[3], c[3];
+            for (int q = 0; q < 3; ++q) {
+                p[q] = pk[q * P + i];
+                w[q] = __fsub_rn(pp[q * P + i], p[q]);
+                const float tk = Tk[q * P + i];
+                const float ratio = tk == 0.f ? 0.f : __fdiv_rn(Tn[q * P + i], tk);
+                c[q] = __fmul_rn(ratio, Le[q * P + i]);
             }
-        } else {
-            drop = true;
+            drop = !place || !splat_one(sv, p, w, c, sum, cnt);   // an SVO without leaves places none
         }
     }
-    uint64_t b = __ballot(drop);
+    const uint64_t b = __ballot(drop);
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(dropped, (unsigned long long)__popcll(b));
 }
 
@@ -162,6 +198,15 @@ hipError_t launch_accumulate(wfpg_svo *svo, const float *pos, const float *wo, c
         hipLaunchKernelGGL(k_add_dropped, dim3(1), dim3(1), 0, s, svo->d_dropped,
                            (unsigned long long)n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_paths(wfpg_svo *svo, const float *pos, const float *T, const float *eye,
+                                   const int32_t *hit, const float *Le, int64_t P, int d, hipStream_t s)
+{
+    if (P > 0 && d > 0)
+        hipLaunchKernelGGL(k_splat_paths, dim3(nblocks(P * d, 256)), dim3(256), 0, s, svo->view(), pos, T, eye, hit,
+                           Le, P, d, svo->n[svo->depth] > 0, svo->d_sum, svo->d_cnt, svo->d_dropped);
     return hipGetLastError();
 }
 

@@ -282,6 +282,16 @@ wfpg_status svo_accumulate(wfpg_svo *svo, const float *pos, const float *wo, con
     return from_hip(e);
 }
 
+wfpg_status svo_accumulate_paths(wfpg_svo *svo, const float *pos, const float *T, const float *eye,
+                                 const int32_t *hit, const float *Le, int64_t P, int32_t d, void *hip_stream)
+{
+    if (!svo || P < 0 || d < 1 || d > 64 || (P > 0 && (!pos || !T || !eye || !hit || !Le))) return WFPG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_accumulate_paths(svo, pos, T, eye, hit, Le, P, d, s);
+    if (e == hipSuccess) e = launch_propagate(svo, s);
+    return from_hip(e);
+}
+
 static wfpg_status guide_common(const wfpg_svo *svo, int mode, const wfpg_opts *o, GuideArgs &a,
                                 void *hip_stream)
 {

@@ -65,6 +65,8 @@ hipError_t launch_build(struct ::wfpg_svo *svo, const RectCells *d_rects, const 
                         int64_t n_rects, int64_t n_frag, hipStream_t s);
 hipError_t launch_accumulate(struct ::wfpg_svo *svo, const float *pos, const float *wo,
                              const float *rgb, int64_t n, hipStream_t s);
+hipError_t launch_accumulate_paths(struct ::wfpg_svo *svo, const float *pos, const float *T, const float *eye,
+                                   const int32_t *hit, const float *Le, int64_t P, int d, hipStream_t s);
 hipError_t launch_propagate(struct ::wfpg_svo *svo, hipStream_t s);
 
 enum GuideMode {
