@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 MEASURED_TRAFFIC = {
     "sources_sha256": "d1df27a097d0347f04719b2bfca6e85fc35de292beaffebec3eaaf425f3e2903",
     "N": 16,
-    "tile": {"waves_per_block": 4, "lds_levels": 5, "blocks_per_cu": 8},
+    "tile": {"waves_per_block": 4, "blocks_per_cu": 8},
     "bytes_per_launch": 5112374822,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]

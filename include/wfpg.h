@@ -340,15 +340,14 @@ wfpg_status wfpg_debug_march(const wfpg_svo *svo, const float *pos, int64_t n,
 
 /* ---------------------------------------------------------------------
  * Launch shape of the guide kernels and its autotuner. A tile is the number
- * of waves per workgroup (one wave per vertex), the number of top SVO levels
- * staged in LDS (levels 0..lds_levels-1) and the persistent grid size in
- * workgroups per compute unit. Tiles are cached per (device, N, SVO depth,
- * exitance format); guide_pdf, guide_sample, pdf_eval use the cached tile or
- * a default. Results never depend on the tile.
+ * of waves per workgroup (each wave keeps up to four vertices in flight) and
+ * the persistent grid size in workgroups per compute unit. Tiles are cached
+ * per (device, N, SVO depth, exitance format); guide_pdf, guide_sample,
+ * pdf_eval use the cached tile or a default. Results never depend on the
+ * tile.
  * ------------------------------------------------------------------- */
 typedef struct {
     int32_t waves_per_block;
-    int32_t lds_levels;
     int32_t blocks_per_cu;
 } wfpg_tile;
 
@@ -356,8 +355,8 @@ typedef struct {
 wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out);
 
 /* Force a tile for resolution N (EINVAL if it exceeds the kernel's limits:
- * 1..16 waves, 1..depth+1 levels, 1..64 blocks per CU, the device's LDS
- * per workgroup: 160 KiB on MI355X). */
+ * 1..16 waves, 1..64 blocks per CU, the device's LDS per workgroup: 160 KiB
+ * on MI355X). */
 wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile);
 
 /* Sweep candidate tiles for resolution N on the given DEVICE queue pos

@@ -56,7 +56,7 @@ class WfpgError(RuntimeError):
 
 
 class Tile(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int32), ("lds_levels", C.c_int32),
+    _fields_ = [("waves_per_block", C.c_int32),
                 ("blocks_per_cu", C.c_int32)]
 
 
@@ -390,12 +390,11 @@ def march_counts(svo: SVO, pos, opts: Opts, stream=None):
 def get_tile(svo: SVO, N: int) -> dict:
     t = Tile()
     _check("wfpg_get_tile", lib().wfpg_get_tile(svo.handle, N, C.byref(t)))
-    return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
-                blocks_per_cu=t.blocks_per_cu)
+    return dict(waves_per_block=t.waves_per_block, blocks_per_cu=t.blocks_per_cu)
 
 
-def set_tile(svo: SVO, N: int, waves_per_block: int, lds_levels: int, blocks_per_cu: int):
-    t = Tile(waves_per_block, lds_levels, blocks_per_cu)
+def set_tile(svo: SVO, N: int, waves_per_block: int, blocks_per_cu: int):
+    t = Tile(waves_per_block, blocks_per_cu)
     _check("wfpg_set_tile", lib().wfpg_set_tile(svo.handle, N, C.byref(t)))
 
 
@@ -405,8 +404,7 @@ def autotune(svo: SVO, pos, N: int, reps: int = 3, stream=None) -> dict:
     ms = C.c_float(0)
     _check("wfpg_autotune", lib().wfpg_autotune(svo.handle, _dptr(pos, 3, "pos"), pos.shape[1], N,
                                                 reps, _stream(stream), C.byref(t), C.byref(ms)))
-    return dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
-                blocks_per_cu=t.blocks_per_cu, ms=ms.value)
+    return dict(waves_per_block=t.waves_per_block, blocks_per_cu=t.blocks_per_cu, ms=ms.value)
 
 
 def autotune_n(svo: SVO, pos, budget_ns_per_vertex: float, reps: int = 3, stream=None) -> dict:
@@ -417,8 +415,7 @@ def autotune_n(svo: SVO, pos, budget_ns_per_vertex: float, reps: int = 3, stream
     _check("wfpg_autotune_n", lib().wfpg_autotune_n(svo.handle, _dptr(pos, 3, "pos"), pos.shape[1], reps,
                                                     budget_ns_per_vertex, _stream(stream), C.byref(N),
                                                     C.byref(t), C.cast(ms, C.c_void_p)))
-    return dict(N=N.value, tile=dict(waves_per_block=t.waves_per_block, lds_levels=t.lds_levels,
-                                     blocks_per_cu=t.blocks_per_cu),
+    return dict(N=N.value, tile=dict(waves_per_block=t.waves_per_block, blocks_per_cu=t.blocks_per_cu),
                 ms_per_N={8: ms[0], 16: ms[1], 32: ms[2]})
 
 

@@ -496,11 +496,20 @@ wfpg_status wfpg_dir_table_jitter(int32_t N, uint32_t jitter_key, float *out)
     float *d = nullptr;
     hipError_t e = hipMalloc((void **)&d, bytes);
     if (e != hipSuccess) return from_hip(e);
-    hipLaunchKernelGGL(k_jitter_table, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, 0, N, jitter_key, d);
-    e = hipGetLastError();
+    e = wfpg::launch_jitter_table(N, jitter_key, d, 0);
     if (e == hipSuccess) e = hipMemcpy(out, d, bytes, hipMemcpyDeviceToHost);
     const hipError_t f = hipFree(d);
     return from_hip(e != hipSuccess ? e : f);
 }
 
 }  // extern "C"
+
+namespace wfpg {
+
+hipError_t launch_jitter_table(int N, uint32_t key, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_jitter_table, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N, key, out);
+    return hipGetLastError();
+}
+
+}  // namespace wfpg

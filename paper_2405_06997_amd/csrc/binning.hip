@@ -360,27 +360,20 @@ constexpr int bin_field_threads() { return N * N < 1024 ? N * N : 1024; }
 template <int N>
 __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     SvoView sv, const float *__restrict__ opos, int64_t cap, const int32_t *nbins, const float *__restrict__ dirtab,
-    float eps, float omega, float pdf_scale, int lds_levels, int jitter, uint32_t jitter_key, int blur, float *pdf,
-    int32_t *err)
+    float eps, float omega, float pdf_scale, int blur, float *pdf, int32_t *err)
 {
     constexpr int NN = N * N, B = bin_field_threads<N>(), PER = NN / B;
-    extern __shared__ uint64_t lbits[];
+    extern __shared__ float L[];   // the bin's field values
     __shared__ float wsum[16];
     const int64_t b = blockIdx.x;
     if (b >= *nbins) return;   // uniform over the block
-    const uint32_t nlw = woff(lds_levels);
-    for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
-    __syncthreads();
     const uint64_t *gbits = sv.bits;
-    auto bits = [gbits, lds_levels](int lvl, uint32_t wi) -> uint64_t {
-        return lvl < lds_levels ? lbits[wi] : gbits[wi];
-    };
+    auto bits = [gbits](int, uint32_t wi) -> uint64_t { return gbits[wi]; };   // cached global reads
     const int D = sv.depth, fmt = sv.fmt;
     const uint32_t O[3] = {core::quantize_pos(opos[b]), core::quantize_pos(opos[cap + b]),
                            core::quantize_pos(opos[2 * cap + b])};
     const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D), O[2] >> (WFPG_FINE - D));
     const bool occ = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
-    float *L = reinterpret_cast<float *>(lbits + nlw);   // the bin's field values
     // each lane marches its cones c = tid + B j one after another, a few
     // occupancy tests at a time, so a wave waits for its busiest lane's total
     // rather than for the longest ray of every round
@@ -392,13 +385,9 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     while (true) {
         if (!act && j < PER) {
             const int c = threadIdx.x + B * j;
-            if (jitter) {
-                aa::jitter_dir(N, c, jitter_key, dx, dy, dz);
-            } else {
-                dx = dirtab[3 * c];
-                dy = dirtab[3 * c + 1];
-                dz = dirtab[3 * c + 2];
-            }
+            dx = dirtab[3 * c];
+            dy = dirtab[3 * c + 1];
+            dz = dirtab[3 * c + 2];
             uint32_t a0, a1, a2;
             int s0, s1, s2;
             core::split_dir(core::quantize_dir(dx), a0, s0);
@@ -510,20 +499,20 @@ hipError_t grow(void *&p, size_t &have, size_t want)
 struct BinWork {
     void *count = nullptr, *mark = nullptr, *okey = nullptr, *slot = nullptr, *node_of = nullptr,
          *bin_of = nullptr, *nbins = nullptr, *opos = nullptr, *pdf = nullptr, *rcdf = nullptr,
-         *mcdf = nullptr, *coarse = nullptr;
+         *mcdf = nullptr, *coarse = nullptr, *jtab = nullptr;
     size_t s_count = 0, s_mark = 0, s_okey = 0, s_slot = 0, s_node = 0, s_bin = 0, s_nbins = 0, s_opos = 0,
-           s_pdf = 0, s_rcdf = 0, s_mcdf = 0, s_coarse = 0;
+           s_pdf = 0, s_rcdf = 0, s_mcdf = 0, s_coarse = 0, s_jtab = 0;
 };
 
 // One workgroup per bin: the field of each bin origin into W->pdf.
 template <int N>
 void launch_bin_field(int32_t nb, size_t lds, hipStream_t s, const SvoView &v, const BinWork *W, int64_t cap,
-                      const float *tab, const wfpg_bin_opts *o, float omega, float scale, int lds_levels,
+                      const float *tab, const wfpg_bin_opts *o, float omega, float scale,
                       const wfpg_svo *svo)
 {
     hipLaunchKernelGGL(k_bin_field<N>, dim3((unsigned)nb), dim3(bin_field_threads<N>()), lds, s, v,
-                       (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, o->eps, omega, scale, lds_levels,
-                       (int)o->jitter, o->jitter_key, (int)o->blur, (float *)W->pdf, svo->d_err);
+                       (const float *)W->opos, cap, (const int32_t *)W->nbins, tab, o->eps, omega, scale,
+                       (int)o->blur, (float *)W->pdf, svo->d_err);
 }
 
 void destroy_bin_work(void *w)
@@ -531,7 +520,7 @@ void destroy_bin_work(void *w)
     BinWork *b = (BinWork *)w;
     if (!b) return;
     void *ps[] = {b->count, b->mark, b->okey, b->slot, b->node_of, b->bin_of, b->nbins, b->opos, b->pdf,
-                  b->rcdf, b->mcdf, b->coarse};
+                  b->rcdf, b->mcdf, b->coarse, b->jtab};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete b;
@@ -649,15 +638,19 @@ hipError_t binned_fields(const wfpg_svo *svo, const float *pos, int64_t n, uint6
     if (e == hipSuccess && nb > 0 && N >= WFPG_BIN_FIELD_MIN_N) {   // one workgroup per bin field
         const double pi = 3.14159265358979323846;
         const float *tab = device_dirtab(N);
-        const int lds_levels = std::min(6, svo->depth + 1);
-        const size_t lds = (size_t)level_woff(lds_levels) * 8 + (size_t)NN * 4;   // bitmap words, field
+        if (opts->jitter && tab) {   // this call's jittered cone directions, once, into the bin scratch
+            e = grow(W->jtab, W->s_jtab, (size_t)NN * 3 * 4);
+            if (e == hipSuccess) e = launch_jitter_table(N, opts->jitter_key, (float *)W->jtab, s);
+            tab = e == hipSuccess ? (const float *)W->jtab : nullptr;
+        }
+        const size_t lds = (size_t)NN * 4;   // the field
         const SvoView v = svo->view();
         const float omega = (float)(4.0 * pi / (double)NN), scale = (float)((double)NN / (4.0 * pi));
         if (!tab) e = hipErrorOutOfMemory;
-        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
-        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
-        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
-        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts, omega, scale, lds_levels, svo);
+        else if (N == 16) launch_bin_field<16>(nb, lds, s, v, W, cap, tab, opts, omega, scale, svo);
+        else if (N == 32) launch_bin_field<32>(nb, lds, s, v, W, cap, tab, opts, omega, scale, svo);
+        else if (N == 64) launch_bin_field<64>(nb, lds, s, v, W, cap, tab, opts, omega, scale, svo);
+        else launch_bin_field<128>(nb, lds, s, v, W, cap, tab, opts, omega, scale, svo);
         if (e == hipSuccess) e = hipGetLastError();
     } else if (e == hipSuccess && nb > 0) {   // one field per bin origin (plane stride cap)
         GuideArgs a;

@@ -324,7 +324,7 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// LDS layout of a block: [top-level bitmap words][N*N*3 bin directions]
+// LDS layout of a block: [N*N*3 bin directions]
 // [N*N*3 quantized directions |q| | sign << 31][per wave: kSlots vertex
 // slots x N*N hit records][per wave: kSlots node-test counters (count
 // mode)]. A hit record is the node the cone footprint selects, as
@@ -342,7 +342,7 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 // BLUR: the field is blurred before its CDF (a variant of its own: the blur's
 // registers would lower the occupancy of the unblurred kernel).
 template <int N, int MODE, bool BLUR>
-__global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds_levels)
+__global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
 {
     constexpr int NN = N * N;
     constexpr int S = guide_slots(N);
@@ -351,14 +351,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int D = sv.depth;
-    const uint32_t nlw = woff(lds_levels);
-    uint64_t *lbits = smem;
-    float *ldir = reinterpret_cast<float *>(smem + nlw);
+    float *ldir = reinterpret_cast<float *>(smem);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
     constexpr int RW = guide_rec_words(MODE);
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
     uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * RW * NN + (size_t)wave * S;
-    for (uint32_t w = threadIdx.x; w < nlw; w += blockDim.x) lbits[w] = sv.bits[w];
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         float d[3];
         if (a.jitter) {
@@ -379,10 +376,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
 
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
     const int64_t ps = a.stride ? a.stride : n;   // SoA plane stride
+    // every occupancy test is a plain global load: the top levels stay hot in
+    // the L1/L2 caches (staging them in LDS made the loads flat loads through
+    // a pointer select, which measured slower)
     const uint64_t *gbits = sv.bits;
-    auto bits = [gbits, lbits, lds_levels](int lvl, uint32_t wi) -> uint64_t {
-        return lvl < lds_levels ? lbits[wi] : gbits[wi];
-    };
+    auto bits = [gbits](int, uint32_t wi) -> uint64_t { return gbits[wi]; };
 
     // wave-uniform stream and slot state
     int64_t chunk_next = 0;
@@ -488,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a, int lds
         Hit h = {-1, 0u, 0u};
         if (lbin >= 0) {
             for (int m = 0; m < kMicro; ++m) {
-                res = core::micro_step(st, D, bits, 5, vis, h);
+                res = core::micro_step<true>(st, D, bits, 5, vis, h);
                 if (res != core::STEP_CONTINUE) break;
             }
             if (res == core::STEP_CONTINUE && (iters += kMicro) >= core::kMaxTests) {
@@ -578,8 +576,7 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
         }
     }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.queue_ctr);
-    int levels = tc.lds_levels;
-    void *args[] = {(void *)&v, (void *)&a, (void *)&levels};
+    void *args[] = {(void *)&v, (void *)&a};
     const hipError_t e = hipLaunchKernel(fn, dim3(grid), blk, args, lds, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();

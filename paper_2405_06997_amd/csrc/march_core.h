@@ -150,9 +150,18 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
     }
 }
 
-template <class Bits>
+// OPAQUE_SIGNS: hide the ray's signs from the optimizer at every step, so the
+// sign tests stay in the loop as vector compares. For a caller whose scalar
+// registers are already full (the guide kernel's queue and slot bookkeeping),
+// the loop-invariant lane masks the compiler would otherwise hoist are spilled
+// into vector lanes and cost two lane moves per use; elsewhere the hoisted
+// masks are the cheaper form.
+template <bool OPAQUE_SIGNS = false, class Bits>
 WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (OPAQUE_SIGNS) asm volatile("" : "+v"(s.sg0), "+v"(s.sg1), "+v"(s.sg2));
+#endif
     if (s.phase == PH_ADVANCE) {
         const uint32_t size = 1u << (kFine - s.lvl);
         const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);

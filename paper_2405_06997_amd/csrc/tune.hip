@@ -1,5 +1,5 @@
-// Autotuner of the guide kernel's launch shape (waves per block, SVO levels
-// staged in LDS, persistent grid size), cached per (device, N, depth, format).
+// Autotuner of the guide kernel's launch shape (waves per block, persistent
+// grid size), cached per (device, N, depth, format).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +31,6 @@ TileConfig default_tile(int N, int depth)
 {
     TileConfig t;
     t.waves_per_block = 4;   // the tuner's usual pick for the frame-scale room at N = 16
-    t.lds_levels = 5;
     t.blocks_per_cu = N == 32 ? 4 : 8;
     return legalize_tile(t, N, depth);
 }
@@ -58,8 +57,7 @@ TileConfig legalize_tile(TileConfig t, int N, int depth)
 {
     t.waves_per_block = std::min(std::max(t.waves_per_block, 1), 16);
     t.blocks_per_cu = std::min(std::max(t.blocks_per_cu, 1), 64);
-    t.lds_levels = std::min(std::max(t.lds_levels, 1), std::min(7, depth + 1));
-    while (t.lds_levels > 1 && guide_lds_bytes(N, t) > guide_max_lds()) --t.lds_levels;
+    (void)depth;
     while (t.waves_per_block > 1 && guide_lds_bytes(N, t) > guide_max_lds()) --t.waves_per_block;
     return t;
 }
@@ -83,7 +81,6 @@ wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out)
     if (!svo || !out || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
     const TileConfig t = choose_tile(svo, N);
     out->waves_per_block = t.waves_per_block;
-    out->lds_levels = t.lds_levels;
     out->blocks_per_cu = t.blocks_per_cu;
     return WFPG_OK;
 }
@@ -93,10 +90,8 @@ wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile)
     if (!svo || !tile || (N != 8 && N != 16 && N != 32)) return WFPG_EINVAL;
     TileConfig t;
     t.waves_per_block = tile->waves_per_block;
-    t.lds_levels = tile->lds_levels;
     t.blocks_per_cu = tile->blocks_per_cu;
-    if (t.waves_per_block < 1 || t.waves_per_block > 16 || t.blocks_per_cu < 1 ||
-        t.blocks_per_cu > 64 || t.lds_levels < 1 || t.lds_levels > svo->depth + 1 ||
+    if (t.waves_per_block < 1 || t.waves_per_block > 16 || t.blocks_per_cu < 1 || t.blocks_per_cu > 64 ||
         guide_lds_bytes(N, t) > guide_max_lds())
         return WFPG_EINVAL;
     std::lock_guard<std::mutex> g(g_mu);
@@ -132,25 +127,18 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
         a.dir_out = d_dir;
         a.pdf_out = d_pdf;
         const int waves[] = {1, 2, 4, 8, 16};
-        const int levels[] = {5, 6, 7};
         const int bpcu[] = {1, 2, 4, 8, 16};
         std::vector<TileConfig> cand;
         for (int w : waves)
-            for (int l : levels)
-                for (int b : bpcu) {
-                    TileConfig t;
-                    t.waves_per_block = w;
-                    t.lds_levels = std::min(l, svo->depth + 1);
-                    t.blocks_per_cu = b;
-                    // at least 4 and at most 32 waves per CU: fewer cannot hide the
-                    // march's memory latency, more cannot be resident
-                    if (guide_lds_bytes(N, t) > guide_max_lds() || w * b > 32 || w * b < 4) continue;
-                    bool dup = false;
-                    for (const TileConfig &c : cand)
-                        dup = dup || (c.waves_per_block == t.waves_per_block &&
-                                      c.lds_levels == t.lds_levels && c.blocks_per_cu == t.blocks_per_cu);
-                    if (!dup) cand.push_back(t);
-                }
+            for (int b : bpcu) {
+                TileConfig t;
+                t.waves_per_block = w;
+                t.blocks_per_cu = b;
+                // at least 4 and at most 32 waves per CU: fewer cannot hide the
+                // march's memory latency, more cannot be resident
+                if (guide_lds_bytes(N, t) > guide_max_lds() || w * b > 32 || w * b < 4) continue;
+                cand.push_back(t);
+            }
         for (const TileConfig &t : cand) {
             e = launch_guide(svo, N, MODE_SAMPLE, a, t, s);   // warm-up
             if (e != hipSuccess) break;
@@ -168,8 +156,8 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
             std::sort(ts.begin(), ts.end());
             const float med = ts[ts.size() / 2];
             if (std::getenv("WFPG_TUNE_VERBOSE"))
-                std::fprintf(stderr, "tune N=%d waves=%d lds_levels=%d blocks/CU=%d: %.3f ms\n", N,
-                             t.waves_per_block, t.lds_levels, t.blocks_per_cu, med);
+                std::fprintf(stderr, "tune N=%d waves=%d blocks/CU=%d: %.3f ms\n", N, t.waves_per_block,
+                             t.blocks_per_cu, med);
             if (med < best_t) { best_t = med; best = t; }
         }
     }
@@ -185,7 +173,6 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
     }
     if (best_out) {
         best_out->waves_per_block = best.waves_per_block;
-        best_out->lds_levels = best.lds_levels;
         best_out->blocks_per_cu = best.blocks_per_cu;
     }
     if (best_ms) *best_ms = best_t;

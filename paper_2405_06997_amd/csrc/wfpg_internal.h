@@ -104,16 +104,14 @@ struct GuideArgs {
 };
 
 struct TileConfig {          // launch shape chosen by the autotuner
-    int waves_per_block;     // 1, 2, 4, 8
-    int lds_levels;          // top levels held in LDS: 5, 6 or 7
+    int waves_per_block;     // 1 .. 16
     int blocks_per_cu;       // persistent grid size factor
 };
 
 hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const GuideArgs &a,
                         const TileConfig &tc, hipStream_t s);
 
-// LDS bytes of one guide block: staged bitmap levels, bin directions and the
-// per-wave hit records.
+// LDS bytes of one guide block: bin directions and the per-wave hit records.
 // Query vertices a wave keeps in flight (hit records of each in LDS).
 __host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : 4; }
 
@@ -124,7 +122,7 @@ __host__ __device__ constexpr int guide_rec_words(int mode) { return mode == MOD
 inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE)
 {
     const size_t S = (size_t)guide_slots(N);
-    return (size_t)level_woff(tc.lds_levels) * 8 + (size_t)N * N * 3 * 4 * 2 +
+    return (size_t)N * N * 3 * 4 * 2 +
            (size_t)tc.waves_per_block * S * ((size_t)guide_rec_words(mode) * N * N * 4 + 4);
 }
 // LDS a guide workgroup may use on the current device (all modes but debug).
@@ -149,6 +147,8 @@ hipError_t note_error(hipError_t e, const char *file, int line);
         if (e_ != hipSuccess) return ::wfpg::note_error(e_, __FILE__, __LINE__);             \
     } while (0)
 const float *device_dirtab(int N);   // uploaded once per N per device
+// The jittered cone directions of key `key` (N*N*3 FP32, device), on `s`.
+hipError_t launch_jitter_table(int N, uint32_t key, float *out, hipStream_t s);
 void host_dir_table(int N, float *out);
 
 }  // namespace wfpg

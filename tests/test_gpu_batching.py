@@ -71,14 +71,13 @@ def test_autotune_and_tiles(env):
     assert best["ms"] > 0
     assert w.get_tile(g, 16)["waves_per_block"] == best["waves_per_block"]
     # results do not depend on the launch shape
-    for tile in [(1, 5, 2), (6, 5, 16), (4, 6, 8), (2, 7, 4)]:
+    for tile in [(1, 2), (6, 16), (4, 8), (2, 4), (16, 2)]:
         w.set_tile(g, 16, *tile)
         d, p = w.guide_sample(g, pos, w.make_opts(N=16), seed=1, bounce=0)
         assert torch.equal(d, ref_d) and torch.equal(p, ref_p)
-    with pytest.raises(w.WfpgError):
-        w.set_tile(g, 16, 0, 5, 2)
-    with pytest.raises(w.WfpgError):
-        w.set_tile(g, 16, 4, 12, 2)
+    for bad in [(0, 2), (17, 2), (4, 0), (4, 65)]:
+        with pytest.raises(w.WfpgError):
+            w.set_tile(g, 16, *bad)
 
 
 def test_autotune_picks_finest_N_within_budget(env):
