@@ -363,7 +363,8 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
     float eps, float omega, float pdf_scale, int blur, float *pdf, int32_t *err)
 {
     constexpr int NN = N * N, B = bin_field_threads<N>(), PER = NN / B;
-    extern __shared__ float L[];   // the bin's field values
+    extern __shared__ float L[];   // the bin's field values (first the cones' hit records)
+    uint32_t *Lrec = reinterpret_cast<uint32_t *>(L);
     __shared__ float wsum[16];
     const int64_t b = blockIdx.x;
     if (b >= *nbins) return;   // uniform over the block
@@ -374,20 +375,24 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
                            core::quantize_pos(opos[2 * cap + b])};
     const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D), O[2] >> (WFPG_FINE - D));
     const bool occ = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
-    // each lane marches its cones c = tid + B j one after another, a few
-    // occupancy tests at a time, so a wave waits for its busiest lane's total
-    // rather than for the longest ray of every round
-    int j = 0, it = 0;
-    bool act = false;
+    // lanes march cones one after another, a few occupancy tests at a time;
+    // a lane that finishes takes the block's next unmarched cone (one LDS
+    // atomic per wave and refill), so lanes stay busy until the bin's cones
+    // run out instead of waiting for the lane with the longest share
+    __shared__ int s_next;
+    if (threadIdx.x == 0) s_next = B;   // cones 0..B-1 start on their thread
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    int cur = threadIdx.x, it = 0;
+    bool act = false, more = true;
     float dx = 0.f, dy = 0.f, dz = 0.f;
     core::MicroState st;
     float local = 0.f;
     while (true) {
-        if (!act && j < PER) {
-            const int c = threadIdx.x + B * j;
-            dx = dirtab[3 * c];
-            dy = dirtab[3 * c + 1];
-            dz = dirtab[3 * c + 2];
+        if (!act && more) {
+            dx = dirtab[3 * cur];
+            dy = dirtab[3 * cur + 1];
+            dz = dirtab[3 * cur + 2];
             uint32_t a0, a1, a2;
             int s0, s1, s2;
             core::split_dir(core::quantize_dir(dx), a0, s0);
@@ -398,7 +403,7 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
             act = true;
             it = 0;
         }
-        if (__ballot(act) == 0ull) break;   // this wave has marched all its cones
+        if (__ballot(act) == 0ull) break;   // no cone left for this wave
         int res = core::STEP_CONTINUE;
         core::Hit h = {-1, 0u, 0u};
         if (act) {
@@ -413,29 +418,55 @@ __global__ void __launch_bounds__(bin_field_threads<N>()) k_bin_field(
             }
         }
         if (act && res != core::STEP_CONTINUE) {
-            float val = fmt == WFPG_FP32 ? eps : round16_bin(eps, fmt);
+            // the cone footprint (Eq. 7) is decided here; its node's value is read in
+            // one pass after the march, so a finishing lane never stalls the wave
+            // on dependent loads: record = 1 << 3*level | node key (0: a miss)
+            uint32_t rv = 0u;
             if (res == core::STEP_HIT) {
                 const float dsel = h.axis == 0 ? dx : (h.axis == 1 ? dy : dz);
                 const int k = core::footprint_levels(h.delta, fabsf(dsel), D, omega);
-                const int lf = D - k;
-                const uint32_t node = h.key >> (3 * k);
-                int64_t g = -1;
-                node_index(sv, lf, node, g);   // the footprint node is an ancestor of the hit leaf
-                const float4 Nn = sv.nrm[g];
-                const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
-                if (fmt == WFPG_FP32) {
-                    const float2 e = sv.e32[g];
-                    val = (side ? e.y : e.x) + eps;
-                } else {
-                    const uint32_t pk = sv.e16[g];
-                    val = round16_bin(unpack16_bin(pk, side, fmt) + eps, fmt);
-                }
+                rv = (1u << (3 * (D - k))) | (h.key >> (3 * k));
             }
-            L[threadIdx.x + B * j] = val;
-            local += val;
-            ++j;
+            Lrec[cur] = rv;
             act = false;
         }
+        const uint64_t want = __ballot(!act && more);
+        if (want) {
+            const int first = __ffsll((unsigned long long)want) - 1;
+            int base = 0;
+            if (lane == first) base = atomicAdd(&s_next, __popcll(want));
+            base = __shfl(base, first);
+            if (!act && more) {
+                const uint64_t below = want & ((1ull << lane) - 1ull);
+                cur = base + __popcll(below);
+                more = cur < NN;
+            }
+        }
+    }
+    __syncthreads();   // every record of the bin is written
+    // values of this thread's cones: footprint node, side, exitance + eps
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + B * q;
+        const uint32_t r = Lrec[c];
+        float val = fmt == WFPG_FP32 ? eps : round16_bin(eps, fmt);
+        if (r) {
+            const int lf = (31 - __builtin_clz(r)) / 3;
+            const uint32_t node = r ^ (1u << (3 * lf));
+            int64_t g = -1;
+            node_index(sv, lf, node, g);   // the footprint node is an ancestor of the hit leaf
+            const float4 Nn = sv.nrm[g];
+            const int side =
+                core::dot3(Nn.x, Nn.y, Nn.z, dirtab[3 * c], dirtab[3 * c + 1], dirtab[3 * c + 2]) < 0.f ? 0 : 1;
+            if (fmt == WFPG_FP32) {
+                const float2 e = sv.e32[g];
+                val = (side ? e.y : e.x) + eps;
+            } else {
+                const uint32_t pk = sv.e16[g];
+                val = round16_bin(unpack16_bin(pk, side, fmt) + eps, fmt);
+            }
+        }
+        L[c] = val;   // in place over the thread's own record
+        local += val;
     }
     if (blur) {   // uniform over the block: blur the whole field, then re-total
         float t[PER];
