@@ -281,10 +281,13 @@ __global__ void k_bin_coarse(const float *__restrict__ pdf, const int32_t *nbins
     coarse[t] = F;
 }
 
-// Product sample of every member (Sec. 3.6), one wave per member as the paper
-// gives a warp to a ray: lane C takes cell C's sum of the member's bin field
-// and the member's table entry, the wave picks the cell, then the fine bin
-// inside it from the bin field. Grid-stride over members.
+// Product sample of every member (Sec. 3.6), a wave per member at a time as
+// the paper gives a warp to a ray: lane C takes cell C's sum of the member's
+// bin field and the member's table entry, the wave picks the cell, then the
+// fine bin inside it from the bin field. A wave owns 64 consecutive members:
+// lane m draws member m's uniforms and loads its bin and normal up front,
+// the wave then walks the members one by one, and all 64 directions are
+// decoded and written together at the end. Grid-stride over member batches.
 template <int N>
 __global__ void __launch_bounds__(256) k_bin_product(int64_t n, uint64_t seed, uint32_t bounce,
                                                      const int32_t *bin_of, const int32_t *slot_of,
@@ -295,44 +298,64 @@ __global__ void __launch_bounds__(256) k_bin_product(int64_t n, uint64_t seed, u
     constexpr int SB = N / prod::kCells;
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += waves) {
-        const int32_t bin = bin_of[i];   // wave-uniform: one member per wave
-        if (lane == 0 && bin_out) bin_out[i] = bin;
-        if (bin < 0) {
-            if (lane == 0) {
-                dir_out[i] = 0.f;
-                dir_out[n + i] = 0.f;
-                dir_out[2 * n + i] = 0.f;
-                pdf_out[i] = 0.f;
-            }
-            continue;
+    const float tx = tab8[3 * lane], ty = tab8[3 * lane + 1], tz = tab8[3 * lane + 2];   // cell centre
+    for (int64_t base = ((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6) * 64; base < n; base += waves * 64) {
+        const int64_t im = base + lane;   // this lane's member
+        const bool valid = im < n;
+        const int32_t bin = valid ? bin_of[im] : -1;
+        if (valid && bin_out) bin_out[im] = bin;
+        const int32_t sl = bin >= 0 ? slot_of[bin] : -1;
+        float nx = 0.f, ny = 0.f, nz = 0.f;
+        if (valid && !bsdf) {
+            nx = nrm[im];
+            ny = nrm[n + im];
+            nz = nrm[2 * n + im];
         }
-        const int64_t sl = slot_of[bin];
-        prod::Upper q;
-        prod::upper_level(coarse[sl * 64 + lane], prod::table_entry(nrm, bsdf, i, n, tab8, lane), lane, q);
-        uint32_t w[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 2u};
+        uint32_t w[4] = {(uint32_t)(uint64_t)im, (uint32_t)((uint64_t)im >> 32), bounce, 2u};
         core::philox(w, (uint32_t)seed, (uint32_t)(seed >> 32));
-        const int c = prod::pick_cell(q, (float)(w[0] >> 8) * 5.9604644775390625e-8f,
-                                      (float)(w[1] >> 8) * 5.9604644775390625e-8f, lane);
-        uint32_t r[4] = {(uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), bounce, 0u};
+        uint32_t r[4] = {(uint32_t)(uint64_t)im, (uint32_t)((uint64_t)im >> 32), bounce, 0u};
         core::philox(r, (uint32_t)seed, (uint32_t)(seed >> 32));
-        const int V = c >> 3, U = c & 7;
-        const float *blk = pdf + sl * N * N + (V * SB) * N + U * SB;
-        int dv = 0, du = 0;
-        const float Lb = prod::pick_fine<SB>([&](int y, int x) { return blk[y * N + x]; },
-                                             (float)(r[0] >> 8) * 5.9604644775390625e-8f,
-                                             (float)(r[1] >> 8) * 5.9604644775390625e-8f, lane, dv, du);
-        const float Pc = __shfl(q.P, c), Fc = __shfl(q.F, c);
-        if (lane == 0) {
-            const float inv = 1.f / (float)N;
-            const float u3 = (float)(r[2] >> 8) * 5.9604644775390625e-8f;
-            const float u4 = (float)(r[3] >> 8) * 5.9604644775390625e-8f;
-            float ox, oy, oz;
-            oct_decode_f((float)(U * SB + du) * inv + u3 * inv, (float)(V * SB + dv) * inv + u4 * inv, ox, oy, oz);
-            dir_out[i] = ox;
-            dir_out[n + i] = oy;
-            dir_out[2 * n + i] = oz;
-            pdf_out[i] = (Pc / q.total) * (Lb / Fc) * scale;
+        const float w1 = (float)(w[0] >> 8) * 5.9604644775390625e-8f, w2 = (float)(w[1] >> 8) * 5.9604644775390625e-8f;
+        const float u1 = (float)(r[0] >> 8) * 5.9604644775390625e-8f, u2 = (float)(r[1] >> 8) * 5.9604644775390625e-8f;
+        int my_u = 0, my_v = 0;
+        float my_pdf = 0.f;
+        const int cnt = (int)min((int64_t)64, n - base);
+        for (int m = 0; m < cnt; ++m) {   // wave-uniform
+            const int32_t slm = __shfl(sl, m);
+            if (slm < 0) continue;
+            float x;
+            if (bsdf) {
+                x = bsdf[(base + m) * 64 + lane];
+            } else {
+                x = core::dot3(__shfl(nx, m), __shfl(ny, m), __shfl(nz, m), tx, ty, tz);
+            }
+            prod::Upper q;
+            prod::upper_level(coarse[(int64_t)slm * 64 + lane], x > 0.f ? x : 0.f, lane, q);
+            const int c = prod::pick_cell(q, __shfl(w1, m), __shfl(w2, m), lane);
+            const int V = c >> 3, U = c & 7;
+            const float *blk = pdf + (int64_t)slm * N * N + (V * SB) * N + U * SB;
+            int dv = 0, du = 0;
+            const float Lb = prod::pick_fine<SB>([&](int y, int xx) { return blk[y * N + xx]; }, __shfl(u1, m),
+                                                 __shfl(u2, m), lane, dv, du);
+            const float Pc = __shfl(q.P, c), Fc = __shfl(q.F, c);
+            if (lane == m) {
+                my_u = U * SB + du;
+                my_v = V * SB + dv;
+                my_pdf = (Pc / q.total) * (Lb / Fc) * scale;
+            }
+        }
+        if (valid) {
+            float ox = 0.f, oy = 0.f, oz = 0.f;
+            if (sl >= 0) {
+                const float inv = 1.f / (float)N;
+                const float u3 = (float)(r[2] >> 8) * 5.9604644775390625e-8f;
+                const float u4 = (float)(r[3] >> 8) * 5.9604644775390625e-8f;
+                oct_decode_f((float)my_u * inv + u3 * inv, (float)my_v * inv + u4 * inv, ox, oy, oz);
+            }
+            dir_out[im] = ox;
+            dir_out[n + im] = oy;
+            dir_out[2 * n + im] = oz;
+            pdf_out[im] = my_pdf;
         }
     }
 }
@@ -637,7 +660,7 @@ void launch_product(int64_t m, int64_t n, uint64_t seed, uint32_t bounce, const 
     const double pi = 3.14159265358979323846;
     hipLaunchKernelGGL(k_bin_coarse<N>, dim3(nblk(m * 64, 256)), dim3(256), 0, s, (const float *)W->pdf,
                        (const int32_t *)W->nbins, (float *)W->coarse);
-    const int64_t blocks = std::min<int64_t>(nblk(n, 4), (int64_t)1 << 20);   // 4 members per block
+    const int64_t blocks = std::min<int64_t>(nblk(n, 256), (int64_t)1 << 20);   // 64 members per wave
     hipLaunchKernelGGL(k_bin_product<N>, dim3((unsigned)blocks), dim3(256), 0, s, n, seed, bounce,
                        (const int32_t *)W->bin_of, (const int32_t *)W->slot, (const float *)W->pdf,
                        (const float *)W->coarse, nrm, bsdf, tab8, (float)((double)(N * N) / (4.0 * pi)), dir_out,
