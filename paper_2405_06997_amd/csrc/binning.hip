@@ -178,7 +178,7 @@ __global__ void k_bin_slots(int64_t nodes, const unsigned long long *origin_key,
 // (inclusive prefix of the row sums) of every bin's pdf; one thread per
 // (bin, row) for the rows, then the marginal from the row totals.
 template <int N>
-__global__ void k_bin_cdf(const float *__restrict__ pdf, const int32_t *nbins, float *rcdf, float *mcdf)
+__global__ void k_bin_cdf(const float *__restrict__ pdf, const int32_t *nbins, float *rcdf)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t b = t / N;
@@ -191,15 +191,33 @@ __global__ void k_bin_cdf(const float *__restrict__ pdf, const int32_t *nbins, f
         acc += p[u];
         r[u] = acc;
     }
-    if (v == 0) {   // marginal after the rows: recomputed from the pdf in row order
-        float m = 0.f;
-        for (int vv = 0; vv < N; ++vv) {
-            float rs = 0.f;
-            for (int u = 0; u < N; ++u) rs += pdf[b * N * N + vv * N + u];
-            m += rs;
-            mcdf[b * N + vv] = m;
-        }
+}
+
+// Marginal CDF of each bin over its rows: the row sums are the last entries
+// of the row CDFs (the same sequential FP32 sums), accumulated in row order.
+template <int N>
+__global__ void k_bin_marg(const float *__restrict__ rcdf, const int32_t *nbins, float *mcdf)
+{
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= *nbins) return;
+    float m = 0.f;
+    for (int v = 0; v < N; ++v) {
+        m += rcdf[b * N * N + v * N + N - 1];
+        mcdf[b * N + v] = m;
     }
+}
+
+// First k in [0, N) with t < cdf[k] (cdf non-decreasing), N - 1 if none.
+template <int N>
+__device__ __forceinline__ int upper_index(const float *cdf, float t)
+{
+    int lo = 0, hi = N - 1;   // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (t < cdf[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 __device__ __forceinline__ void oct_decode_f(float x, float y, float &dx, float &dy, float &dz)
@@ -246,15 +264,9 @@ __global__ void k_bin_sample(int64_t n, uint64_t seed, uint32_t bounce, const in
     const float u3 = (float)(c[2] >> 8) * 5.9604644775390625e-8f;
     const float u4 = (float)(c[3] >> 8) * 5.9604644775390625e-8f;
     const float *M = mcdf + s * N;
-    const float tv = u1 * M[N - 1];
-    int v = N - 1;
-    for (int k = N - 2; k >= 0; --k)
-        if (tv < M[k]) v = k;
+    const int v = upper_index<N>(M, u1 * M[N - 1]);
     const float *R = rcdf + s * N * N + v * N;
-    const float tu = u2 * R[N - 1];
-    int u = N - 1;
-    for (int k = N - 2; k >= 0; --k)
-        if (tu < R[k]) u = k;
+    const int u = upper_index<N>(R, u2 * R[N - 1]);
     const float inv = 1.f / (float)N;
     float ox, oy, oz;
     oct_decode_f((float)u * inv + u3 * inv, (float)v * inv + u4 * inv, ox, oy, oz);
@@ -646,7 +658,9 @@ void launch_cdf_sample(int64_t cap, int64_t n, uint64_t seed, uint32_t bounce, B
                        float *pdf_out, int32_t *bin_out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_cdf<N>, dim3(nblk(cap * N, 256)), dim3(256), 0, s, (const float *)W->pdf,
-                       (const int32_t *)W->nbins, (float *)W->rcdf, (float *)W->mcdf);
+                       (const int32_t *)W->nbins, (float *)W->rcdf);
+    hipLaunchKernelGGL(k_bin_marg<N>, dim3(nblk(cap, 256)), dim3(256), 0, s, (const float *)W->rcdf,
+                       (const int32_t *)W->nbins, (float *)W->mcdf);
     hipLaunchKernelGGL(k_bin_sample<N>, dim3(nblk(n, 256)), dim3(256), 0, s, n, seed, bounce,
                        (const int32_t *)W->bin_of, (const int32_t *)W->slot, (const float *)W->pdf,
                        (const float *)W->rcdf, (const float *)W->mcdf, dir_out, pdf_out, bin_out);
