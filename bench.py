@@ -68,7 +68,7 @@ def parse():
                     help="run one device copy of this size before timing (counter calibration)")
     ap.add_argument("--sections", default="binned,product,extract,learned,batching,precision",
                     help="comma-separated extra sections after the headline march step "
-                         "(binned, learned, batching, precision; empty for none)")
+                         "(binned, product, extract, learned, batching, precision; empty for none)")
     ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
     ap.add_argument("--train-pairs", type=int, default=50_000_000,
                     help="(vertex, march pdf) pairs the learned model is trained on")
@@ -87,9 +87,10 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; the path shards by "
-                                   "queue ranges with a replicated SVO (see DESIGN.md), but "
-                                   "no multi-GPU run is part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU only; the path would shard by queue "
+                                   "ranges over replicated SVOs, with one all-reduce of the splat "
+                                   "accumulators per frame, but runs on several GPUs are not "
+                                   "supported", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

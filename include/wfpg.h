@@ -51,7 +51,7 @@ enum {
     WFPG_ENOMEM = -2,      /* device or host allocation failed */
     WFPG_EDEVICE = -3,     /* HIP runtime error or device-side fault */
     WFPG_ESTATE = -4,      /* call not valid in the object's current state */
-    WFPG_EUNSUPPORTED = -5 /* valid request this build does not support */
+    WFPG_EUNSUPPORTED = -5 /* valid request the library does not support */
 };
 
 /* Storage format of the exitance and of the field bins (the CDF and pdf are
