@@ -356,6 +356,16 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     constexpr int RW = guide_rec_words(MODE);
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
     uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * RW * NN + (size_t)wave * S;
+    // The per-vertex finalization reads its arguments from an LDS copy: held
+    // in scalar registers across the march loop they overflowed the scalar
+    // file and were spilled into vector lanes (two lane moves per use); read
+    // from LDS at each finalization they cost a few loads per vertex.
+    __shared__ SvoView s_sv;
+    __shared__ GuideArgs s_a;
+    if (threadIdx.x == 0) {
+        s_sv = sv;
+        s_a = a;
+    }
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         float d[3];
         if (a.jitter) {
@@ -408,7 +418,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             if (done < 0) break;
             wave_lds_fence();
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
-            finalize<N, MODE, BLUR>(sv, a, ldir, recs + done * RW * NN, vd, ps, lane, vl);
+            finalize<N, MODE, BLUR>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * RW * NN,
+                                    vd, ps, lane, vl);
             wave_lds_fence();
 #pragma unroll
             for (int k = 0; k < S; ++k)

@@ -31,7 +31,7 @@ TileConfig default_tile(int N, int depth)
 {
     TileConfig t;
     t.waves_per_block = 4;   // the tuner's usual pick for the frame-scale room at N = 16
-    t.blocks_per_cu = N == 32 ? 4 : 8;
+    t.blocks_per_cu = N == 32 ? 4 : 6;
     return legalize_tile(t, N, depth);
 }
 
