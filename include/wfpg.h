@@ -355,7 +355,7 @@ typedef struct {
 wfpg_status wfpg_get_tile(const wfpg_svo *svo, int32_t N, wfpg_tile *out);
 
 /* Force a tile for resolution N (EINVAL if it exceeds the kernel's limits:
- * 1..16 waves, 1..64 blocks per CU, the device's LDS per workgroup: 160 KiB
+ * 1..16 waves, 1..64 blocks per CU, the device's LDS per workgroup less 1 KiB: 159 KiB
  * on MI355X). */
 wfpg_status wfpg_set_tile(const wfpg_svo *svo, int32_t N, const wfpg_tile *tile);
 

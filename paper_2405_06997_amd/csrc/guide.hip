@@ -362,6 +362,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     // from LDS at each finalization they cost a few loads per vertex.
     __shared__ SvoView s_sv;
     __shared__ GuideArgs s_a;
+    static_assert(sizeof(SvoView) + sizeof(GuideArgs) + 64 <= kGuideStaticLds, "static LDS over its reserve");
     if (threadIdx.x == 0) {
         s_sv = sv;
         s_a = a;

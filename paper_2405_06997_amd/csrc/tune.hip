@@ -49,8 +49,11 @@ size_t guide_max_lds()
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
         v = 64 * 1024;
-    cache[dev] = (size_t)v;
-    return (size_t)v;
+    // dynamic LDS only: the guide kernel's static LDS (its argument copies)
+    // must fit beside it
+    const size_t dyn = (size_t)v - kGuideStaticLds;
+    cache[dev] = dyn;
+    return dyn;
 }
 
 TileConfig legalize_tile(TileConfig t, int N, int depth)

@@ -125,7 +125,10 @@ inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPL
     return (size_t)N * N * 3 * 4 * 2 +
            (size_t)tc.waves_per_block * S * ((size_t)guide_rec_words(mode) * N * N * 4 + 4);
 }
-// LDS a guide workgroup may use on the current device (all modes but debug).
+// Dynamic LDS a guide workgroup may use on the current device (all modes but
+// debug): the device's per-workgroup LDS less kGuideStaticLds, a bound on the
+// kernel's static LDS (checked at compile time in the kernel's source).
+constexpr size_t kGuideStaticLds = 1024;
 size_t guide_max_lds();
 constexpr int kCounterPool = 64;   // concurrent guide launches per SVO with distinct counters
 
