@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per 2 cycles per SIMD
+# (32 lanes per clock, the rate behind the 157.3 TFLOP/s FP32 vector peak), 2.4 GHz
+VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 2
 
 # HBM bytes per launch of k_guide<16, SAMPLE> on this workload, from two
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) each scaled by what the same
@@ -35,12 +38,14 @@ MEASURED_TRAFFIC = {
     "N": 16,
     "tile": {"waves_per_block": 4, "blocks_per_cu": 6},
     "bytes_per_launch": 4018276417,
+    "valu_wave_instrs_per_launch": 26992914636,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 
 
-def measured_traffic(N, tile):
-    """The counter-derived traffic if it still describes the kernel that runs."""
+def measured_counters(N, tile):
+    """The counter-derived figures (HBM bytes, VALU instructions per launch) if
+    they still describe the kernel that runs, else None."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -49,7 +54,7 @@ def measured_traffic(N, tile):
     m = MEASURED_TRAFFIC
     if h.hexdigest() != m["sources_sha256"] or N != m["N"] or tile != m["tile"]:
         return None
-    return m["bytes_per_launch"]
+    return m
 
 
 def parse():
@@ -156,7 +161,8 @@ def main():
 
     gs_avg = float(np.mean(gs_ms))
     achieved = alg_bytes / (gs_avg * 1e-3) / 1e9
-    traffic = measured_traffic(args.N, tile)
+    counters = measured_counters(args.N, tile)
+    traffic = None if counters is None else counters["bytes_per_launch"]
     out = {
         "metric": "guided samples/sec (PDF build+sample) on 1 MI355X; MLP vs SVO march at KL<=0.05",
         "value": n / (step_ms * 1e-3),
@@ -186,12 +192,18 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "traffic_gbs": None if traffic is None else traffic / (gs_avg * 1e-3) / 1e9,
             "node_tests_per_bin": visits / (n * NN), "hit_fraction": hits / (n * NN),
+            # the march is integer-ALU bound: VALU issue beside the logical HBM fraction
+            "valu": None if counters is None else {
+                "achieved": counters["valu_wave_instrs_per_launch"] / (gs_avg * 1e-3),
+                "peak": VALU_PEAK_WAVE_INSTR_S, "unit": "wave64 VALU instructions/s",
+                "frac": counters["valu_wave_instrs_per_launch"] / (gs_avg * 1e-3) / VALU_PEAK_WAVE_INSTR_S},
         },
     }
     orc = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
-        out["cpu_baseline"], orc = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n)
+        out["cpu_baseline"], orc, ref = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n, seed=K)
+        out["parity"] = parity(d_out, p_out, ref, args.N)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
     unknown = sections - {"binned", "product", "extract", "learned", "batching", "precision"}
     if unknown:
@@ -524,10 +536,12 @@ def chi_square(w, g, orc, cam, N, dev, V=64, per=16384):
     return {"samples": V * per, "vertices": V, "stat": stat, "dof": dof, "p_value": float(chi2.sf(stat, dof))}
 
 
-def cpu_baseline(room, splats, cam, N, S, n):
+def cpu_baseline(room, splats, cam, N, S, n, seed):
     """The oracle, as it stands, on the host cores: accumulate + propagate of
     all 2M splats timed in full, guide_sample on an evenly strided sample of S
-    queue vertices, extrapolated to the whole queue."""
+    queue vertices (with their queue indices as RNG counters and the seed of
+    the last timed step, so its samples are that step's), extrapolated to the
+    whole queue; then the same on one thread for a smaller sample."""
     import numpy as np
 
     import oracle
@@ -537,18 +551,55 @@ def cpu_baseline(room, splats, cam, N, S, n):
     o.propagate()
     t_acc = time.perf_counter() - t
     stride = max(1, n // S)
-    sub = np.ascontiguousarray(cam[:, ::stride][:, :S])
+    idx = np.arange(0, n, stride)[:S]
+    sub = np.ascontiguousarray(cam[:, idx])
     S = sub.shape[1]
     t = time.perf_counter()
-    o.guide_sample(sub, N, seed=1, bounce=0)
+    ref = o.guide_sample(sub, N, seed=seed, bounce=0, counter=idx)
     t_gs = time.perf_counter() - t
+    ref["index"] = idx
     step = t_acc + t_gs / S * n
-    base = {"value": n / step, "unit": "samples/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    cores = oracle.num_threads()
+    S1 = max(1, S // 32)
+    oracle.set_num_threads(1)
+    t = time.perf_counter()
+    o.guide_sample(np.ascontiguousarray(sub[:, :S1]), N, seed=seed, bounce=0, counter=idx[:S1])
+    t1 = time.perf_counter() - t
+    oracle.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    base = {"value": n / step, "unit": "samples/s", "cores": cores, "kind": "oracle", "cpu_model": model,
             "sample": f"accumulate+propagate of all 2M splats ({t_acc:.2f} s) + guide_sample on "
                       f"every {stride}th camera-queue vertex ({S} of {n}, {t_gs:.2f} s), extrapolated "
-                      f"to one full step"}
-    return base, o
+                      f"to one full step",
+            "single_thread_guide_samples_per_s": S1 / t1}
+    return base, o, ref
+
+
+def parity(d_out, p_out, ref, N):
+    """The last timed step's samples against the oracle's on the CPU-baseline
+    sample: sampled bins equal outside the FP32 scan band, pdf and direction
+    errors on the equal ones (bars: 1e-5 relative, 4e-6 chord)."""
+    import numpy as np
+
+    import oracle
+    idx = ref["index"]
+    d = d_out[:, idx].cpu().numpy().astype(np.float64)
+    p = p_out[idx].cpu().numpy().astype(np.float64)
+    uv = oracle.oct_encode_many(d)
+    gb = np.minimum((uv * N).astype(np.int64), N - 1)
+    same = (gb[0] == ref["bin"][:, 0]) & (gb[1] == ref["bin"][:, 1])
+    band = (ref["margin"] < 1e-5).any(1)
+    rel = np.abs(p[same] - ref["pdf"][same]) / ref["pdf"][same]
+    chord = np.linalg.norm(d[:, same] - ref["dir"][:, same], axis=0)
+    return {"vertices": int(len(idx)), "same_bin": float(same.mean()),
+            "differing_outside_scan_band": int((~same & ~band).sum()),
+            "pdf_max_rel_err": float(rel.max()), "dir_max_chord": float(chord.max()),
+            "ok": bool((~same & ~band).sum() == 0 and rel.max() <= 1e-5 and chord.max() < 4e-6)}
 
 
 if __name__ == "__main__":

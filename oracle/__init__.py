@@ -91,6 +91,7 @@ def lib():
             "orc_oct_encode_many": (None, [vp, i64, vp]),
             "orc_oct_decode_many": (None, [vp, i64, vp]),
             "orc_num_threads": (i32, []),
+            "orc_set_num_threads": (None, [i32]),
             "orc_nn_mlp_params": (i64, []),
             "orc_nn_num_params": (i64, [vp]),
             "orc_nn_resolutions": (None, [vp, vp]),
@@ -119,6 +120,10 @@ def _soa(a, dtype=np.float32):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int):
+    lib().orc_set_num_threads(t)
 
 
 def morton(x: int, y: int, z: int) -> int:

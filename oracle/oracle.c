@@ -1027,6 +1027,12 @@ void orc_oct_decode_many(const double *xy, int64_t n, double *d)
 }
 
 /* Number of OpenMP threads the parallel loops above use. */
+/* Threads of the parallel loops from now on (the CPU baseline's single-thread leg). */
+void orc_set_num_threads(int32_t n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
 int32_t orc_num_threads(void)
 {
     int t = 1;
