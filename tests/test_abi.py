@@ -38,6 +38,9 @@ def test_status_strings_and_defaults():
     o = lib.wfpg_default_opts()
     assert (o.N, o.mode, o.probe_stride) == (16, 0, 256)
     assert abs(o.eps - 0.01) < 1e-9 and abs(o.kl_bound - 0.05) < 1e-9
+    assert (o.jitter, o.jitter_key, o.blur) == (0, 0, 0)
+    b = lib.wfpg_default_bin_opts()
+    assert (b.N, b.c_ray, b.l_min, b.jitter, b.blur) == (16, 512, 5, 0, 0)
 
 
 @pytest.mark.parametrize("N", [8, 16, 32])
@@ -58,5 +61,13 @@ def test_invalid_arguments_rejected_without_device():
     h = C.c_void_p()
     assert lib.svo_build(None, 0, 11, 0, None, C.byref(h)) == -1
     assert lib.svo_build(None, 0, 6, 7, None, C.byref(h)) == -1
+    o16 = w.make_opts(N=16)
+    assert lib.guide_sample_product(None, None, None, None, 0, 0, 0, C.byref(o16), None, None, None) == -1
+    assert lib.pdf_eval_product(None, None, None, None, None, 0, C.byref(o16), None, None) == -1
+    bo = w.bin_opts()
+    assert lib.guide_sample_binned_product(None, None, None, None, 0, 0, 0, C.byref(bo), None, None, None,
+                                           None) == -1
+    assert lib.svo_accumulate_paths(None, None, None, None, None, None, 0, 4, None) == -1
+    assert lib.wfpg_dir_table_jitter(12, 0, None) == -1
     assert lib.wfpg_dir_table(12, None) == -1
     assert lib.svo_level_size(None, 0) == -1
