@@ -495,10 +495,12 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             continue;
         }
         int res = core::STEP_CONTINUE;
-        Hit h = {-1, 0u, 0u};
         if (lbin >= 0) {
+            // unrolled: the steps run as one straight sequence, a lane that finished
+            // masked out of the rest
+#pragma unroll
             for (int m = 0; m < kMicro; ++m) {
-                res = core::micro_step<true>(st, D, bits, 5, vis, h);
+                res = core::micro_step(st, D, bits, 5, vis);
                 if (res != core::STEP_CONTINUE) break;
             }
             if (res == core::STEP_CONTINUE && (iters += kMicro) >= core::kMaxTests) {
@@ -509,6 +511,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
             uint32_t *rec = recs + lslot * RW * NN;
+            const Hit h = res == core::STEP_HIT ? core::hit_of(st) : Hit{-1, 0u, 0u};
             if constexpr (MODE == MODE_DEBUG) {
                 rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
                 rec[2 * lbin + 1] = h.delta;

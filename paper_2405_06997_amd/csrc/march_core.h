@@ -37,7 +37,13 @@ constexpr int kFine = 30;
 // take one 64-bit word each, level l >= 3 takes 8^l / 64 words).
 WFPG_HD uint32_t woff(int l)
 {
-    return l <= 3 ? (uint32_t)l : 3u + ((0x09249249u & ((1u << (3 * l - 9)) - 1u)) << 3);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t t = __umul24((uint32_t)l, 3u) - 9u;   // a full-rate 24-bit product
+#else
+    const uint32_t t = 3u * (uint32_t)l - 9u;
+#endif
+    const uint32_t f = 3u + ((0x09249249u & ((1u << (t & 31u)) - 1u)) << 3);
+    return l <= 3 ? (uint32_t)l : f;
 }
 
 WFPG_HD uint32_t part1by2(uint32_t v)
@@ -75,27 +81,6 @@ struct Hit {
 };
 
 enum { STEP_CONTINUE = 0, STEP_HIT = 1, STEP_MISS = 2 };
-
-// Which half of a cell the ray is in along one axis just after the current
-// crossing (tn/td, ta): the mid-plane M counts as crossed iff its crossing
-// parameter is smaller, or equal with an axis not above ta.
-WFPG_HD uint32_t upper_half(uint32_t M, uint32_t O, uint32_t aq, int sg, int j, uint32_t tn,
-                            uint32_t td, int ta)
-{
-    if (sg == 0) return O >= M ? 1u : 0u;
-    int32_t dl = (int32_t)(M - O);
-    if (sg < 0) dl = -dl;
-    const int64_t lhs = (int64_t)dl * (int64_t)td - (int64_t)((uint64_t)tn * aq);
-    const bool crossed = lhs < (int64_t)(j <= ta) || (sg > 0 && dl == 0);
-    return (crossed != (sg < 0)) ? 1u : 0u;
-}
-
-// Distance (2^-30 units) from O to the far face of [lo, lo + size) along
-// the ray's direction on one axis (1 when the axis is not crossed).
-WFPG_HD uint32_t far_face(uint32_t lo, uint32_t size, uint32_t O, int sg)
-{
-    return sg > 0 ? lo + size - O : (sg < 0 ? O - lo : 1u);
-}
 
 WFPG_HD void split_dir(int q, uint32_t &aq, int &sg)
 {
@@ -150,96 +135,115 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
     }
 }
 
-// OPAQUE_SIGNS: hide the ray's signs from the optimizer at every step, so the
-// sign tests stay in the loop as vector compares. For a caller whose scalar
-// registers are already full (the guide kernel's queue and slot bookkeeping),
-// the loop-invariant lane masks the compiler would otherwise hoist are spilled
-// into vector lanes and cost two lane moves per use; elsewhere the hoisted
-// masks are the cheaper form.
-template <bool OPAQUE_SIGNS = false, class Bits>
-WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis, Hit &h)
+// One occupancy test per call, with no branch that depends on the lane: every
+// lane computes the exit step of PH_ADVANCE and both candidate cells (the
+// ancestor of PH_PATH, the child of PH_DESCEND) and keeps what its phase
+// selects, so a wave whose lanes sit in different phases runs one straight
+// sequence with every lane active instead of each phase's code under its own
+// lane mask. On STEP_HIT the hit is hit_of(s).
+template <class Bits>
+WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
-    if constexpr (OPAQUE_SIGNS) asm volatile("" : "+v"(s.sg0), "+v"(s.sg1), "+v"(s.sg2));
-#endif
-    if (s.phase == PH_ADVANCE) {
-        const uint32_t size = 1u << (kFine - s.lvl);
-        const uint32_t dl0 = far_face(s.lo0, size, s.O0, s.sg0);
-        const uint32_t dl1 = far_face(s.lo1, size, s.O1, s.sg1);
-        const uint32_t dl2 = far_face(s.lo2, size, s.O2, s.sg2);
-        const uint32_t c1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? 0xffffffffu : 0u;
-        const uint32_t D01 = (dl1 & c1) | (dl0 & ~c1), Q01 = (s.aq1 & c1) | (s.aq0 & ~c1);
-        const uint32_t c2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? 0xffffffffu : 0u;
-        const uint32_t m0 = ~c1 & ~c2, m1 = c1 & ~c2, m2 = c2;
-        const int e = (int)((m1 & 1u) | (m2 & 2u));
-        const uint32_t De = (dl2 & m2) | (D01 & ~m2);
-        const uint32_t Qe = (s.aq2 & m2) | (Q01 & ~m2);
-        const int sgn = (int)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) | ((uint32_t)s.sg2 & m2));
-        const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
-        const int64_t nl = (int64_t)le + (int64_t)sgn * (int64_t)size;
-        if (nl < 0 || nl >= (1ll << kFine)) return STEP_MISS;
-        const uint32_t nlu = (uint32_t)nl;
-        const uint32_t oldc = le >> (kFine - s.lvl), newc = nlu >> (kFine - s.lvl);
-        const uint32_t m = 0x09249249u << e;
-        s.key = sgn > 0 ? ((((s.key | ~m) + 1u) & m) | (s.key & ~m)) : ((((s.key & m) - 1u) & m) | (s.key & ~m));
-        s.lo0 = (nlu & m0) | (s.lo0 & ~m0);
-        s.lo1 = (nlu & m1) | (s.lo1 & ~m1);
-        s.lo2 = (nlu & m2) | (s.lo2 & ~m2);
-        s.tn = De;
-        s.td = Qe;
-        s.ta = e;
-        s.l = s.lvl - (31 - __builtin_clz(oldc ^ newc));   // first level not shared with the cell left
-        s.phase = PH_PATH;
-    }
-    // the cell to test: an ancestor of the entered cell, or the child the ray is in
-    int tl;
-    uint32_t tk, n0 = s.lo0, n1 = s.lo1, n2 = s.lo2;
-    if (s.phase == PH_PATH) {
-        tl = s.l;
-        tk = s.key >> (3 * (s.lvl - s.l));
-    } else {
-        const uint32_t half = 1u << (29 - s.lvl);
-        const uint32_t oct = upper_half(s.lo0 + half, s.O0, s.aq0, s.sg0, 0, s.tn, s.td, s.ta) |
-                             (upper_half(s.lo1 + half, s.O1, s.aq1, s.sg1, 1, s.tn, s.td, s.ta) << 1) |
-                             (upper_half(s.lo2 + half, s.O2, s.aq2, s.sg2, 2, s.tn, s.td, s.ta) << 2);
-        tk = (s.key << 3) | oct;
-        n0 += (oct & 1u) ? half : 0u;
-        n1 += (oct & 2u) ? half : 0u;
-        n2 += (oct & 4u) ? half : 0u;
-        tl = s.lvl + 1;
-    }
+    const bool n0 = s.sg0 < 0, n1 = s.sg1 < 0, n2 = s.sg2 < 0;
+
+    // PH_ADVANCE: the first exit crossing of the current cell. Distance to the
+    // far face per axis; an axis the ray does not cross gets lo + size - O >= 1,
+    // which only ever meets a zero |q| in the comparisons below.
+    const bool adv = s.phase == PH_ADVANCE;
+    const uint32_t size = 1u << (kFine - s.lvl);
+    const uint32_t dl0 = n0 ? s.O0 - s.lo0 : s.lo0 + size - s.O0;
+    const uint32_t dl1 = n1 ? s.O1 - s.lo1 : s.lo1 + size - s.O1;
+    const uint32_t dl2 = n2 ? s.O2 - s.lo2 : s.lo2 + size - s.O2;
+    // axis choice as lane masks (selects between the three axes' registers
+    // compiled to a stack array indexed by the axis)
+    const uint32_t C1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? ~0u : 0u;   // axis 1 before axis 0
+    const uint32_t D01 = (dl1 & C1) | (dl0 & ~C1), Q01 = (s.aq1 & C1) | (s.aq0 & ~C1);
+    const uint32_t C2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? ~0u : 0u;      // axis 2 before both
+    const uint32_t m0 = ~C1 & ~C2, m1 = C1 & ~C2, m2 = C2;
+    const int e = (int)((m1 & 1u) | (m2 & 2u));
+    // NE: all ones when the crossed axis moves down (the sign bit of its q, spread)
+    const uint32_t NE = (uint32_t)((int32_t)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) |
+                                             ((uint32_t)s.sg2 & m2)) >> 31);
+    const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
+    // the crossed axis has |q| > 0, so it moves by one cell; leaving the cube
+    // wraps below 0 or reaches 2^30, both >= 2^30 as unsigned
+    const uint32_t nlu = le + ((size ^ NE) - NE);   // le -/+ size
+    const bool miss = adv & (nlu >= (1u << kFine));
+    const uint32_t m = 0x09249249u << e;   // the key bits of axis e
+    const uint32_t kstep = (((s.key & m) - 1u) & NE) | (((s.key | ~m) + 1u) & ~NE);
+    const uint32_t akey = (kstep & m) | (s.key & ~m);
+    // first level not shared with the cell left (le and nlu differ at level lvl, so ch >= 1)
+    const uint32_t ch = (le ^ nlu) >> (kFine - s.lvl);
+    const int al = s.lvl - (31 - __builtin_clz(ch));
+    const uint32_t A = adv ? ~0u : 0u;
+    s.lo0 = (nlu & m0 & A) | (s.lo0 & ~(m0 & A));
+    s.lo1 = (nlu & m1 & A) | (s.lo1 & ~(m1 & A));
+    s.lo2 = (nlu & m2 & A) | (s.lo2 & ~(m2 & A));
+    s.key = adv ? akey : s.key;
+    s.tn = adv ? ((dl2 & m2) | (D01 & ~m2)) : s.tn;
+    s.td = adv ? ((s.aq2 & m2) | (Q01 & ~m2)) : s.td;
+    s.ta = adv ? e : s.ta;
+    const int l = adv ? al : s.l;
+    const bool path = adv || s.phase == PH_PATH;
+
+    // PH_PATH candidate: the entered cell's ancestor at level l (l <= lvl)
+    const uint32_t pk = s.key >> ((3 * (s.lvl - l)) & 31);
+    // PH_DESCEND candidate: the child the ray is in just after the current
+    // crossing tn/td. Along axis j the mid-plane M counts as crossed iff its
+    // parameter is smaller, or equal with j not above ta; a plane behind the
+    // origin (dl < 0) is always crossed, and with no motion along j the point
+    // O decides (O >= M: upper half). dl is the signed distance along the
+    // ray's direction on j.
+    const uint32_t half = 1u << (29 - s.lvl);
+    const uint32_t M0 = s.lo0 + half, M1 = s.lo1 + half, M2 = s.lo2 + half;
+    const int32_t t0 = (int32_t)(M0 - s.O0), t1 = (int32_t)(M1 - s.O1), t2 = (int32_t)(M2 - s.O2);
+    const int32_t d0 = n0 ? -t0 : t0, d1 = n1 ? -t1 : t1, d2 = n2 ? -t2 : t2;
+    // (non-short-circuit ors: both products are always formed, no branch)
+    const bool x0 = (d0 < 0) | ((uint64_t)(uint32_t)d0 * s.td < (uint64_t)s.tn * s.aq0 + (uint32_t)(s.ta >= 0)) |
+                    (!n0 & (d0 == 0));
+    const bool x1 = (d1 < 0) | ((uint64_t)(uint32_t)d1 * s.td < (uint64_t)s.tn * s.aq1 + (uint32_t)(s.ta >= 1)) |
+                    (!n1 & (d1 == 0));
+    const bool x2 = (d2 < 0) | ((uint64_t)(uint32_t)d2 * s.td < (uint64_t)s.tn * s.aq2 + (uint32_t)(s.ta >= 2)) |
+                    (!n2 & (d2 == 0));
+    const bool u0 = x0 != n0, u1 = x1 != n1, u2 = x2 != n2;   // upper half of the cell on each axis
+    const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
+
+    // the cell to test (a lane that left the cube tests the root instead: its
+    // stepped key and level are out of range)
+    const int tl = miss ? 0 : (path ? l : s.lvl + 1);
+    const uint32_t tk = miss ? 0u : (path ? pk : dk);
+    const uint32_t g0 = s.lo0 + (!path && u0 ? half : 0u);
+    const uint32_t g1 = s.lo1 + (!path && u1 ? half : 0u);
+    const uint32_t g2 = s.lo2 + (!path && u2 ? half : 0u);
     const uint64_t w = bits(tl, woff(tl) + (tk >> 6));
-    vis += (tl >= count_from);
-    if (!((w >> (tk & 63)) & 1ull)) {   // empty: the cell to leave next
-        const uint32_t mk = ~((1u << (kFine - tl)) - 1u);
-        s.lvl = tl;
-        s.key = tk;
-        s.lo0 = n0 & mk;
-        s.lo1 = n1 & mk;
-        s.lo2 = n2 & mk;
-        s.phase = PH_ADVANCE;
-        return STEP_CONTINUE;
-    }
-    if (s.phase == PH_PATH) {
-        if (tl < s.lvl) {
-            s.l = tl + 1;
-            return STEP_CONTINUE;
-        }
-        s.phase = PH_DESCEND;   // the entered cell is occupied
-    } else {
-        s.lvl = tl;
-        s.key = tk;
-        s.lo0 = n0;
-        s.lo1 = n1;
-        s.lo2 = n2;
-    }
-    if (s.lvl == D) {
-        h.axis = s.ta;
-        h.key = s.key;
-        h.delta = s.tn;
-        return STEP_HIT;
-    }
-    return STEP_CONTINUE;
+    vis += (!miss && tl >= count_from) ? 1 : 0;
+    const bool occ = (w >> (tk & 63)) & 1ull;
+
+    // Empty: the tested cell is the one to leave next. Occupied: on the path,
+    // the next level down (the entered cell itself: descend from it); in a
+    // descent, the child becomes the cell. A hit is an occupied leaf.
+    const bool take = !occ || !path;
+    const uint32_t mk = ~((1u << (kFine - tl)) - 1u);
+    const int olvl = s.lvl;
+    s.lo0 = take ? (g0 & mk) : s.lo0;
+    s.lo1 = take ? (g1 & mk) : s.lo1;
+    s.lo2 = take ? (g2 & mk) : s.lo2;
+    s.lvl = take ? tl : olvl;
+    s.key = take ? tk : s.key;
+    s.phase = !occ ? PH_ADVANCE : (path && tl < olvl ? PH_PATH : PH_DESCEND);
+    s.l = tl + 1;
+    if (miss) return STEP_MISS;
+    return occ && tl == D ? STEP_HIT : STEP_CONTINUE;
+}
+
+// The hit of a march whose last step returned STEP_HIT.
+WFPG_HD Hit hit_of(const MicroState &s)
+{
+    Hit h;
+    h.axis = s.ta;
+    h.key = s.key;
+    h.delta = s.tn;
+    return h;
 }
 
 // Whole march: 1 on a hit, 0 on a miss, -1 if the iteration bound is
@@ -258,8 +262,11 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
     const bool occ = (bits(D, woff(D) + (ok >> 6)) >> (ok & 63)) & 1ull;
     micro_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, count_from, vis);
     for (int it = 0; it < kMaxTests; ++it) {
-        const int st = micro_step(s, D, bits, count_from, vis, h);
-        if (st == STEP_HIT) return 1;
+        const int st = micro_step(s, D, bits, count_from, vis);
+        if (st == STEP_HIT) {
+            h = hit_of(s);
+            return 1;
+        }
         if (st == STEP_MISS) return 0;
     }
     return -1;
