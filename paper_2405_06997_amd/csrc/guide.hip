@@ -390,8 +390,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     // every occupancy test is a plain global load: the top levels stay hot in
     // the L1/L2 caches (staging them in LDS made the loads flat loads through
     // a pointer select, which measured slower)
-    const uint64_t *gbits = sv.bits;
-    auto bits = [gbits](int, uint32_t wi) -> uint64_t { return gbits[wi]; };
+    const uint32_t *gbits = reinterpret_cast<const uint32_t *>(sv.bits);   // 32-bit words
+    auto bits = [gbits](int, uint32_t wi) -> uint32_t { return gbits[wi]; };
 
     // wave-uniform stream and slot state
     int64_t chunk_next = 0;
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(a.pos[k * ps + vi]);
                 const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D),
                                                     O[2] >> (WFPG_FINE - D));
-                const bool oc = (bits(D, woff(D) + (okey >> 6)) >> (okey & 63)) & 1ull;
+                const bool oc = core::occupied(bits, D, okey);
                 F0 = uni(O[0]); F1 = uni(O[1]); F2 = uni(O[2]); Fkey = uni(okey);
                 Focc = uni((int)oc) != 0;
 #pragma unroll

@@ -46,6 +46,15 @@ WFPG_HD uint32_t woff(int l)
     return l <= 3 ? (uint32_t)l : f;
 }
 
+// Occupancy bit of cell `key` at level l, read as 32-bit words: bit key & 31
+// of word 2 woff(l) + key / 32 (the bitmaps are little-endian 64-bit words).
+// bits(l, i) returns 32-bit word i.
+template <class Bits>
+WFPG_HD bool occupied(const Bits &bits, int l, uint32_t key)
+{
+    return (bits(l, 2u * woff(l) + (key >> 5)) >> (key & 31u)) & 1u;
+}
+
 WFPG_HD uint32_t part1by2(uint32_t v)
 {
     v &= 0x3ffu;
@@ -169,16 +178,17 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     // wraps below 0 or reaches 2^30, both >= 2^30 as unsigned
     const uint32_t nlu = le + ((size ^ NE) - NE);   // le -/+ size
     const bool miss = adv & (nlu >= (1u << kFine));
-    const uint32_t m = 0x09249249u << e;   // the key bits of axis e
-    const uint32_t kstep = (((s.key & m) - 1u) & NE) | (((s.key | ~m) + 1u) & ~NE);
-    const uint32_t akey = (kstep & m) | (s.key & ~m);
+    // the key's axis-e coordinate (its bits under m) plus or minus one: a
+    // decrement is an increment of the complemented bits
+    const uint32_t m = 0x09249249u << e;
+    const uint32_t kinc = (((s.key ^ NE) | ~m) + 1u) & m;
+    const uint32_t akey = ((kinc ^ NE) & m) | (s.key & ~m);
     // first level not shared with the cell left (le and nlu differ at level lvl, so ch >= 1)
     const uint32_t ch = (le ^ nlu) >> (kFine - s.lvl);
     const int al = s.lvl - (31 - __builtin_clz(ch));
-    const uint32_t A = adv ? ~0u : 0u;
-    s.lo0 = (nlu & m0 & A) | (s.lo0 & ~(m0 & A));
-    s.lo1 = (nlu & m1 & A) | (s.lo1 & ~(m1 & A));
-    s.lo2 = (nlu & m2 & A) | (s.lo2 & ~(m2 & A));
+    s.lo0 = adv & (m0 != 0u) ? nlu : s.lo0;
+    s.lo1 = adv & (m1 != 0u) ? nlu : s.lo1;
+    s.lo2 = adv & (m2 != 0u) ? nlu : s.lo2;
     s.key = adv ? akey : s.key;
     s.tn = adv ? ((dl2 & m2) | (D01 & ~m2)) : s.tn;
     s.td = adv ? ((s.aq2 & m2) | (Q01 & ~m2)) : s.td;
@@ -198,12 +208,14 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const uint32_t M0 = s.lo0 + half, M1 = s.lo1 + half, M2 = s.lo2 + half;
     const int32_t t0 = (int32_t)(M0 - s.O0), t1 = (int32_t)(M1 - s.O1), t2 = (int32_t)(M2 - s.O2);
     const int32_t d0 = n0 ? -t0 : t0, d1 = n1 ? -t1 : t1, d2 = n2 ? -t2 : t2;
-    // (non-short-circuit ors: both products are always formed, no branch)
-    const bool x0 = (d0 < 0) | ((uint64_t)(uint32_t)d0 * s.td < (uint64_t)s.tn * s.aq0 + (uint32_t)(s.ta >= 0)) |
+    // (signed products: a plane behind the origin gives a negative left side;
+    // non-short-circuit ors, so nothing branches)
+    const int64_t td = (int64_t)(int32_t)s.td;   // < 2^24: a signed 32 x 32 product
+    const bool x0 = ((int64_t)d0 * td < (int64_t)((uint64_t)s.tn * s.aq0 + (uint32_t)(s.ta >= 0))) |
                     (!n0 & (d0 == 0));
-    const bool x1 = (d1 < 0) | ((uint64_t)(uint32_t)d1 * s.td < (uint64_t)s.tn * s.aq1 + (uint32_t)(s.ta >= 1)) |
+    const bool x1 = ((int64_t)d1 * td < (int64_t)((uint64_t)s.tn * s.aq1 + (uint32_t)(s.ta >= 1))) |
                     (!n1 & (d1 == 0));
-    const bool x2 = (d2 < 0) | ((uint64_t)(uint32_t)d2 * s.td < (uint64_t)s.tn * s.aq2 + (uint32_t)(s.ta >= 2)) |
+    const bool x2 = ((int64_t)d2 * td < (int64_t)((uint64_t)s.tn * s.aq2 + (uint32_t)(s.ta >= 2))) |
                     (!n2 & (d2 == 0));
     const bool u0 = x0 != n0, u1 = x1 != n1, u2 = x2 != n2;   // upper half of the cell on each axis
     const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
@@ -212,22 +224,21 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     // stepped key and level are out of range)
     const int tl = miss ? 0 : (path ? l : s.lvl + 1);
     const uint32_t tk = miss ? 0u : (path ? pk : dk);
-    const uint32_t g0 = s.lo0 + (!path && u0 ? half : 0u);
-    const uint32_t g1 = s.lo1 + (!path && u1 ? half : 0u);
-    const uint32_t g2 = s.lo2 + (!path && u2 ? half : 0u);
-    const uint64_t w = bits(tl, woff(tl) + (tk >> 6));
     vis += (!miss && tl >= count_from) ? 1 : 0;
-    const bool occ = (w >> (tk & 63)) & 1ull;
+    const bool occ = occupied(bits, tl, tk);
 
     // Empty: the tested cell is the one to leave next. Occupied: on the path,
     // the next level down (the entered cell itself: descend from it); in a
-    // descent, the child becomes the cell. A hit is an occupied leaf.
+    // descent, the child becomes the cell. A hit is an occupied leaf. The
+    // corner of the new cell: the old corner cut to level tl (an ancestor), or
+    // with the child's half added on each axis (a child); unchanged when the
+    // cell stays.
     const bool take = !occ || !path;
-    const uint32_t mk = ~((1u << (kFine - tl)) - 1u);
+    const uint32_t MK = take ? ~((1u << (kFine - tl)) - 1u) : ~0u;
     const int olvl = s.lvl;
-    s.lo0 = take ? (g0 & mk) : s.lo0;
-    s.lo1 = take ? (g1 & mk) : s.lo1;
-    s.lo2 = take ? (g2 & mk) : s.lo2;
+    s.lo0 = (s.lo0 & MK) | (!path & u0 ? half : 0u);
+    s.lo1 = (s.lo1 & MK) | (!path & u1 ? half : 0u);
+    s.lo2 = (s.lo2 & MK) | (!path & u2 ? half : 0u);
     s.lvl = take ? tl : olvl;
     s.key = take ? tk : s.key;
     s.phase = !occ ? PH_ADVANCE : (path && tl < olvl ? PH_PATH : PH_DESCEND);
@@ -259,7 +270,7 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
     split_dir(q1, aq1, sg1);
     split_dir(q2, aq2, sg2);
     const uint32_t ok = morton3(O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D));
-    const bool occ = (bits(D, woff(D) + (ok >> 6)) >> (ok & 63)) & 1ull;
+    const bool occ = occupied(bits, D, ok);
     micro_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, count_from, vis);
     for (int it = 0; it < kMaxTests; ++it) {
         const int st = micro_step(s, D, bits, count_from, vis);

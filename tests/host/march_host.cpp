@@ -13,7 +13,8 @@ extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, con
                                  int32_t *visits)
 {
     const int NN = N * N;
-    auto load = [&](int, uint32_t wi) -> uint64_t { return bits[wi]; };
+    const uint32_t *bits32 = reinterpret_cast<const uint32_t *>(bits);   // 32-bit words
+    auto load = [&](int, uint32_t wi) -> uint32_t { return bits32[wi]; };
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t i = 0; i < n; ++i) {
         uint32_t O[3];
