@@ -207,16 +207,18 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const uint32_t half = 1u << (29 - s.lvl);
     const uint32_t M0 = s.lo0 + half, M1 = s.lo1 + half, M2 = s.lo2 + half;
     const int32_t t0 = (int32_t)(M0 - s.O0), t1 = (int32_t)(M1 - s.O1), t2 = (int32_t)(M2 - s.O2);
-    const int32_t d0 = n0 ? -t0 : t0, d1 = n1 ? -t1 : t1, d2 = n2 ? -t2 : t2;
-    // (signed products: a plane behind the origin gives a negative left side;
-    // non-short-circuit ors, so nothing branches)
-    const int64_t td = (int64_t)(int32_t)s.td;   // < 2^24: a signed 32 x 32 product
-    const bool x0 = ((int64_t)d0 * td < (int64_t)((uint64_t)s.tn * s.aq0 + (uint32_t)(s.ta >= 0))) |
-                    (!n0 & (d0 == 0));
-    const bool x1 = ((int64_t)d1 * td < (int64_t)((uint64_t)s.tn * s.aq1 + (uint32_t)(s.ta >= 1))) |
-                    (!n1 & (d1 == 0));
-    const bool x2 = ((int64_t)d2 * td < (int64_t)((uint64_t)s.tn * s.aq2 + (uint32_t)(s.ta >= 2))) |
-                    (!n2 & (d2 == 0));
+    // With d = ±t the signed distance along the direction, the plane is
+    // crossed iff d td < tn |q_j| + k (k = 1 when j is not above ta), i.e.
+    // iff P = tn |q_j| - d td > -k: P is one signed 32 x 32 + 64 product-add
+    // (td < 2^24); a plane behind the origin (d < 0) gives P > 0.
+    const int64_t td = (int64_t)(int32_t)s.td;
+    const int64_t P0 = (int64_t)(n0 ? t0 : -t0) * td + (int64_t)((uint64_t)s.tn * s.aq0);
+    const int64_t P1 = (int64_t)(n1 ? t1 : -t1) * td + (int64_t)((uint64_t)s.tn * s.aq1);
+    const int64_t P2 = (int64_t)(n2 ? t2 : -t2) * td + (int64_t)((uint64_t)s.tn * s.aq2);
+    // (non-short-circuit ors, so nothing branches)
+    const bool x0 = (s.ta >= 0 ? P0 >= 0 : P0 > 0) | (!n0 & (t0 == 0));
+    const bool x1 = (s.ta >= 1 ? P1 >= 0 : P1 > 0) | (!n1 & (t1 == 0));
+    const bool x2 = (s.ta >= 2 ? P2 >= 0 : P2 > 0) | (!n2 & (t2 == 0));
     const bool u0 = x0 != n0, u1 = x1 != n1, u2 = x2 != n2;   // upper half of the cell on each axis
     const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
 
