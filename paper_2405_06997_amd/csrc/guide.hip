@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
             uint32_t *rec = recs + lslot * RW * NN;
-            const Hit h = res == core::STEP_HIT ? core::hit_of(st) : Hit{-1, 0u, 0u};
+            const Hit h = res == core::STEP_HIT ? core::hit_of(st, D) : Hit{-1, 0u, 0u};
             if constexpr (MODE == MODE_DEBUG) {
                 rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
                 rec[2 * lbin + 1] = h.delta;

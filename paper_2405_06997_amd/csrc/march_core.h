@@ -111,13 +111,20 @@ WFPG_HD void split_dir(int q, uint32_t &aq, int &sg)
 enum { PH_ADVANCE = 0, PH_PATH = 1, PH_DESCEND = 2 };
 constexpr int kMaxTests = 1 << 17;   // > worst-case occupancy tests of a depth-10 ray
 
+// The march runs in a frame mirrored on every axis the ray descends
+// (x -> 2^30 - x), so that it always moves towards larger coordinates:
+// cell planes map to cell planes and crossing parameters are unchanged, and a
+// mirrored cell's key is the original key with that axis's bits complemented.
+// Only the membership of points lying exactly on a plane differs between the
+// frames; the mid-plane test below keeps the original rule for it.
 struct MicroState {
-    uint32_t O0, O1, O2;      // origin, 2^-30 units
+    uint32_t O0, O1, O2;      // origin in the mirrored frame, 2^-30 units
     uint32_t aq0, aq1, aq2;   // |q|
-    int sg0, sg1, sg2;        // sign(q)
+    uint32_t mir;             // bit j: axis j is mirrored (q_j < 0)
+    uint32_t flip;            // key bits of the mirrored axes, all levels
     int lvl, ta, l, phase;
-    uint32_t key, tn, td;
-    uint32_t lo0, lo1, lo2;
+    uint32_t key, tn, td;     // key in the mirrored frame
+    uint32_t lo0, lo1, lo2;   // cell corner in the mirrored frame
 };
 
 // Start at the origin's cell. When the origin's leaf is occupied it is the
@@ -127,14 +134,20 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
                          uint32_t aq0, uint32_t aq1, uint32_t aq2, int sg0, int sg1, int sg2, int D,
                          int count_from, int &vis)
 {
-    s.O0 = O[0]; s.O1 = O[1]; s.O2 = O[2];
+    const uint32_t leaf = 1u << (kFine - D), mk = ~(leaf - 1u);
+    const bool n0 = sg0 < 0, n1 = sg1 < 0, n2 = sg2 < 0;
+    s.O0 = n0 ? (1u << kFine) - O[0] : O[0];
+    s.O1 = n1 ? (1u << kFine) - O[1] : O[1];
+    s.O2 = n2 ? (1u << kFine) - O[2] : O[2];
+    s.lo0 = n0 ? (1u << kFine) - (O[0] & mk) - leaf : O[0] & mk;
+    s.lo1 = n1 ? (1u << kFine) - (O[1] & mk) - leaf : O[1] & mk;
+    s.lo2 = n2 ? (1u << kFine) - (O[2] & mk) - leaf : O[2] & mk;
     s.aq0 = aq0; s.aq1 = aq1; s.aq2 = aq2;
-    s.sg0 = sg0; s.sg1 = sg1; s.sg2 = sg2;
+    s.mir = (n0 ? 1u : 0u) | (n1 ? 2u : 0u) | (n2 ? 4u : 0u);
+    s.flip = (n0 ? 0x09249249u : 0u) | (n1 ? 0x12492492u : 0u) | (n2 ? 0x24924924u : 0u);
     s.ta = -1; s.tn = 0; s.td = 1;
-    const uint32_t mk = ~((1u << (kFine - D)) - 1u);
     s.lvl = D;
-    s.key = origin_key;
-    s.lo0 = O[0] & mk; s.lo1 = O[1] & mk; s.lo2 = O[2] & mk;
+    s.key = origin_key ^ (s.flip >> (kFine - 3 * D));
     s.l = 0;
     if (origin_occupied) {
         s.phase = PH_ADVANCE;
@@ -149,20 +162,19 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
 // ancestor of PH_PATH, the child of PH_DESCEND) and keeps what its phase
 // selects, so a wave whose lanes sit in different phases runs one straight
 // sequence with every lane active instead of each phase's code under its own
-// lane mask. On STEP_HIT the hit is hit_of(s).
+// lane mask. On STEP_HIT the hit is hit_of(s, D).
 template <class Bits>
 WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis)
 {
-    const bool n0 = s.sg0 < 0, n1 = s.sg1 < 0, n2 = s.sg2 < 0;
-
-    // PH_ADVANCE: the first exit crossing of the current cell. Distance to the
-    // far face per axis; an axis the ray does not cross gets lo + size - O >= 1,
-    // which only ever meets a zero |q| in the comparisons below.
+    // PH_ADVANCE: the first exit crossing of the current cell, through its
+    // upper face on every axis. An axis the ray does not cross (|q| = 0) has
+    // lo + size - O >= 1, which only ever meets its zero |q| in the
+    // comparisons below.
     const bool adv = s.phase == PH_ADVANCE;
     const uint32_t size = 1u << (kFine - s.lvl);
-    const uint32_t dl0 = n0 ? s.O0 - s.lo0 : s.lo0 + size - s.O0;
-    const uint32_t dl1 = n1 ? s.O1 - s.lo1 : s.lo1 + size - s.O1;
-    const uint32_t dl2 = n2 ? s.O2 - s.lo2 : s.lo2 + size - s.O2;
+    const uint32_t dl0 = s.lo0 + size - s.O0;
+    const uint32_t dl1 = s.lo1 + size - s.O1;
+    const uint32_t dl2 = s.lo2 + size - s.O2;
     // axis choice as lane masks (selects between the three axes' registers
     // compiled to a stack array indexed by the axis)
     const uint32_t C1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? ~0u : 0u;   // axis 1 before axis 0
@@ -170,19 +182,12 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const uint32_t C2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? ~0u : 0u;      // axis 2 before both
     const uint32_t m0 = ~C1 & ~C2, m1 = C1 & ~C2, m2 = C2;
     const int e = (int)((m1 & 1u) | (m2 & 2u));
-    // NE: all ones when the crossed axis moves down (the sign bit of its q, spread)
-    const uint32_t NE = (uint32_t)((int32_t)(((uint32_t)s.sg0 & m0) | ((uint32_t)s.sg1 & m1) |
-                                             ((uint32_t)s.sg2 & m2)) >> 31);
     const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
-    // the crossed axis has |q| > 0, so it moves by one cell; leaving the cube
-    // wraps below 0 or reaches 2^30, both >= 2^30 as unsigned
-    const uint32_t nlu = le + ((size ^ NE) - NE);   // le -/+ size
+    // one cell up along the crossed axis (|q| > 0); leaving the cube reaches 2^30
+    const uint32_t nlu = le + size;
     const bool miss = adv & (nlu >= (1u << kFine));
-    // the key's axis-e coordinate (its bits under m) plus or minus one: a
-    // decrement is an increment of the complemented bits
-    const uint32_t m = 0x09249249u << e;
-    const uint32_t kinc = (((s.key ^ NE) | ~m) + 1u) & m;
-    const uint32_t akey = ((kinc ^ NE) & m) | (s.key & ~m);
+    const uint32_t m = 0x09249249u << e;   // the key bits of axis e: add one to them
+    const uint32_t akey = ((((s.key | ~m) + 1u) & m)) | (s.key & ~m);
     // first level not shared with the cell left (le and nlu differ at level lvl, so ch >= 1)
     const uint32_t ch = (le ^ nlu) >> (kFine - s.lvl);
     const int al = s.lvl - (31 - __builtin_clz(ch));
@@ -200,34 +205,34 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const uint32_t pk = s.key >> ((3 * (s.lvl - l)) & 31);
     // PH_DESCEND candidate: the child the ray is in just after the current
     // crossing tn/td. Along axis j the mid-plane M counts as crossed iff its
-    // parameter is smaller, or equal with j not above ta; a plane behind the
-    // origin (dl < 0) is always crossed, and with no motion along j the point
-    // O decides (O >= M: upper half). dl is the signed distance along the
-    // ray's direction on j.
+    // parameter is smaller, or equal with j not above ta: with d = M - O,
+    // iff d td < tn |q_j| + k (k = 1 when j is not above ta), i.e. iff
+    // P = tn |q_j| + k - d td > 0, one signed 32 x 32 + 64 product-add
+    // (td < 2^24); a plane behind the origin (d < 0) gives P > 0. A point on
+    // the plane (d = 0) of an axis that is not mirrored is in the upper half
+    // (the half-open cells of the original frame); that decides only where
+    // tn |q_j| = 0 (at the origin, or with no motion along j, where O >= M
+    // is the whole rule), and there k = 1 gives it.
     const uint32_t half = 1u << (29 - s.lvl);
-    const uint32_t M0 = s.lo0 + half, M1 = s.lo1 + half, M2 = s.lo2 + half;
-    const int32_t t0 = (int32_t)(M0 - s.O0), t1 = (int32_t)(M1 - s.O1), t2 = (int32_t)(M2 - s.O2);
-    // With d = ±t the signed distance along the direction, the plane is
-    // crossed iff d td < tn |q_j| + k (k = 1 when j is not above ta), i.e.
-    // iff P = tn |q_j| - d td > -k: P is one signed 32 x 32 + 64 product-add
-    // (td < 2^24); a plane behind the origin (d < 0) gives P > 0.
+    const int32_t nd0 = (int32_t)(s.O0 - s.lo0 - half);   // -d
+    const int32_t nd1 = (int32_t)(s.O1 - s.lo1 - half);
+    const int32_t nd2 = (int32_t)(s.O2 - s.lo2 - half);
     const int64_t td = (int64_t)(int32_t)s.td;
-    const int64_t P0 = (int64_t)(n0 ? t0 : -t0) * td + (int64_t)((uint64_t)s.tn * s.aq0);
-    const int64_t P1 = (int64_t)(n1 ? t1 : -t1) * td + (int64_t)((uint64_t)s.tn * s.aq1);
-    const int64_t P2 = (int64_t)(n2 ? t2 : -t2) * td + (int64_t)((uint64_t)s.tn * s.aq2);
-    // (non-short-circuit ors, so nothing branches)
-    const bool x0 = (s.ta >= 0 ? P0 >= 0 : P0 > 0) | (!n0 & (t0 == 0));
-    const bool x1 = (s.ta >= 1 ? P1 >= 0 : P1 > 0) | (!n1 & (t1 == 0));
-    const bool x2 = (s.ta >= 2 ? P2 >= 0 : P2 > 0) | (!n2 & (t2 == 0));
-    const bool u0 = x0 != n0, u1 = x1 != n1, u2 = x2 != n2;   // upper half of the cell on each axis
+    const bool t0 = s.tn == 0u;
+    const uint32_t k0 = (s.ta >= 0) | (s.aq0 == 0u) | (((s.mir & 1u) == 0u) & t0) ? 1u : 0u;
+    const uint32_t k1 = (s.ta >= 1) | (s.aq1 == 0u) | (((s.mir & 2u) == 0u) & t0) ? 1u : 0u;
+    const uint32_t k2 = (s.ta >= 2) | (s.aq2 == 0u) | (((s.mir & 4u) == 0u) & t0) ? 1u : 0u;
+    const bool u0 = (int64_t)nd0 * td + (int64_t)((uint64_t)s.tn * s.aq0 + k0) > 0;
+    const bool u1 = (int64_t)nd1 * td + (int64_t)((uint64_t)s.tn * s.aq1 + k1) > 0;
+    const bool u2 = (int64_t)nd2 * td + (int64_t)((uint64_t)s.tn * s.aq2 + k2) > 0;
     const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
 
     // the cell to test (a lane that left the cube tests the root instead: its
-    // stepped key and level are out of range)
+    // stepped key and level are out of range), its key back in the original frame
     const int tl = miss ? 0 : (path ? l : s.lvl + 1);
     const uint32_t tk = miss ? 0u : (path ? pk : dk);
     vis += (!miss && tl >= count_from) ? 1 : 0;
-    const bool occ = occupied(bits, tl, tk);
+    const bool occ = occupied(bits, tl, tk ^ (s.flip >> (kFine - 3 * tl)));
 
     // Empty: the tested cell is the one to leave next. Occupied: on the path,
     // the next level down (the entered cell itself: descend from it); in a
@@ -249,12 +254,13 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     return occ && tl == D ? STEP_HIT : STEP_CONTINUE;
 }
 
-// The hit of a march whose last step returned STEP_HIT.
-WFPG_HD Hit hit_of(const MicroState &s)
+// The hit of a march whose last step returned STEP_HIT: the crossing axis, the
+// leaf key in the original frame, and |B - O| of the crossing.
+WFPG_HD Hit hit_of(const MicroState &s, int D)
 {
     Hit h;
     h.axis = s.ta;
-    h.key = s.key;
+    h.key = s.key ^ (s.flip >> (kFine - 3 * D));
     h.delta = s.tn;
     return h;
 }
@@ -277,7 +283,7 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
     for (int it = 0; it < kMaxTests; ++it) {
         const int st = micro_step(s, D, bits, count_from, vis);
         if (st == STEP_HIT) {
-            h = hit_of(s);
+            h = hit_of(s, D);
             return 1;
         }
         if (st == STEP_MISS) return 0;
