@@ -50,3 +50,29 @@ extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, con
         }
     }
 }
+
+// One march per (point, direction) pair for arbitrary directions (axis-aligned
+// and other directions with zero components included): out = {hit, axis, key,
+// delta} per pair, point-major.
+extern "C" void host_march_dirs(const uint64_t *bits, int D, const float *pos, int64_t n, const float *dirs,
+                                int nd, int64_t *out)
+{
+    const uint32_t *bits32 = reinterpret_cast<const uint32_t *>(bits);
+    auto load = [&](int, uint32_t wi) -> uint32_t { return bits32[wi]; };
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t O[3];
+        for (int k = 0; k < 3; ++k) O[k] = quantize_pos(pos[k * n + i]);
+        for (int b = 0; b < nd; ++b) {
+            const float *d = dirs + 3 * b;
+            int vis = 0;
+            Hit h = {-1, 0u, 0u};
+            const int res = march(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), D, load, 0, vis,
+                                  h);
+            int64_t *o = out + (i * nd + b) * 4;
+            o[0] = res;
+            o[1] = res > 0 ? h.axis : -1;
+            o[2] = res > 0 ? (int64_t)h.key : -1;
+            o[3] = res > 0 ? (int64_t)h.delta : -1;
+        }
+    }
+}

@@ -21,6 +21,8 @@ def host_lib(tmp_path_factory):
                            "-o", str(out)])
     L = C.CDLL(str(out))
     L.host_debug_march.restype = None
+    L.host_march_dirs.restype = None
+    L.host_march_dirs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]
     L.host_debug_march.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_int64,
                                                        C.c_void_p, C.c_int, C.c_float,
                                                        C.c_void_p, C.c_void_p]
@@ -105,3 +107,42 @@ def test_host_core_room(orc, host_lib):
     pos = np.concatenate([cam[:, idx], rnd], 1)
     got, vis = run_host(host_lib, o, 10, pos, 16)
     compare(o, got, vis, pos, 16)
+
+
+def test_host_core_special_directions(orc, host_lib):
+    """Directions with zero components (the axes, the face and cube
+    diagonals) and random ones, from points on cell corners, faces and the
+    cube's faces, where the membership of points on planes decides: every
+    (hit, axis, leaf key, |B - O|) equal to the oracle's single-ray march."""
+    import itertools
+    box = synth.cornell_box()
+    D = 5
+    o = orc.SVO(box, D)
+    dirs = [np.array(v, float) / np.linalg.norm(v) for v in itertools.product([-1, 0, 1], repeat=3) if any(v)]
+    rng = np.random.default_rng(8)
+    r = rng.normal(size=(24, 3))
+    r[np.arange(24), rng.integers(0, 3, 24)] = 0.0
+    dirs += list(r / np.linalg.norm(r, axis=1, keepdims=True))
+    dirs = np.ascontiguousarray(np.array(dirs, np.float32))
+    pos = (rng.integers(0, 2 ** D + 1, (3, 160)) / 2 ** D).astype(np.float32)
+    pos[:, 80:] = np.where(rng.random((3, 80)) < 0.5, pos[:, 80:], rng.random((3, 80))).astype(np.float32)
+    # the corners of the 1/4 and 1/8 grids lie on the planes of many levels at
+    # once, also in empty space, where a coarse cell is left through a face
+    # the point lies on and the next cell is descended from that crossing
+    g4 = np.stack(np.meshgrid(*[np.arange(5) / 4] * 3, indexing="ij")).reshape(3, -1)
+    g8 = np.stack(np.meshgrid(*[np.arange(9) / 8] * 3, indexing="ij")).reshape(3, -1)
+    pos = np.ascontiguousarray(np.concatenate([pos, g4, g8], 1).astype(np.float32))
+    bits, _, _, _ = bitmaps_from_oracle(o, D)
+    out = np.zeros((pos.shape[1], len(dirs), 4), np.int64)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    host_lib.host_march_dirs(p(bits), D, p(pos), pos.shape[1], p(dirs), len(dirs), p(out))
+    hits = 0
+    for i in range(pos.shape[1]):
+        for b in range(len(dirs)):
+            w = o.march_one(pos[:, i], dirs[b])
+            got = out[i, b]
+            assert got[0] == w["hit"], (i, b, got, w)
+            if w["hit"]:
+                hits += 1
+                assert (got[1], got[2], got[3]) == (w["axis"], w["key"], w["delta"]), (i, b, got, w)
+    assert hits > 1000
