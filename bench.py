@@ -34,7 +34,7 @@ VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 2
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3e6158cca3931736f15e4af51b2c932f2814b8ec271d6fde2d41ae80f5c3f183",
+    "sources_sha256": "fbb23b13eae09dcb9658bde088fb3de9e26ec7d2a04e2405403369002f5a751e",
     "N": 16,
     "tile": {"waves_per_block": 4, "blocks_per_cu": 6},
     "bytes_per_launch": 5112204934,

@@ -37,11 +37,7 @@ constexpr int kFine = 30;
 // take one 64-bit word each, level l >= 3 takes 8^l / 64 words).
 WFPG_HD uint32_t woff(int l)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t t = __umul24((uint32_t)l, 3u) - 9u;   // a full-rate 24-bit product
-#else
-    const uint32_t t = 3u * (uint32_t)l - 9u;
-#endif
+    const uint32_t t = 3u * (uint32_t)l - 9u;   // wraps for l < 3, where l is returned
     const uint32_t f = 3u + ((0x09249249u & ((1u << (t & 31u)) - 1u)) << 3);
     return l <= 3 ? (uint32_t)l : f;
 }
