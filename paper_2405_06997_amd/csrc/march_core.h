@@ -293,22 +293,21 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
 // k = #{ j in 1..D : A > 2.5 * 4^(j-1) } levels above the leaf.
 WFPG_HD int footprint_levels(uint32_t delta, float dabs, int D, float omega)
 {
-    float scale = 1.0f;
-    WFPG_UNROLL
-    for (int i = 0; i < kFine; ++i)                         // exact 2^-(30-D)
-        if (i < kFine - D) scale *= 0.5f;
+    const float scale = __builtin_ldexpf(1.0f, D - kFine);   // exactly 2^-(30-D)
     const float dist = ((float)delta * scale) / dabs;
     const float sq = dist * dist;
     const float A = sq * omega;
-    int k = 0;
-    float thr = 2.5f;
-    WFPG_UNROLL
-    for (int j = 1; j <= 10; ++j) {
-        if (j > D) break;
-        k += A > thr ? 1 : 0;
-        thr *= 4.0f;
-    }
-    return k;
+    // The thresholds 2.5 * 4^(j-1) are 1.25 * 2^(2j-1): with A = m 2^e,
+    // m in [1, 2), A exceeds the j-th iff 2j - 1 < e, or 2j - 1 = e and
+    // m > 1.25, so k = floor(e / 2) plus one when e is odd and m > 1.25,
+    // capped at D (the same count as comparing with each threshold in turn).
+    if (!(A > 2.5f)) return 0;                 // also NaN
+    if (A > 3.40282347e38f) return D;          // infinity
+    int e;
+    const float m = __builtin_frexpf(A, &e);   // A = m 2^e, m in [0.5, 1)
+    --e;
+    const int k = (e >> 1) + (((e & 1) != 0) && m > 0.625f ? 1 : 0);
+    return k < D ? k : D;
 }
 
 // Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), the counter-based
