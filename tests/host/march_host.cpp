@@ -76,3 +76,9 @@ extern "C" void host_march_dirs(const uint64_t *bits, int D, const float *pos, i
         }
     }
 }
+
+// Footprint level of the library for given (delta, |d_axis|, D, omega).
+extern "C" int host_footprint_levels(uint32_t delta, float dabs, int D, float omega)
+{
+    return footprint_levels(delta, dabs, D, omega);
+}

@@ -21,6 +21,8 @@ def host_lib(tmp_path_factory):
                            "-o", str(out)])
     L = C.CDLL(str(out))
     L.host_debug_march.restype = None
+    L.host_footprint_levels.restype = C.c_int
+    L.host_footprint_levels.argtypes = [C.c_uint32, C.c_float, C.c_int, C.c_float]
     L.host_march_dirs.restype = None
     L.host_march_dirs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]
     L.host_debug_march.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_int64,
@@ -146,3 +148,22 @@ def test_host_core_special_directions(orc, host_lib):
                 hits += 1
                 assert (got[1], got[2], got[3]) == (w["axis"], w["key"], w["delta"]), (i, b, got, w)
     assert hits > 1000
+
+
+def test_host_footprint_levels_at_thresholds(host_lib):
+    """Eq. 7: the footprint is k levels above the leaf, k the number of
+    j = 1..D with A > 2.5 * 4^(j-1). With delta = 2^(30-D) and |d| = 1 the
+    distance is exactly one leaf, so A = omega: every threshold, its FP32
+    neighbours on both sides, 0, infinity and random values, for every D."""
+    thr = [np.float32(2.5) * np.float32(4) ** j for j in range(12)]
+    vals = [np.float32(0), np.float32(np.inf), np.float32(1e-30), np.float32(3e38)]
+    for t in thr:
+        t = np.float32(t)
+        vals += [t, np.nextafter(t, np.float32(0)), np.nextafter(t, np.float32(np.inf)),
+                 np.float32(t * np.float32(1.5))]
+    vals += list(np.random.default_rng(4).uniform(0, 6e6, 300).astype(np.float32))
+    for D in range(1, 11):
+        for A in vals:
+            want = sum(1 for j in range(1, D + 1) if A > np.float32(2.5) * np.float32(4) ** (j - 1))
+            got = host_lib.host_footprint_levels(1 << (30 - D), 1.0, D, float(A))
+            assert got == want, (D, float(A), got, want)
