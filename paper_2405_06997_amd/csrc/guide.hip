@@ -463,7 +463,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 feed = f;
                 nxt = 0;
             }
-            const int take = min(__popcll(idle), NN - nxt);
+            const int nidle = (int)__popcll(idle), left = NN - nxt;
+            const int take = nidle < left ? nidle : left;   // (integer min: the mixed-type min was FP64)
             const int r = lanes_below(idle);
             const bool mine = ((idle >> lane) & 1ull) && r < take;
             if (mine) {
