@@ -151,6 +151,21 @@ def test_march_bitexact_c1(c1, w, torch_dev):
         assert hr > 0.3
 
 
+def test_march_bitexact_on_planes(c1, w, torch_dev):
+    """Queries exactly on cell planes, where the march's mirrored frame must
+    reproduce the original frame's half-open cells: the corners of the 1/4,
+    1/8 and leaf (1/64) grids, the cube's faces, and random points with some
+    coordinates snapped to leaf planes; every record and visit count bit-exact."""
+    rng = np.random.default_rng(17)
+    g4 = np.stack(np.meshgrid(*[np.arange(5) / 4] * 3, indexing="ij")).reshape(3, -1)
+    g8 = np.stack(np.meshgrid(*[np.arange(9) / 8] * 3, indexing="ij")).reshape(3, -1)
+    leaf = rng.integers(0, 65, (3, 400)) / 64.0
+    mix = np.where(rng.random((3, 400)) < 0.5, rng.integers(0, 65, (3, 400)) / 64.0, rng.random((3, 400)))
+    pos = np.ascontiguousarray(np.concatenate([g4, g8, leaf, mix], 1).astype(np.float32))
+    for N in (8, 16):
+        _march_compare(c1["o"], c1["g"], w, torch_dev, pos, N)
+
+
 @pytest.mark.parametrize("N,k", [(16, 384), (8, 256), (32, 48)])
 def test_march_bitexact_c2(c2, w, torch_dev, N, k):
     cam, _ = sample_cols(c2["cam"], k // 2, 1)
