@@ -116,7 +116,7 @@ constexpr int kMaxTests = 1 << 17;   // > worst-case occupancy tests of a depth-
 struct MicroState {
     uint32_t O0, O1, O2;      // origin in the mirrored frame, 2^-30 units
     uint32_t aq0, aq1, aq2;   // |q|
-    uint32_t mir;             // bit j: axis j is mirrored (q_j < 0)
+    uint32_t mir;             // bit j: axis j is mirrored (q_j < 0); bit 3 + j: q_j = 0
     uint32_t flip;            // key bits of the mirrored axes, all levels
     int lvl, ta, l, phase;
     uint32_t key, tn, td;     // key in the mirrored frame
@@ -139,7 +139,9 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
     s.lo1 = n1 ? (1u << kFine) - (O[1] & mk) - leaf : O[1] & mk;
     s.lo2 = n2 ? (1u << kFine) - (O[2] & mk) - leaf : O[2] & mk;
     s.aq0 = aq0; s.aq1 = aq1; s.aq2 = aq2;
-    s.mir = (n0 ? 1u : 0u) | (n1 ? 2u : 0u) | (n2 ? 4u : 0u);
+    // bits 0-2: mirrored axes; bits 3-5: axes without motion (|q| = 0)
+    s.mir = (n0 ? 1u : 0u) | (n1 ? 2u : 0u) | (n2 ? 4u : 0u) | (aq0 == 0u ? 8u : 0u) | (aq1 == 0u ? 16u : 0u) |
+            (aq2 == 0u ? 32u : 0u);
     s.flip = (n0 ? 0x09249249u : 0u) | (n1 ? 0x12492492u : 0u) | (n2 ? 0x24924924u : 0u);
     s.ta = -1; s.tn = 0; s.td = 1;
     s.lvl = D;
@@ -209,15 +211,15 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     // (the half-open cells of the original frame); that decides only where
     // tn |q_j| = 0 (at the origin, or with no motion along j, where O >= M
     // is the whole rule), and there k = 1 gives it.
-    const uint32_t half = 1u << (29 - s.lvl);
+    const uint32_t half = size >> 1;
     const int32_t nd0 = (int32_t)(s.O0 - s.lo0 - half);   // -d
     const int32_t nd1 = (int32_t)(s.O1 - s.lo1 - half);
     const int32_t nd2 = (int32_t)(s.O2 - s.lo2 - half);
     const int64_t td = (int64_t)(int32_t)s.td;
-    const bool t0 = s.tn == 0u;
-    const uint32_t k0 = (s.ta >= 0) | (s.aq0 == 0u) | (((s.mir & 1u) == 0u) & t0) ? 1u : 0u;
-    const uint32_t k1 = (s.ta >= 1) | (s.aq1 == 0u) | (((s.mir & 2u) == 0u) & t0) ? 1u : 0u;
-    const uint32_t k2 = (s.ta >= 2) | (s.aq2 == 0u) | (((s.mir & 4u) == 0u) & t0) ? 1u : 0u;
+    // k_j as bits: bit j of K (j not above ta: the low ta + 1 bits; an axis
+    // without motion; a non-mirrored axis while tn = 0)
+    const uint32_t K = ((1u << (s.ta + 1)) - 1u) | (s.mir >> 3) | (s.tn == 0u ? ~s.mir & 7u : 0u);
+    const uint32_t k0 = K & 1u, k1 = (K >> 1) & 1u, k2 = (K >> 2) & 1u;
     const bool u0 = (int64_t)nd0 * td + (int64_t)((uint64_t)s.tn * s.aq0 + k0) > 0;
     const bool u1 = (int64_t)nd1 * td + (int64_t)((uint64_t)s.tn * s.aq1 + k1) > 0;
     const bool u2 = (int64_t)nd2 * td + (int64_t)((uint64_t)s.tn * s.aq2 + k2) > 0;
