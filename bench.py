@@ -34,11 +34,11 @@ VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 2
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "25889283377a0f1d7108c826d5db164b48b16d567d129802b5db5cc2d5e69271",
+    "sources_sha256": "72bbcc71e6f9588f1f6b0cb287927cec04f4d10a19f373221ba9a8b66e46b2ae",
     "N": 16,
     "tile": {"waves_per_block": 4, "blocks_per_cu": 6},
-    "bytes_per_launch": 5101506979,
-    "valu_wave_instrs_per_launch": 17788966016,
+    "bytes_per_launch": 5120221150,
+    "valu_wave_instrs_per_launch": 17557459930,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 
