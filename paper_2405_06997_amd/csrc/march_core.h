@@ -149,7 +149,7 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
     s.l = 0;
     if (origin_occupied) {
         s.phase = PH_ADVANCE;
-        vis += D + 1 - (count_from < D ? count_from : D);   // levels count_from..D
+        vis += D + 1 > count_from ? D + 1 - count_from : 0;   // levels count_from..D
     } else {
         s.phase = PH_PATH;
     }

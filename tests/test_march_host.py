@@ -100,6 +100,18 @@ def test_host_core_boundaries(orc, host_lib):
     compare(o, got, vis, pos, 8)
 
 
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+def test_host_core_shallow(orc, host_lib, D):
+    """Depths below the first counted level (5): an occupied origin leaf adds
+    no node test, as in the oracle's walk."""
+    box = synth.cornell_box()
+    o = orc.SVO(box, D)
+    pos, _, _ = synth.area_points(box, 512, 3)
+    got, vis = run_host(host_lib, o, D, pos, 8)
+    assert (vis == 0).all()
+    compare(o, got, vis, pos, 8)
+
+
 def test_host_core_room(orc, host_lib):
     room = synth.room()
     o = orc.SVO(room, 10)
