@@ -558,6 +558,7 @@ def cpu_baseline(room, splats, cam, N, S, n, seed):
     ref = o.guide_sample(sub, N, seed=seed, bounce=0, counter=idx)
     t_gs = time.perf_counter() - t
     ref["index"] = idx
+    ref["max_splats"] = int(max(1, o.leaf_accum()[2].max()))
     step = t_acc + t_gs / S * n
     cores = oracle.num_threads()
     S1 = max(1, S // 32)
@@ -583,7 +584,13 @@ def cpu_baseline(room, splats, cam, N, S, n, seed):
 def parity(d_out, p_out, ref, N):
     """The last timed step's samples against the oracle's on the CPU-baseline
     sample: sampled bins equal outside the FP32 scan band, pdf and direction
-    errors on the equal ones (bars: 1e-5 relative, 4e-6 chord)."""
+    errors on the equal ones. Bars: pdf 1e-5 relative; direction chord 2e-6;
+    the scan band (4 log2 N + 3 + 2 (C - 1)) 2^-24 of the total, C the most
+    splats any leaf side received (the FP32 atomic order then moves a stored
+    value by at most (C - 1) 2^-24; two Hillis-Steele scans of depth log2 N
+    sit between the field and a CDF boundary)."""
+    import math
+
     import numpy as np
 
     import oracle
@@ -593,13 +600,15 @@ def parity(d_out, p_out, ref, N):
     uv = oracle.oct_encode_many(d)
     gb = np.minimum((uv * N).astype(np.int64), N - 1)
     same = (gb[0] == ref["bin"][:, 0]) & (gb[1] == ref["bin"][:, 1])
-    band = (ref["margin"] < 1e-5).any(1)
+    C = ref["max_splats"]
+    band_rel = (4 * math.log2(N) + 3 + 2 * (C - 1)) * 2.0 ** -24
+    band = (ref["margin"] < band_rel).any(1)
     rel = np.abs(p[same] - ref["pdf"][same]) / ref["pdf"][same]
     chord = np.linalg.norm(d[:, same] - ref["dir"][:, same], axis=0)
     return {"vertices": int(len(idx)), "same_bin": float(same.mean()),
-            "differing_outside_scan_band": int((~same & ~band).sum()),
+            "scan_band": band_rel, "differing_outside_scan_band": int((~same & ~band).sum()),
             "pdf_max_rel_err": float(rel.max()), "dir_max_chord": float(chord.max()),
-            "ok": bool((~same & ~band).sum() == 0 and rel.max() <= 1e-5 and chord.max() < 4e-6)}
+            "ok": bool((~same & ~band).sum() == 0 and rel.max() <= 1e-5 and chord.max() < 2e-6)}
 
 
 if __name__ == "__main__":

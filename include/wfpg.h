@@ -93,7 +93,9 @@ typedef struct {
  *              octahedral square are the mirrored bins ((N, v) is
  *              (N - 1, N - 1 - v), (u, N) is (N - 1 - u, N - 1)), as the map
  *              joins them on the sphere. 0 or 1 (default 0).
- *  Mode 1 takes neither jitter nor blur (EINVAL). */
+ *  In mode 1 the judge's probes and the fallback march both use eps, jitter
+ *  and blur as given here, so the judge measures the network against the
+ *  very field the fallback would sample. */
 typedef struct {
     int32_t N;
     float eps;
@@ -490,7 +492,8 @@ wfpg_status guide_sample_binned_product(const wfpg_svo *svo, const float *pos, c
  * uses (Sec. 3.3). Table, inputs, weights and activations are BF16, products
  * accumulate in FP32 (MFMA); master parameters and Adam moments are FP32.
  * It is trained on pdfs the march itself produces (guide_pdf at N = 16 with
- * eps = 0.01) by minimising the mean cross-entropy -sum_b t_b log q_b.
+ * eps = target_eps and, with target_blur = 1, the blurred field) by
+ * minimising the mean cross-entropy -sum_b t_b log q_b.
  *
  * Parameter vector order (FP32): W0[64][35], b0[64], W1[64][64], b1, W2, b2,
  * W3, b3, W4[256][64], b4[256], then the table [16][2^log2_table][2]
@@ -509,6 +512,8 @@ typedef struct {
     float beta1, beta2;  /* Adam moment decays (0.9, 0.99) */
     float adam_eps;      /* Adam denominator guard (1e-15) */
     uint64_t seed;       /* initialisation seed, used when the model is created */
+    float target_eps;    /* eps of the march fields the model is trained on, finite > 0 (0.01) */
+    int32_t target_blur; /* 1: the training targets are the blurred fields (Sec. 4), 0 or 1 (0) */
 } wfpg_train_cfg;
 
 wfpg_train_cfg wfpg_default_train_cfg(void);

@@ -75,7 +75,8 @@ class TrainCfg(C.Structure):
     _fields_ = [("log2_table", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32),
                 ("batch", C.c_int32), ("steps", C.c_int32), ("lr_mlp", C.c_float),
                 ("lr_table", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("adam_eps", C.c_float), ("seed", C.c_uint64)]
+                ("adam_eps", C.c_float), ("seed", C.c_uint64), ("target_eps", C.c_float),
+                ("target_blur", C.c_int32)]
 
 
 def make_opts(N: int = 16, eps: float = 0.01, mode: int = 0, kl_bound: float = 0.05,

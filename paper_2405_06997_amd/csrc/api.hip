@@ -133,7 +133,6 @@ bool valid_opts(const wfpg_opts *o)
     if (!std::isfinite(o->eps) || !(o->eps > 0.f)) return false;
     if (o->mode != 0 && o->mode != 1) return false;
     if ((o->jitter != 0 && o->jitter != 1) || (o->blur != 0 && o->blur != 1)) return false;
-    if (o->mode == 1 && (o->jitter || o->blur)) return false;   // the learned stand-in has no field to filter
     return true;
 }
 

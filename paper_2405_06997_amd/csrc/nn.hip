@@ -1068,11 +1068,15 @@ bool valid_cfg(const wfpg_train_cfg *c)
            (c->n_max == 0 || c->n_max > c->n_min) && c->batch >= 64 && c->batch <= (1 << 22) &&
            c->steps >= 0 && std::isfinite(c->lr_mlp) && std::isfinite(c->lr_table) &&
            c->lr_mlp >= 0 && c->lr_table >= 0 && c->beta1 >= 0 && c->beta1 < 1 && c->beta2 >= 0 &&
-           c->beta2 < 1 && c->adam_eps > 0;
+           c->beta2 < 1 && c->adam_eps > 0 && std::isfinite(c->target_eps) && c->target_eps > 0 &&
+           (c->target_blur == 0 || c->target_blur == 1);
 }
 
-hipError_t march_pdf(const wfpg_svo *svo, const float *pos, int64_t n, int64_t stride, float *out,
-                     hipStream_t s)
+// The march's pdf at N = 16 of n vertices (SoA planes of stride `stride`):
+// the field with the given eps, optional jitter key and blur (Sec. 4), as
+// guide_pdf computes it.
+hipError_t march_pdf(const wfpg_svo *svo, const float *pos, int64_t n, int64_t stride, float eps,
+                     int jitter, uint32_t jitter_key, int blur, float *out, hipStream_t s)
 {
     GuideArgs a;
     std::memset(&a, 0, sizeof a);
@@ -1080,7 +1084,10 @@ hipError_t march_pdf(const wfpg_svo *svo, const float *pos, int64_t n, int64_t s
     a.pos = pos;
     a.n = n;
     a.stride = stride;
-    a.eps = 0.01f;
+    a.eps = eps;
+    a.jitter = jitter;
+    a.jitter_key = jitter_key;
+    a.blur = blur;
     a.omega = (float)(4.0 * pi / 256.0);
     a.pdf_scale = (float)(256.0 / (4.0 * pi));
     a.dirtab = device_dirtab(16);
@@ -1108,6 +1115,8 @@ wfpg_train_cfg wfpg_default_train_cfg(void)
     c.beta2 = 0.99f;
     c.adam_eps = 1e-15f;
     c.seed = 1;
+    c.target_eps = 0.01f;
+    c.target_blur = 0;
     return c;
 }
 
@@ -1127,7 +1136,7 @@ wfpg_status guide_train(wfpg_svo *svo, const float *pos, const float *nrm, int64
     for (int st = 0; st < cfg->steps; ++st) {
         int64_t off = (int64_t)(((uint64_t)M->steps_done * (uint64_t)b) % (uint64_t)n);
         if (off + b > n) off = n - b;
-        e = march_pdf(svo, pos + off, b, n, (float *)M->tpdf.p, s);
+        e = march_pdf(svo, pos + off, b, n, cfg->target_eps, 0, 0u, cfg->target_blur, (float *)M->tpdf.p, s);
         if (e == hipSuccess) e = nn::forward(*M, pos + off, nrm + off, b, n, s);
         if (e == hipSuccess) e = nn::backward(*M, pos + off, b, n, (const float *)M->tpdf.p, s);
         if (e != hipSuccess) return st_of(e, __LINE__);
@@ -1269,7 +1278,11 @@ wfpg_status learned_sample(const wfpg_svo *svo, const float *pos, const float *n
                            (float *)M->pnrm.p);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = march_pdf(svo, (const float *)M->ppos.p, m, m, (float *)M->tp.p, s);
+    // the probes' targets are the field the fallback march samples (same eps,
+    // jitter and blur), so the judge measures the network against its output
+    if (e == hipSuccess)
+        e = march_pdf(svo, (const float *)M->ppos.p, m, m, o->eps, o->jitter, o->jitter_key, o->blur,
+                      (float *)M->tp.p, s);
     if (e == hipSuccess) e = nn::forward(*M, (const float *)M->ppos.p, (const float *)M->pnrm.p, m, m, s);
     if (e == hipSuccess) e = nn::fill(M->d_klsum, 1, 0.f, s);
     if (e == hipSuccess) {
@@ -1285,6 +1298,9 @@ wfpg_status learned_sample(const wfpg_svo *svo, const float *pos, const float *n
         a.pos = pos;
         a.n = n;
         a.eps = o->eps;
+        a.jitter = o->jitter;
+        a.jitter_key = o->jitter_key;
+        a.blur = o->blur;
         a.omega = (float)(4.0 * pi / 256.0);
         a.pdf_scale = (float)(256.0 / (4.0 * pi));
         a.seed = seed;

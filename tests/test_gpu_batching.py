@@ -2,10 +2,12 @@
 
 The graph's kernels read their queue lengths from device memory; every
 replay (with eager work and synchronizations in between) must equal eager
-guide_sample bit for bit, also after the lengths shrink."""
+guide_sample bit for bit, also after the lengths shrink, and every bounce of
+the eight-bounce wavefront on the depth-10 room must match the oracle."""
 import numpy as np
 import pytest
 
+import bars
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -105,3 +107,63 @@ def test_autotune_n_on_a_large_queue_uses_a_subset(env):
     assert r["N"] == 32 and all(v > 0 for v in r["ms_per_N"].values())
     d, p = w.guide_sample(g, q, w.make_opts(N=8), seed=2, bounce=1)
     assert torch.equal(d, ref_d) and torch.equal(p, ref_p)
+
+
+def test_graph_eight_bounces_match_oracle(orc):
+    """The batching configuration: the depth-10 room with 2M splats, bounce 0
+    the 1920 x 1080 camera queue, bounces 1-7 area-uniform queues shrinking
+    by U[0.5, 0.8] per bounce, N per bounce in {8, 16, 32}, replayed twice
+    from one captured graph. On every bounce a strided subset (at least 4096
+    vertices; the oracle's counter is the queue index and its bounce the
+    bounce number) matches the oracle at the sampling bars."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_2405_06997_amd as w
+    dev = torch.device("cuda:0")
+    room = synth.room()
+    o = orc.SVO(room, 10)
+    sp = synth.room_splats(room, 2_000_000, 13)
+    o.accumulate(*sp)
+    o.propagate()
+    _, _, cnt = o.leaf_accum()
+    C = int(max(1, cnt.max()))
+    g = w.svo_build(room, 10)
+    w.svo_accumulate(g, *[torch.from_numpy(a).to(dev) for a in sp])
+    cam, cnrm, _ = synth.camera_queue(room)
+    qs, sizes = synth.bounce_queues(room, cam, cnrm, 8, 15)
+    Ns = [16, 8, 32, 16, 8, 32, 16, 8]
+    queues = [torch.from_numpy(np.ascontiguousarray(p)).to(dev) for p, _ in qs]
+    n_dev = torch.tensor(sizes, dtype=torch.int64, device=dev)
+    G = w.BounceGraph(g, queues, n_dev, Ns, seed=4242)
+    for rep in range(2):
+        G.launch()
+        torch.cuda.synchronize()
+        for b, (n, N) in enumerate(zip(sizes, Ns)):
+            step = max(1, n // 4096)
+            idx = np.arange(0, n, step)
+            if len(idx) < 4096:
+                idx = np.arange(n)
+            pos = np.ascontiguousarray(qs[b][0][:, idx])
+            ref = o.guide_sample(pos, N, seed=4242, bounce=b, counter=idx)
+            d = G.dirs[b][:, idx].cpu().numpy().astype(np.float64)
+            p = G.pdfs[b][idx].cpu().numpy().astype(np.float64)
+            uv = oracle.oct_encode_many(d)
+            gb = np.minimum((uv * N).astype(np.int64), N - 1)
+            same = (gb[0] == ref["bin"][:, 0]) & (gb[1] == ref["bin"][:, 1])
+            band = ref["margin"].min(1) < bars.scan_band(N, C)
+            fx, fy = uv[0] * N, uv[1] * N
+            edge = np.minimum(np.abs(fx - np.rint(fx)), np.abs(fy - np.rint(fy)))
+            bad = ~same & ~band & (edge > bars.edge_band(N))
+            assert not bad.any(), (rep, b, np.nonzero(bad)[0][:10])
+            assert same.mean() > 0.99, (rep, b)
+            rel = np.abs(p[same] - ref["pdf"][same]) / ref["pdf"][same]
+            bars.record(f"bounce graph N={N} rel", rel.max(), bars.pdf_bound(N, C))
+            assert rel.max() <= bars.PDF_RTOL, (rep, b, rel.max())
+            ok = same & (edge > bars.edge_band(N))
+            chord = np.linalg.norm(d[:, ok] - ref["dir"][:, ok], axis=0)
+            bars.record(f"bounce graph N={N} dir", chord.max(), bars.DIR_TOL)
+            assert chord.max() < bars.DIR_TOL, (rep, b, chord.max())
+    assert g.stats()["errors"] == 0
+    G.close()

@@ -58,10 +58,12 @@ def box(w, torch_dev):
     o = oracle.SVO(rects, 6)
     xyz, em = o.leaf_info()
     sp = synth.leaf_splats(xyz, o.normals(6), em, 6, seed=2)
+    assert o.accumulate(*sp) == 0
+    o.propagate()
     g = w.svo_build(rects, 6)
     w.svo_accumulate(g, *[dev(torch_dev, a) for a in sp])
     pos, nrm, _ = synth.area_points(rects, 300, 21)
-    return dict(rects=rects, g=g, pos=pos, nrm=nrm)
+    return dict(rects=rects, g=g, o=o, pos=pos, nrm=nrm)
 
 
 def small_model(w, torch_dev, rects):
@@ -233,17 +235,16 @@ def trained(w, torch_dev, box):
     rects, g = box["rects"], box["g"]
     pos, nrm, _ = synth.area_points(rects, 131072, 22)
     dpos, dnrm = dev(torch_dev, pos), dev(torch_dev, nrm)
-    hpos, hnrm, _ = synth.area_points(rects, 4096, 23)      # held out
-    hpos, hnrm = dev(torch_dev, hpos), dev(torch_dev, hnrm)
-    opts = w.make_opts(N=16)
-    target = w.guide_pdf(g, hpos, opts).cpu().numpy().astype(np.float64) * FOUR_PI / 256
+    hpos_h, hnrm_h, _ = synth.area_points(rects, 4096, 23)      # held out
+    hpos, hnrm = dev(torch_dev, hpos_h), dev(torch_dev, hnrm_h)
+    target = box["o"].guide_pdf(hpos_h, 16) * FOUR_PI / 256     # the oracle's march distribution
     target /= target.sum(1, keepdims=True)
     w.guide_train(g, dpos, dnrm, steps=0, seed=1, n_max=64)
     kl_init = kl_to(w, g, hpos, hnrm, target)
     losses = [w.guide_train(g, dpos, dnrm, steps=100, batch=16384, n_max=64) for _ in range(4)]
     kl_trained = kl_to(w, g, hpos, hnrm, target)
-    return dict(g=g, dpos=dpos, dnrm=dnrm, hpos=hpos, hnrm=hnrm, target=target, kl_init=kl_init,
-                kl_trained=kl_trained, losses=losses)
+    return dict(g=g, dpos=dpos, dnrm=dnrm, hpos=hpos, hnrm=hnrm, hpos_h=hpos_h, target=target,
+                kl_init=kl_init, kl_trained=kl_trained, losses=losses)
 
 
 def kl_to(w, g, hpos, hnrm, target):
@@ -272,6 +273,29 @@ def test_judge_kl_is_probe_mean(orc, w, torch_dev, trained):
     q = w.nn_forward(g, hpos, hnrm).cpu().numpy().astype(np.float64)
     want = float(orc.kl_rows(t["target"][::stride], q[::stride]).mean())
     assert abs(kl - want) <= 1e-3 * want + 1e-6, (kl, want)
+
+
+@pytest.mark.parametrize("eps,blur", [(0.1, False), (0.01, True), (0.3, True)])
+def test_judge_uses_the_fallback_field(orc, w, torch_dev, box, trained, eps, blur):
+    """The judge's probes are marched with the caller's eps and blur, the
+    field the fallback would sample: its KL equals the oracle's KL of the
+    network against that field (Sec. 4 initial value and blur)."""
+    t, g = trained, trained["g"]
+    stride = 16
+    opts = w.make_opts(N=16, eps=eps, mode=1, kl_bound=1e30, probe_stride=stride, blur=blur)
+    w.guide_sample(g, t["hpos"], opts, seed=1, bounce=0, nrm=t["hnrm"])
+    kl = w.learned_stats(g)["last_probe_kl"]
+    q = w.nn_forward(g, t["hpos"], t["hnrm"]).cpu().numpy().astype(np.float64)[::stride]
+    L = box["o"].field_aa(np.ascontiguousarray(t["hpos_h"][:, ::stride]), 16, blur=blur, eps=eps)
+    target = L / L.sum(1, keepdims=True)
+    want = float(orc.kl_rows(target, q).mean())
+    assert abs(kl - want) <= 1e-3 * want + 1e-6, (kl, want)
+    # and a bound the network misses makes the call return that field's march samples
+    d0, p0 = w.guide_sample(g, t["hpos"], w.make_opts(N=16, eps=eps, blur=blur), seed=3, bounce=1)
+    d1, p1 = w.guide_sample(g, t["hpos"], w.make_opts(N=16, eps=eps, mode=1, kl_bound=0.0, blur=blur),
+                            seed=3, bounce=1, nrm=t["hnrm"])
+    assert np.array_equal(p0.cpu().numpy().view(np.uint32), p1.cpu().numpy().view(np.uint32))
+    assert np.array_equal(d0.cpu().numpy().view(np.uint32), d1.cpu().numpy().view(np.uint32))
 
 
 def test_fallback_is_the_march_bit_for_bit(w, torch_dev, trained):
