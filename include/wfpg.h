@@ -237,6 +237,29 @@ wfpg_status guide_sample(const wfpg_svo *svo, const float *pos, const float *nrm
                          void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * guide_sample_noalloc -- guide_sample (mode 0) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. It calls no hipMalloc, hipFree or
+ * allocating library routine; the caller passes inputs and outputs as for
+ * guide_sample and gets the same results bit for bit (same kernels).
+ *
+ * Its scratch is one static device array of 16,640 bytes per GPU, held
+ * until the process ends: the bin-direction tables of N = 8, 16 and 32 and
+ * the vertex-queue counter. The first call on a device, with that device
+ * current, looks the array up and uploads the tables synchronously (make
+ * that first call before capturing a graph); later calls only enqueue a
+ * counter reset (a kernel, not a memset) and the guide kernel on the stream.
+ * Every call on a GPU shares that array: calls that overlap on one GPU
+ * (concurrent streams) race on the counter and must be ordered by the
+ * caller.
+ * Errors: as guide_sample; EINVAL for N beyond the tables (not 8, 16 or
+ * 32); EUNSUPPORTED for mode 1 (the learned form keeps working buffers).
+ * ------------------------------------------------------------------- */
+wfpg_status guide_sample_noalloc(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
+                                 uint32_t bounce, const wfpg_opts *opts, float *dir_out,
+                                 float *pdf_out, void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * pdf_eval -- guiding pdf of given directions (needed to weight guided
  * samples against BSDF and light samples with MIS, Sec. 4): the direction
  * is encoded with the octahedral map, its bin taken, and pdf_b returned;

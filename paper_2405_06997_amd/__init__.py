@@ -30,7 +30,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device erro
 # exported symbols of include/wfpg.h (checked by the CPU test suite)
 EXPORTS = [
     "wfpg_default_opts", "wfpg_status_string", "svo_build", "svo_destroy", "svo_accumulate",
-    "guide_pdf", "guide_sample", "pdf_eval", "svo_stats", "svo_level_size", "svo_export_level",
+    "guide_pdf", "guide_sample", "guide_sample_noalloc", "pdf_eval", "svo_stats", "svo_level_size",
+    "svo_export_level",
     "svo_export_accum", "wfpg_dir_table", "wfpg_debug_march", "wfpg_last_error",
     "wfpg_march_counts", "wfpg_get_tile", "wfpg_set_tile", "wfpg_autotune",
     "wfpg_graph_create", "wfpg_graph_launch", "wfpg_graph_destroy", "wfpg_autotune_n",
@@ -113,6 +114,7 @@ def lib():
         "svo_accumulate_paths": (i32, [vp, vp, vp, vp, vp, vp, i64, i32, vp]),
         "guide_pdf": (i32, [vp, vp, i64, C.POINTER(Opts), vp, vp]),
         "guide_sample": (i32, [vp, vp, vp, i64, u64, u32, C.POINTER(Opts), vp, vp, vp]),
+        "guide_sample_noalloc": (i32, [vp, vp, i64, u64, u32, C.POINTER(Opts), vp, vp, vp]),
         "pdf_eval": (i32, [vp, vp, vp, i64, C.POINTER(Opts), vp, vp]),
         "svo_stats": (i32, [vp, vp, vp, vp, vp]),
         "svo_level_size": (i64, [vp, i32]),
@@ -308,6 +310,18 @@ def guide_sample(svo: SVO, pos, opts: Opts, seed: int, bounce: int, nrm=None, di
         svo.handle, _dptr(pos, 3, "pos"), _dptr(nrm, 3, "nrm") if nrm is not None else None, n,
         seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"), _dptr(pdf_out, name="pdf_out"),
         _stream(stream)))
+    return dir_out, pdf_out
+
+
+def guide_sample_noalloc(svo: SVO, pos, opts: Opts, seed: int, bounce: int, dir_out, pdf_out, stream=None):
+    """guide_sample into caller-provided outputs (3, n) and (n,) through the
+    entry point that allocates no device memory."""
+    n = pos.shape[1]
+    if dir_out.shape != (3, n) or pdf_out.numel() != n:
+        raise ValueError("output shapes must be (3, n) and (n,)")
+    _check("guide_sample_noalloc", lib().guide_sample_noalloc(
+        svo.handle, _dptr(pos, 3, "pos"), n, seed, bounce, C.byref(opts), _dptr(dir_out, 3, "dir_out"),
+        _dptr(pdf_out, name="pdf_out"), _stream(stream)))
     return dir_out, pdf_out
 
 

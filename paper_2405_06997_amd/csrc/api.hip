@@ -136,7 +136,9 @@ bool valid_opts(const wfpg_opts *o)
     return true;
 }
 
-GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o)
+// Kernel arguments common to the guide entry points; the bin-direction table
+// is the library's (uploaded on first use) unless with_table is false.
+GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o, bool with_table = true)
 {
     GuideArgs a;
     std::memset(&a, 0, sizeof a);
@@ -144,7 +146,7 @@ GuideArgs base_args(const wfpg_svo *svo, const wfpg_opts *o)
     a.eps = o->eps;
     a.omega = (float)(4.0 * pi / (double)(o->N * o->N));
     a.pdf_scale = (float)((double)(o->N * o->N) / (4.0 * pi));
-    a.dirtab = device_dirtab(o->N);
+    a.dirtab = with_table ? device_dirtab(o->N) : nullptr;
     a.err = svo->d_err;
     a.jitter = o->jitter;
     a.jitter_key = o->jitter_key;
@@ -502,6 +504,76 @@ wfpg_status wfpg_dir_table_jitter(int32_t N, uint32_t jitter_key, float *out)
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------------------
+// guide_sample without allocation. Its scratch is a file-scope device array:
+// the bin-direction tables of N = 8, 16 and 32 (FP32, three per bin, as
+// host_dir_table computes them) and the vertex-queue counter of the guide
+// kernel. Host code never passes the array's name to the device; it uses the
+// address hipGetSymbolAddress returns, taken once per device.
+namespace {
+
+constexpr size_t kNaTabFloats[3] = {8 * 8 * 3, 16 * 16 * 3, 32 * 32 * 3};
+constexpr size_t kNaTabOff[3] = {0, 8 * 8 * 3, 8 * 8 * 3 + 16 * 16 * 3};   // floats
+constexpr size_t kNaCounterOff = 16384;                                  // bytes (tables: 16128)
+constexpr size_t kNaScratchBytes = kNaCounterOff + 256;
+static_assert((kNaTabOff[2] + kNaTabFloats[2]) * sizeof(float) <= kNaCounterOff, "tables overlap the counter");
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[64] = {};   // device address of `scratch`, per device
+float g_na_host[(kNaTabOff[2] + kNaTabFloats[2])];
+
+// Device address of the scratch array on the current device; on the first
+// call for a device, looks it up and uploads the direction tables
+// (synchronously, with that device current).
+hipError_t noalloc_scratch(unsigned char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return note_error(e, __FILE__, __LINE__);
+        for (int k = 0; k < 3; ++k) host_dir_table(8 << k, g_na_host + kNaTabOff[k]);
+        e = hipMemcpy(ptr, g_na_host, sizeof g_na_host, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return note_error(e, __FILE__, __LINE__);
+        g_na_ptr[dev] = (unsigned char *)ptr;
+    }
+    *out = g_na_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" wfpg_status guide_sample_noalloc(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
+                                            uint32_t bounce, const wfpg_opts *opts, float *dir_out,
+                                            float *pdf_out, void *hip_stream)
+{
+    if (!svo || n < 0 || !valid_opts(opts) || (n > 0 && (!pos || !dir_out || !pdf_out)))
+        return WFPG_EINVAL;
+    if (opts->mode != 0) return WFPG_EUNSUPPORTED;   // the learned form keeps working buffers
+    if (n == 0) return WFPG_OK;
+    unsigned char *sp = nullptr;
+    const hipError_t e = noalloc_scratch(&sp);
+    if (e != hipSuccess) return from_hip(e);
+    GuideArgs a = base_args(svo, opts, false);
+    const int k = opts->N == 8 ? 0 : (opts->N == 16 ? 1 : 2);
+    a.dirtab = reinterpret_cast<const float *>(sp) + kNaTabOff[k];
+    a.queue_ctr = reinterpret_cast<unsigned long long *>(sp + kNaCounterOff);   // reset by the launch
+    a.pos = pos;
+    a.n = n;
+    a.seed = seed;
+    a.bounce = bounce;
+    a.dir_out = dir_out;
+    a.pdf_out = pdf_out;
+    return from_hip(launch_guide(svo, opts->N, MODE_SAMPLE, a, choose_tile(svo, opts->N),
+                                 (hipStream_t)hip_stream));
+}
 
 namespace wfpg {
 
