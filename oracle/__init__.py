@@ -97,6 +97,8 @@ def lib():
             "orc_nn_resolutions": (None, [vp, vp]),
             "orc_nn_forward": (None, [vp, vp, vp, vp, i64, i32, vp, vp]),
             "orc_nn_grad": (C.c_double, [vp, vp, vp, vp, vp, i64, i32, vp]),
+            "orc_nn_inputs": (None, [vp, vp, vp, vp, i64, i32, vp]),
+            "orc_nn_parity_bounds": (None, [vp, vp, vp, vp, vp, i64, C.c_double, vp, vp]),
             "orc_kl_rows": (None, [vp, vp, i64, vp]),
             "orc_nn_encode_info": (None, [vp, vp, vp, vp]),
         }
@@ -536,6 +538,31 @@ def nn_grad(params, cfg: NNCfg, pos, nrm, target, mode: int = 0):
     loss = lib().orc_nn_grad(_p(params), C.byref(cfg), _p(pos), _p(nrm), _p(target),
                              pos.shape[1], mode, _p(g))
     return float(loss), g
+
+
+def nn_parity_bounds(params, cfg: NNCfg, pos, nrm, target=None, inv_b: float = 1.0):
+    """Bounds of the GPU's arithmetic against the BF16-faithful mode (see
+    orc_nn_parity_bounds): the relative bound of every probability (n, 256)
+    and, with a target, the radius around the mode-1 gradient (batch scale
+    inv_b) that each gradient element must lie within."""
+    params = np.ascontiguousarray(params, np.float32)
+    pos, nrm = _soa(pos), _soa(nrm)
+    n = pos.shape[1]
+    pe = np.zeros((n, 256))
+    t = None if target is None else np.ascontiguousarray(target, np.float64)
+    gr = np.zeros(nn_num_params(cfg)) if t is not None else None
+    lib().orc_nn_parity_bounds(_p(params), C.byref(cfg), _p(pos), _p(nrm), None if t is None else _p(t), n,
+                               float(inv_b), _p(pe), None if gr is None else _p(gr))
+    return pe, gr
+
+
+def nn_inputs(params, cfg: NNCfg, pos, nrm, mode: int = 1):
+    """The network's input rows (n x 35): encoded features, then the normal."""
+    params = np.ascontiguousarray(params, np.float32)
+    pos, nrm = _soa(pos), _soa(nrm)
+    x = np.zeros((pos.shape[1], 35))
+    lib().orc_nn_inputs(_p(params), C.byref(cfg), _p(pos), _p(nrm), pos.shape[1], mode, _p(x))
+    return x
 
 
 def kl_rows(p, q) -> np.ndarray:

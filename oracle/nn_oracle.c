@@ -295,3 +295,278 @@ void orc_nn_encode_info(const orc_nn_cfg *c, const float *p, uint32_t *idx, doub
     memcpy(idx, ei.idx, sizeof ei.idx);
     memcpy(w, ei.w, sizeof ei.w);
 }
+
+/* Network inputs (n x 35: the 32 encoded features, then the normal) in the
+ * given mode (tests). */
+void orc_nn_inputs(const float *par, const orc_nn_cfg *c, const float *pos, const float *nrm, int64_t n,
+                   int32_t mode, double *x)
+{
+    int32_t res[NN_L];
+    orc_nn_resolutions(c, res);
+    fwd_state *s = malloc(sizeof(fwd_state));
+    for (int64_t i = 0; i < n; i++) {
+        float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        float q[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
+        forward_one(par, res, c, p, q, mode, s);
+        for (int k = 0; k < NN_IN; k++) x[i * NN_IN + k] = s->x[k];
+    }
+    free(s);
+}
+
+/*
+ * Parity bounds of the GPU's arithmetic against the BF16-faithful mode
+ * (mode 1), for element-wise comparison. Both sides round the same
+ * quantities to BF16 at the same points, but the GPU sums its products in
+ * FP32 (matrix cores, in an order of their own) where this oracle sums in
+ * FP64. Every FP32 sum of K terms is taken to lie within 2 K u sum |terms| of
+ * its exact value (u = 2^-24; first order, any order of the additions; the
+ * factor 2 also covers an accumulation that rounds toward zero). Where such
+ * an interval contains a BF16 rounding boundary (or, before a ReLU, zero),
+ * the GPU may round to another BF16 value than the oracle ("flip"). The
+ * bounds follow every value of the network as an interval centred on the
+ * oracle's own mode-1 value: the radius of a sum is the sum of its terms'
+ * radii (|w| r for a weight times an interval, |a| r_b + r_a |b| + r_a r_b for
+ * a product of intervals) plus the accumulation bound; a BF16 rounding maps
+ * [v - r, v + r] to the BF16 values it may round to, the radius the larger
+ * distance of those from the oracle's rounded value; an ambiguous ReLU mask
+ * widens a gradient interval to contain 0.
+ *  - pe[i][b]: bound of |p_gpu - p| / p for every bin (logit radii, the
+ *    shift by the maximum, expf within 2 ulp, the FP32 sum of 256 terms,
+ *    the division).
+ *  - gr[k] (given target, batch scale inv_b): radius of the interval around
+ *    the oracle's mode-1 gradient that the GPU's gradient lies in: the sum
+ *    over the rows of each contribution's radius, plus 2 m u sum |terms| for
+ *    the FP32 sum of its m terms (rows for the MLP; rows times trilinear
+ *    corners for the table). The logit gradient is (p - t) inv_b with p's
+ *    bound and the target renormalized in FP32 (16 u).
+ * Rows beyond first-order validity are not singled out: all bounds are
+ * first order in u (terms of order u^2 and of the squared radii dropped
+ * except in products of intervals).
+ */
+#define ORC_U (1.0 / 16777216.0)
+
+typedef struct {
+    const float *par;
+    const orc_nn_cfg *c;
+    int32_t res[NN_L];
+    const float *W[5];
+    int64_t woff[5], boff[5], toff;
+    uint64_t T;
+} netv;
+
+static void netv_init(netv *v, const float *par, const orc_nn_cfg *c)
+{
+    int fin[5] = {NN_IN, NN_H, NN_H, NN_H, NN_H}, fout[5] = {NN_H, NN_H, NN_H, NN_H, NN_OUT};
+    int64_t off = 0;
+    v->par = par;
+    v->c = c;
+    orc_nn_resolutions(c, v->res);
+    for (int k = 0; k < 5; k++) {
+        v->woff[k] = off; v->W[k] = par + off; off += (int64_t)fout[k] * fin[k];
+        v->boff[k] = off; off += fout[k];
+    }
+    v->toff = off;
+    v->T = (uint64_t)1 << c->log2_table;
+}
+
+/* BF16 rounding of an FP32 value within [v - r, v + r] (v the oracle's
+ * value): the radius around bf16(v) of the values it may take. */
+static double bf16_radius(double v, double r, int relu)
+{
+    double lo = v - r, hi = v + r, own = v;
+    if (relu) {
+        lo = lo > 0.0 ? lo : 0.0;
+        hi = hi > 0.0 ? hi : 0.0;
+        own = own > 0.0 ? own : 0.0;
+    }
+    const double c = (double)bf16r((float)own);
+    const double a = c - (double)bf16r((float)lo), b = (double)bf16r((float)hi) - c;
+    return a > b ? a : b;
+}
+
+typedef struct {
+    double x[NN_IN];
+    double h[4][NN_H], hr[4][NN_H];   /* mode-1 activations and their radii */
+    double a[4][NN_H];                /* mode-1 pre-activations */
+    double p[NN_OUT], pe[NN_OUT];
+    enc_info ei;
+} ival_state;
+
+static void fwd_ival(const netv *v, const float *p, const float *q, ival_state *s)
+{
+    const double u = ORC_U;
+    const int fin[5] = {NN_IN, NN_H, NN_H, NN_H, NN_H};
+    encode(p, v->res, v->c, v->par + v->toff, 1, s->x, &s->ei);   /* the kernels' FP32 order: exact */
+    for (int k = 0; k < 3; k++) s->x[2 * NN_L + k] = (double)bf16r(q[k]);
+    static const double zero[NN_H] = {0};
+    const double *in = s->x, *inr = zero;
+    for (int k = 0; k < 4; k++) {
+        for (int j = 0; j < NN_H; j++) {
+            const double b = (double)v->par[v->boff[k] + j];
+            double acc = b, rad = 0.0, sa = fabs(b);
+            for (int i = 0; i < fin[k]; i++) {
+                const double w = wv(v->W[k], (int64_t)j * fin[k] + i, 1);
+                acc += w * in[i];
+                rad += fabs(w) * inr[i];
+                sa += fabs(w) * (fabs(in[i]) + inr[i]);
+            }
+            rad += 2.0 * (64 + 1) * u * sa;   /* padded fan-in 64, plus the bias */
+            s->a[k][j] = acc;
+            s->h[k][j] = (double)bf16r((float)(acc > 0.0 ? acc : 0.0));
+            s->hr[k][j] = bf16_radius(acc, rad, 1);
+        }
+        in = s->h[k];
+        inr = s->hr[k];
+    }
+    double z[NN_OUT], zr[NN_OUT], zmax = -1e300, rmax = 0.0;
+    for (int j = 0; j < NN_OUT; j++) {
+        const double b = (double)v->par[v->boff[4] + j];
+        double acc = b, rad = 0.0, sa = fabs(b);
+        for (int i = 0; i < NN_H; i++) {
+            const double w = wv(v->W[4], (int64_t)j * NN_H + i, 1);
+            acc += w * s->h[3][i];
+            rad += fabs(w) * s->hr[3][i];
+            sa += fabs(w) * (fabs(s->h[3][i]) + s->hr[3][i]);
+        }
+        z[j] = acc;
+        zr[j] = rad + 2.0 * (64 + 1) * u * sa;
+        if (acc > zmax) zmax = acc;
+        if (zr[j] > rmax) rmax = zr[j];
+    }
+    double sum = 0.0;
+    for (int j = 0; j < NN_OUT; j++) { s->p[j] = exp(z[j] - zmax); sum += s->p[j]; }
+    for (int j = 0; j < NN_OUT; j++) {
+        s->p[j] /= sum;
+        /* ln(p'/p) within zr_j + max zr (the softmax of perturbed logits),
+         * plus the FP32 shift, expf, sum and division */
+        const double d = zr[j] + rmax + u * fabs(z[j] - zmax) + (4.0 + 2.0 * NN_OUT + 2.0) * u;
+        s->pe[j] = expm1(d);
+    }
+}
+
+/* Radii of one row's contributions to every parameter's gradient: mr (MLP
+ * parameters, by index), tr and tc (table contributions of the row's
+ * [level][corner][feature]: radius and |centre|), and ma, |centre| + radius of
+ * each MLP contribution (for the accumulation bound). */
+static void bwd_ival(const netv *v, const ival_state *s, const double *t, double inv_b, double *mr, double *ma,
+                     double *tr, double *tc)
+{
+    const double u = ORC_U;
+    const int fin[5] = {NN_IN, NN_H, NN_H, NN_H, NN_H};
+    double dc[NN_OUT], dr[NN_OUT];
+    for (int j = 0; j < NN_OUT; j++) {
+        const double g = (s->p[j] - t[j]) * inv_b;
+        const double eg = (s->pe[j] * s->p[j] + 16.0 * u * t[j] + u * fabs(s->p[j] - t[j])) * inv_b + u * fabs(g);
+        mr[v->boff[4] + j] = eg;   /* the bias takes the unrounded FP32 value */
+        ma[v->boff[4] + j] = fabs(g) + eg;
+        dc[j] = (double)bf16r((float)g);
+        dr[j] = bf16_radius(g, eg, 0);
+        for (int k2 = 0; k2 < NN_H; k2++) {
+            const double hc = s->h[3][k2], hr = s->hr[3][k2];
+            const int64_t k = v->woff[4] + (int64_t)j * NN_H + k2;
+            mr[k] = fabs(dc[j]) * hr + dr[j] * fabs(hc) + dr[j] * hr;
+            ma[k] = fabs(dc[j] * hc) + mr[k];
+        }
+    }
+    double gc[NN_H], grd[NN_H];   /* gradient of a layer's input: centre, radius */
+    for (int k2 = 0; k2 < NN_H; k2++) {
+        double c = 0.0, r = 0.0, sa = 0.0;
+        for (int j = 0; j < NN_OUT; j++) {
+            const double w = wv(v->W[4], (int64_t)j * NN_H + k2, 1);
+            c += w * dc[j];
+            r += fabs(w) * dr[j];
+            sa += fabs(w) * (fabs(dc[j]) + dr[j]);
+        }
+        gc[k2] = c;
+        grd[k2] = r + 2.0 * NN_OUT * u * sa;
+    }
+    for (int k = 3; k >= 0; k--) {
+        double ac[NN_H], ar[NN_H];
+        for (int j = 0; j < NN_H; j++) {
+            const int on = s->h[k][j] > 0.0;
+            const int sure = s->hr[k][j] == 0.0 || (on && s->h[k][j] - s->hr[k][j] > 0.0);
+            const double c = on ? gc[j] : 0.0;
+            const double r = sure ? (on ? grd[j] : 0.0) : fabs(gc[j]) + grd[j];   /* mask may differ */
+            mr[v->boff[k] + j] = r;   /* unrounded FP32 */
+            ma[v->boff[k] + j] = fabs(c) + r;
+            ac[j] = (double)bf16r((float)c);
+            ar[j] = bf16_radius(c, r, 0);
+        }
+        const double *in = k == 0 ? s->x : s->h[k - 1];
+        for (int j = 0; j < NN_H; j++)
+            for (int i = 0; i < fin[k]; i++) {
+                const double ir = k == 0 ? 0.0 : s->hr[k - 1][i];
+                const int64_t kk = v->woff[k] + (int64_t)j * fin[k] + i;
+                mr[kk] = fabs(ac[j]) * ir + ar[j] * fabs(in[i]) + ar[j] * ir;
+                ma[kk] = fabs(ac[j] * in[i]) + mr[kk];
+            }
+        for (int i = 0; i < fin[k]; i++) {
+            double c = 0.0, r = 0.0, sa = 0.0;
+            for (int j = 0; j < NN_H; j++) {
+                const double w = wv(v->W[k], (int64_t)j * fin[k] + i, 1);
+                c += w * ac[j];
+                r += fabs(w) * ar[j];
+                sa += fabs(w) * (fabs(ac[j]) + ar[j]);
+            }
+            gc[i] = c;
+            grd[i] = r + 2.0 * NN_H * u * sa;
+        }
+    }
+    for (int l = 0; l < NN_L; l++)
+        for (int q = 0; q < 8; q++)
+            for (int f = 0; f < NN_F; f++) {
+                const int k = (l * 8 + q) * NN_F + f;
+                const double w = fabs(s->ei.w[l][q]);
+                const double c = w * fabs(gc[2 * l + f]);
+                tr[k] = w * grd[2 * l + f] + u * (c + w * grd[2 * l + f]);   /* FP32 product */
+                tc[k] = c;
+            }
+}
+
+void orc_nn_parity_bounds(const float *par, const orc_nn_cfg *c, const float *pos, const float *nrm,
+                          const double *target, int64_t n, double inv_b, double *pe, double *gr)
+{
+    netv v;
+    netv_init(&v, par, c);
+    const int64_t mlp = v.toff, np = orc_nn_num_params(c);
+    const int64_t ntab = (int64_t)NN_L * (int64_t)v.T * NN_F;
+    const int grad = target && gr;
+    double *R = NULL, *A = NULL, *mr = NULL, *ma = NULL;
+    int64_t *cnt = NULL;
+    if (grad) {
+        R = calloc((size_t)np, sizeof(double));
+        A = calloc((size_t)np, sizeof(double));
+        cnt = calloc((size_t)ntab, sizeof(int64_t));
+        mr = malloc(sizeof(double) * (size_t)mlp);
+        ma = malloc(sizeof(double) * (size_t)mlp);
+    }
+    ival_state *s = malloc(sizeof(ival_state));
+    for (int64_t i = 0; i < n; i++) {
+        const float p[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        const float q[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
+        fwd_ival(&v, p, q, s);
+        if (pe)
+            for (int j = 0; j < NN_OUT; j++) pe[i * NN_OUT + j] = s->pe[j];
+        if (!grad) continue;
+        double tr[NN_L * 8 * NN_F], tc[NN_L * 8 * NN_F];
+        bwd_ival(&v, s, target + i * NN_OUT, inv_b, mr, ma, tr, tc);
+        for (int64_t k = 0; k < mlp; k++) { R[k] += mr[k]; A[k] += ma[k]; }
+        for (int l = 0; l < NN_L; l++)
+            for (int qq = 0; qq < 8; qq++)
+                for (int f = 0; f < NN_F; f++) {
+                    const int k = (l * 8 + qq) * NN_F + f;
+                    const int64_t e = ((int64_t)l * (int64_t)v.T + s->ei.idx[l][qq]) * NN_F + f;
+                    R[mlp + e] += tr[k];
+                    A[mlp + e] += tc[k] + tr[k];
+                    cnt[e] += 1;
+                }
+    }
+    if (grad) {
+        for (int64_t k = 0; k < np; k++) {
+            const double m = k < mlp ? (double)n : (double)cnt[k - mlp];
+            gr[k] = R[k] + 2.0 * m * ORC_U * A[k];
+        }
+        free(R); free(A); free(cnt); free(mr); free(ma);
+    }
+    free(s);
+}

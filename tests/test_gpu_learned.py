@@ -1,16 +1,16 @@
 """GPU tests of the learned stand-in for the march, through the C ABI.
 
 * The BF16 MFMA forward pass and the backward pass (gradients of the mean
-  cross-entropy) agree with the BF16-faithful CPU oracle, which rounds to BF16
-  at the same points (table, inputs, weights, hidden activations, logit and
-  pre-activation gradients) but accumulates in FP64. The GPU accumulates BF16
-  products in FP32 inside the matrix cores, in another order, so a value that
-  lies within an FP32 rounding of a BF16 rounding boundary may round to the
-  neighbouring BF16 value (2^-8 relative) on one side only. The bars below
-  bound the effect of a few such flips, not of a wrong term: a dropped term,
-  a transposed operand or a wrong index moves the compared quantities by
-  orders of magnitude more (the same tests against the FP64 oracle would
-  fail their bars only by the BF16 rounding itself, which is larger).
+  cross-entropy) agree element by element with the BF16-faithful CPU oracle,
+  which rounds to BF16 at the same points (table, inputs, weights, hidden
+  activations, logit and pre-activation gradients) but accumulates in FP64.
+  The GPU accumulates BF16 products in FP32 inside the matrix cores, in
+  another order, so a value within its FP32 accumulation error of a BF16
+  rounding boundary may round to the neighbouring BF16 value on one side
+  only. The oracle derives, for every probability and every gradient
+  element, the bound of the FP32 accumulations plus every such flip they
+  allow (tests/test_oracle_nn_bounds.py pins it against an FP32 emulation in
+  random orders); the measured errors are recorded against it.
 * Sampling from the network returns the pdf of the bin it sampled.
 * Training lowers the KL to the march; the judge falls back to the march,
   bit for bit, when the probes' KL exceeds the bound.
@@ -20,6 +20,7 @@ import math
 import numpy as np
 import pytest
 
+import bars
 import nn_params
 import synth
 
@@ -75,6 +76,9 @@ def small_model(w, torch_dev, rects):
 
 # ------------------------------------------------------------- forward ----
 def test_forward_matches_bf16_oracle(orc, w, torch_dev, box):
+    """Every probability within the oracle's derived bound of the
+    BF16-faithful forward (FP32 accumulation plus every BF16 flip it allows,
+    propagated to the logits and through the softmax)."""
     cfg = orc.nn_cfg(**SMALL)
     n_par = orc.nn_num_params(cfg)
     g = small_model(w, torch_dev, box["rects"])
@@ -85,15 +89,15 @@ def test_forward_matches_bf16_oracle(orc, w, torch_dev, box):
     pos, nrm = box["pos"], box["nrm"]          # 300 rows: 4 full 64-row tiles and a ragged one
     prob = w.nn_forward(g, dev(torch_dev, pos), dev(torch_dev, nrm)).cpu().numpy().astype(np.float64)
     p1, _ = orc.nn_forward(params, cfg, pos, nrm, mode=1)
-    p0, _ = orc.nn_forward(params, cfg, pos, nrm, mode=0)
+    pe, _ = orc.nn_parity_bounds(params, cfg, pos, nrm)
     assert np.allclose(prob.sum(1), 1, atol=1e-5)
-    kl_gpu = orc.kl_rows(p1, prob)
-    kl_ref = orc.kl_rows(p0, p1)           # the BF16 rounding itself
-    # a handful of one-ulp BF16 flips moves the KL by far less than the rounding does
-    assert kl_gpu.max() < 1e-5, kl_gpu.max()
-    assert kl_gpu.mean() < 0.05 * kl_ref.mean(), (kl_gpu.mean(), kl_ref.mean())
     rel = np.abs(prob - p1) / p1
-    assert np.median(rel) < 1e-4 and rel.max() < 2e-2, (np.median(rel), rel.max())
+    bars.record("nn forward rel (median)", np.median(rel))
+    bars.record("nn forward rel / bound", (rel / pe).max(), 1.0)
+    bars.record("nn forward rel", rel.max(), 1e-3)
+    assert (rel <= pe).all(), (rel / pe).max()
+    kl_gpu = orc.kl_rows(p1, prob)
+    assert kl_gpu.max() < 1e-5, kl_gpu.max()
 
 
 def test_forward_pinned_structure(orc, w, torch_dev, box):
@@ -125,30 +129,47 @@ def test_forward_pinned_structure(orc, w, torch_dev, box):
 
 # ------------------------------------------------------------ backward ----
 def test_gradient_matches_bf16_oracle(orc, w, torch_dev, box):
+    """Every gradient element within the oracle's derived bound around the
+    BF16-faithful gradient: FP32 accumulation over the rows and within the
+    products, plus every BF16 flip the accumulations allow (forward
+    activations, logit and hidden gradients, ReLU masks), propagated as
+    intervals. The bound is tight at the output layer and loose towards the
+    input, where worst-case flips compound; the per-block norms of the
+    difference are therefore also held against the whole BF16 rounding
+    effect, which a dropped term or a transposed operand exceeds by far."""
     cfg = orc.nn_cfg(**SMALL)
     n_par = orc.nn_num_params(cfg)
     g = small_model(w, torch_dev, box["rects"])
     rng = np.random.default_rng(6)
     params = nn_params.random_params(n_par, rng)
     w.nn_set_params(g, params)
-    pos, nrm = box["pos"], box["nrm"]
-    t = rng.random((pos.shape[1], 256)) ** 4
-    t /= t.sum(1, keepdims=True)
-    loss, grad = w.nn_grad(g, dev(torch_dev, pos), dev(torch_dev, nrm), dev(torch_dev, t.astype(np.float32)))
+    B = 256   # rows; a power of two, so the batch scale 1/B is exact in FP32
+    pos, nrm = np.ascontiguousarray(box["pos"][:, :B]), np.ascontiguousarray(box["nrm"][:, :B])
+    t32 = (rng.random((B, 256)) ** 4).astype(np.float32)
+    t32 /= t32.sum(1, keepdims=True)
+    t = t32.astype(np.float64)
+    t /= t.sum(1, keepdims=True)             # the kernels renormalize the target rows in FP32
+    loss, grad = w.nn_grad(g, dev(torch_dev, pos), dev(torch_dev, nrm), dev(torch_dev, t32))
     grad = grad.cpu().numpy().astype(np.float64)
     l1, g1 = orc.nn_grad(params, cfg, pos, nrm, t, mode=1)
     l0, g0 = orc.nn_grad(params, cfg, pos, nrm, t, mode=0)
+    _, gr = orc.nn_parity_bounds(params, cfg, pos, nrm, target=t, inv_b=1.0 / B)
     assert abs(loss - l1) < 1e-5 * abs(l1), (loss, l1)
+    d = np.abs(grad - g1)
+    bars.record("nn gradient |diff| / bound", (d / np.maximum(gr, 1e-300)).max(), 1.0)
+    assert (d <= gr * (1 + 1e-9) + 1e-300).all(), (d / np.maximum(gr, 1e-300)).max()
     lay = nn_params.layout(n_par)
-    report = {}
     for name, (a, m) in lay.items():
-        d = np.linalg.norm(grad[a:a + m] - g1[a:a + m])
-        ref = np.linalg.norm(g0[a:a + m] - g1[a:a + m])
-        nrm1 = np.linalg.norm(g1[a:a + m])
-        report[name] = (d / nrm1, ref / nrm1)
-        # FP32-vs-FP64 accumulation plus a few BF16 flips, against the
-        # whole BF16 rounding (ref) and the gradient's own size
-        assert d <= 2e-2 * nrm1 and d <= 0.5 * ref + 1e-6 * nrm1, (name, report[name])
+        gg, ref = g1[a:a + m], g0[a:a + m]
+        big = np.abs(gg) > 1e-3 * np.abs(gg).max()
+        rel = d[a:a + m][big] / np.abs(gg[big])
+        bars.record(f"nn gradient {name} rel (median)", np.median(rel), 1e-3)
+        bars.record(f"nn gradient {name} rel (max)", rel.max())
+        bars.record(f"nn gradient {name} bound rel (median)", np.median(gr[a:a + m][big] / np.abs(gg[big])))
+        assert np.median(rel) <= 1e-3, (name, np.median(rel))   # the typical element: no flip reaches it
+        nd = np.linalg.norm(d[a:a + m])
+        nref = np.linalg.norm(ref - gg)
+        assert nd <= 0.5 * nref + 1e-6 * np.linalg.norm(gg), (name, nd, nref)
     # the table gradient touches exactly the corners of the encoded cells
     a, m = lay["table"]
     assert np.array_equal(grad[a:a + m] != 0, g1[a:a + m] != 0)
@@ -381,3 +402,7 @@ def test_forward_full_size_configuration(orc, w, torch_dev):
     p1, _ = orc.nn_forward(params, cfg, pos, nrm, mode=1)
     kl = orc.kl_rows(p1, prob)
     assert kl.max() < 1e-5, kl.max()
+    pe, _ = orc.nn_parity_bounds(params, cfg, pos, nrm)
+    rel = np.abs(prob - p1) / p1
+    bars.record("nn forward full size rel / bound", (rel / pe).max(), 1.0)
+    assert (rel <= pe).all(), (rel / pe).max()
