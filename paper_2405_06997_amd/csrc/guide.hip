@@ -392,6 +392,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     // a pointer select, which measured slower)
     const uint32_t *gbits = reinterpret_cast<const uint32_t *>(sv.bits);   // 32-bit words
     auto bits = [gbits](int, uint32_t wi) -> uint32_t { return gbits[wi]; };
+    const uint64_t *gbits64 = sv.bits;
+    auto bits64 = [gbits64](uint32_t wi) -> uint64_t { return gbits64[wi]; };
 
     // wave-uniform stream and slot state
     int64_t chunk_next = 0;
@@ -501,7 +503,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             // masked out of the rest
 #pragma unroll
             for (int m = 0; m < kMicro; ++m) {
-                res = core::micro_step(st, D, bits, 5, vis);
+                res = core::micro_step(st, D, bits64, 5, vis);
                 if (res != core::STEP_CONTINUE) break;
             }
             if (res == core::STEP_CONTINUE && (iters += kMicro) >= core::kMaxTests) {

@@ -37,7 +37,7 @@ constexpr int kFine = 30;
 // take one 64-bit word each, level l >= 3 takes 8^l / 64 words).
 WFPG_HD uint32_t woff(int l)
 {
-    const uint32_t t = 3u * (uint32_t)l - 9u;   // wraps for l < 3, where l is returned
+    const uint32_t t = 3u * ((uint32_t)l & 15u) - 9u;   // wraps for l < 3, where l is returned
     const uint32_t f = 3u + ((0x09249249u & ((1u << (t & 31u)) - 1u)) << 3);
     return l <= 3 ? (uint32_t)l : f;
 }
@@ -155,14 +155,24 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
     }
 }
 
-// One occupancy test per call, with no branch that depends on the lane: every
-// lane computes the exit step of PH_ADVANCE and both candidate cells (the
-// ancestor of PH_PATH, the child of PH_DESCEND) and keeps what its phase
-// selects, so a wave whose lanes sit in different phases runs one straight
-// sequence with every lane active instead of each phase's code under its own
-// lane mask. On STEP_HIT the hit is hit_of(s, D).
-template <class Bits>
-WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, int &vis)
+// One 64-bit occupancy load per call, with no branch that depends on the
+// lane: every lane computes the exit step of PH_ADVANCE and both candidate
+// cells (the ancestor of PH_PATH, the child of PH_DESCEND) and keeps what its
+// phase selects, so a wave whose lanes sit in different phases runs one
+// straight sequence with every lane active instead of each phase's code under
+// its own lane mask.
+//
+// A 64-bit word of level L (the cells of one level-(L-2) cell, Morton order)
+// answers three levels at once: level L-2 (the word is not zero), level L-1
+// (one of its bytes) and level L (one bit). A path descent therefore tests
+// up to three ancestors of the entered cell per call -- the window [l, T],
+// T = min(l + 2, lvl) -- and stops at the first empty one, exactly the tests
+// of the top-down walk one at a time; a child descent tests one level. The
+// node tests counted are those of the walk (levels >= count_from).
+// bits64(wi) returns 64-bit word wi of the concatenated bitmaps. On STEP_HIT
+// the hit is hit_of(s, D).
+template <class Bits64>
+WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_from, int &vis)
 {
     // PH_ADVANCE: the first exit crossing of the current cell, through its
     // upper face on every axis. An axis the ray does not cross (|q| = 0) has
@@ -199,8 +209,6 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const int l = adv ? al : s.l;
     const bool path = adv || s.phase == PH_PATH;
 
-    // PH_PATH candidate: the entered cell's ancestor at level l (l <= lvl)
-    const uint32_t pk = s.key >> ((3 * (s.lvl - l)) & 31);
     // PH_DESCEND candidate: the child the ray is in just after the current
     // crossing tn/td. Along axis j the mid-plane M counts as crossed iff its
     // parameter is smaller, or equal with j not above ta: with d = M - O,
@@ -225,31 +233,51 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits &bits, int count_from, i
     const bool u2 = (int64_t)nd2 * td + (int64_t)((uint64_t)s.tn * s.aq2 + k2) > 0;
     const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
 
-    // the cell to test (a lane that left the cube tests the root instead: its
-    // stepped key and level are out of range), its key back in the original frame
-    const int tl = miss ? 0 : (path ? l : s.lvl + 1);
-    const uint32_t tk = miss ? 0u : (path ? pk : dk);
-    vis += (!miss && tl >= count_from) ? 1 : 0;
-    const bool occ = occupied(bits, tl, tk ^ (s.flip >> (kFine - 3 * tl)));
+    // The levels tested: the window [ws, T] of the path (ancestors of the
+    // entered cell at level lvl, l <= lvl), or the child's level. A lane that
+    // left the cube tests the root instead (its stepped key is out of range).
+    // Levels are < 16: masked so that the products by 3 stay 24-bit ones.
+    const int Tp = l + 2 < s.lvl ? l + 2 : s.lvl;
+    const int T = (miss ? 0 : (path ? Tp : s.lvl + 1)) & 15;
+    const int ws = miss ? 0 : (path ? l : T);
+    const uint32_t tk = miss ? 0u : (path ? s.key >> ((3 * ((s.lvl - Tp) & 15)) & 31) : dk);
+    // the word of level wl = max(T, 2) holding the cell (original frame;
+    // level D itself on SVOs of depth 1), read as two 32-bit halves
+    const int w2 = D < 2 ? D : 2;
+    const int wl = (T < w2 ? w2 : T) & 15;
+    const uint32_t ko = (tk ^ (s.flip >> (kFine - 3 * T))) << (3 * ((wl - T) & 3));
+    const uint64_t W = bits64(woff(wl) + (ko >> 6));
+    const uint32_t wlo = (uint32_t)W, whi = (uint32_t)(W >> 32);
+    const uint32_t wh = (ko & 32u) ? whi : wlo;                   // the half holding the cell
+    const bool o0 = (wlo | whi) != 0u;                            // level wl - 2
+    const bool o1 = ((wh >> (ko & 0x18u)) & 0xffu) != 0u;         // level wl - 1
+    const bool o2 = ((wh >> (ko & 31u)) & 1u) != 0u;              // level wl
+    // the first empty level of the window (-1: all occupied)
+    const bool f0 = wl - 2 >= ws && !o0;
+    const bool f1 = wl - 1 >= ws && wl - 1 <= T && !o1;
+    const bool f2 = wl <= T && !o2;
+    const int ee = f0 ? wl - 2 : (f1 ? wl - 1 : (f2 ? wl : -1));
+    const int last = ee >= 0 ? ee : T;
+    const int from = ws > count_from ? ws : count_from;
+    vis += (!miss && last >= from) ? last - from + 1 : 0;
 
-    // Empty: the tested cell is the one to leave next. Occupied: on the path,
-    // the next level down (the entered cell itself: descend from it); in a
-    // descent, the child becomes the cell. A hit is an occupied leaf. The
-    // corner of the new cell: the old corner cut to level tl (an ancestor), or
-    // with the child's half added on each axis (a child); unchanged when the
-    // cell stays.
-    const bool take = !occ || !path;
-    const uint32_t MK = take ? ~((1u << (kFine - tl)) - 1u) : ~0u;
-    const int olvl = s.lvl;
+    // The new cell: on the path the ancestor at the first empty level (the
+    // entered cell itself when the window is all occupied); in a descent the
+    // child. Its corner: the old corner cut to its level, with the child's
+    // half added on each axis for a child.
+    const bool full = ee < 0;
+    const int nl = path ? (full ? s.lvl : ee) : s.lvl + 1;
+    const uint32_t MK = ~((1u << (kFine - nl)) - 1u);
     s.lo0 = (s.lo0 & MK) | (!path & u0 ? half : 0u);
     s.lo1 = (s.lo1 & MK) | (!path & u1 ? half : 0u);
     s.lo2 = (s.lo2 & MK) | (!path & u2 ? half : 0u);
-    s.lvl = take ? tl : olvl;
-    s.key = take ? tk : s.key;
-    s.phase = !occ ? PH_ADVANCE : (path && tl < olvl ? PH_PATH : PH_DESCEND);
-    s.l = tl + 1;
+    s.key = path ? s.key >> ((3 * ((s.lvl - nl) & 15)) & 31) : dk;
+    const bool at_cell = !path || T == s.lvl;   // the window reached the cell itself
+    s.lvl = nl;
+    s.phase = !full ? PH_ADVANCE : (at_cell ? PH_DESCEND : PH_PATH);
+    s.l = T + 1;
     if (miss) return STEP_MISS;
-    return occ && tl == D ? STEP_HIT : STEP_CONTINUE;
+    return full && at_cell && nl == D ? STEP_HIT : STEP_CONTINUE;
 }
 
 // The hit of a march whose last step returned STEP_HIT: the crossing axis, the
@@ -265,8 +293,8 @@ WFPG_HD Hit hit_of(const MicroState &s, int D)
 
 // Whole march: 1 on a hit, 0 on a miss, -1 if the iteration bound is
 // exceeded (never expected).
-template <class Bits>
-WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits &bits,
+template <class Bits, class Bits64>
+WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits &bits, const Bits64 &bits64,
                   int count_from, int &vis, Hit &h)
 {
     MicroState s;
@@ -279,7 +307,7 @@ WFPG_HD int march(const uint32_t O[3], int q0, int q1, int q2, int D, const Bits
     const bool occ = occupied(bits, D, ok);
     micro_begin(s, O, ok, occ, aq0, aq1, aq2, sg0, sg1, sg2, D, count_from, vis);
     for (int it = 0; it < kMaxTests; ++it) {
-        const int st = micro_step(s, D, bits, count_from, vis);
+        const int st = micro_step(s, D, bits64, count_from, vis);
         if (st == STEP_HIT) {
             h = hit_of(s, D);
             return 1;

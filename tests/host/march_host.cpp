@@ -15,6 +15,7 @@ extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, con
     const int NN = N * N;
     const uint32_t *bits32 = reinterpret_cast<const uint32_t *>(bits);   // 32-bit words
     auto load = [&](int, uint32_t wi) -> uint32_t { return bits32[wi]; };
+    auto load64 = [&](uint32_t wi) -> uint64_t { return bits[wi]; };
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t i = 0; i < n; ++i) {
         uint32_t O[3];
@@ -24,7 +25,7 @@ extern "C" void host_debug_march(const uint64_t *bits, const uint32_t *rank, con
             int vis = 0;
             Hit h = {-1, 0u, 0u};
             const int res = march(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), D,
-                                  load, 5, vis, h);
+                                  load, load64, 5, vis, h);
             int32_t *o = out + ((int64_t)i * NN + b) * 8;
             o[0] = res > 0;
             o[1] = res > 0 ? h.axis : -1;
@@ -59,6 +60,7 @@ extern "C" void host_march_dirs(const uint64_t *bits, int D, const float *pos, i
 {
     const uint32_t *bits32 = reinterpret_cast<const uint32_t *>(bits);
     auto load = [&](int, uint32_t wi) -> uint32_t { return bits32[wi]; };
+    auto load64 = [&](uint32_t wi) -> uint64_t { return bits[wi]; };
     for (int64_t i = 0; i < n; ++i) {
         uint32_t O[3];
         for (int k = 0; k < 3; ++k) O[k] = quantize_pos(pos[k * n + i]);
@@ -66,8 +68,8 @@ extern "C" void host_march_dirs(const uint64_t *bits, int D, const float *pos, i
             const float *d = dirs + 3 * b;
             int vis = 0;
             Hit h = {-1, 0u, 0u};
-            const int res = march(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), D, load, 0, vis,
-                                  h);
+            const int res = march(O, quantize_dir(d[0]), quantize_dir(d[1]), quantize_dir(d[2]), D, load, load64, 0,
+                                  vis, h);
             int64_t *o = out + (i * nd + b) * 4;
             o[0] = res;
             o[1] = res > 0 ? h.axis : -1;
