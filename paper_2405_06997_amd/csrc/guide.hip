@@ -345,6 +345,7 @@ template <int N, int MODE, bool BLUR>
 __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
 {
     constexpr int NN = N * N;
+    constexpr int BPL = NN / 64;
     constexpr int S = guide_slots(N);
     extern __shared__ uint64_t smem[];
     if (a.gate && *a.gate == 0) return;   // uniform: every thread reads the same flag
@@ -354,8 +355,16 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     float *ldir = reinterpret_cast<float *>(smem);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
     constexpr int RW = guide_rec_words(MODE);
+    const int nw = blockDim.x / 64;
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
-    uint32_t *svis = lq + 3 * NN + (size_t)blockDim.x / 64 * S * RW * NN + (size_t)wave * S;
+    uint32_t *svis = lq + 3 * NN + (size_t)nw * S * RW * NN + (size_t)wave * S;
+    // per wave: the bins each slot still has to march, one 64-bit mask per
+    // 64 bins (bit l of mask j: bin 64 j + l), and a 64-entry exchange buffer
+    // through which the hand-out passes bins to idle lanes
+    uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) +
+                      (size_t)wave * S * BPL;
+    uint16_t *xch = reinterpret_cast<uint16_t *>(reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) +
+                                                 (size_t)nw * S * BPL) + (size_t)wave * 64;
     // The per-vertex finalization reads its arguments from an LDS copy: held
     // in scalar registers across the march loop they overflowed the scalar
     // file and were spilled into vector lanes (two lane moves per use); read
@@ -403,12 +412,34 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     int rem[S];                          // bins of the slot not yet finished
 #pragma unroll
     for (int k = 0; k < S; ++k) { vs[k] = -1; rem[k] = 0; }
-    int feed = -1, nxt = NN;             // slot being handed out and its next bin
+    int feed = -1, nxt = BPL;            // slot being handed out and its mask of bins being handed out
     uint32_t F0 = 0, F1 = 0, F2 = 0, Fkey = 0;   // origin and origin-leaf key of the fed vertex
     bool Focc = false;
     // per-lane march state
     int lslot = 0, lbin = -1, vis = 0, iters = 0;
     core::MicroState st;
+
+    // the record of a finished march (res: STEP_HIT or STEP_MISS) of bin b
+    // of slot k whose vertex is v, with its node-test count pv
+    auto finish = [&](const core::MicroState &ms, int res, int k, int b, int64_t v, int pv) {
+        uint32_t *rec = recs + k * RW * NN;
+        const Hit h = res == core::STEP_HIT ? core::hit_of(ms, D) : Hit{-1, 0u, 0u};
+        if constexpr (MODE == MODE_DEBUG) {
+            rec[2 * b] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
+            rec[2 * b + 1] = h.delta;
+            if (a.dbg_visits) a.dbg_visits[(size_t)v * NN + b] = pv;
+        } else {
+            // cone footprint (Eq. 7) decided here: the record is the node it selects
+            uint32_t rv = 0u;
+            if (res == core::STEP_HIT) {
+                const float dsel = ldir[3 * b + h.axis];
+                const int kk = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
+                rv = (1u << (3 * (D - kk))) | (h.key >> (3 * kk));
+            }
+            rec[b] = rv;
+        }
+        if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[k], (uint32_t)pv);
+    };
 
     while (true) {
         // finalize every slot whose bins are all finished
@@ -431,7 +462,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
         // hand out bins to idle lanes
         uint64_t idle = __ballot(lbin < 0);
         while (idle) {
-            if (feed < 0 || nxt >= NN) {
+            if (feed < 0 || nxt >= BPL) {
                 int f = -1;
 #pragma unroll
                 for (int k = 0; k < S; ++k)
@@ -455,23 +486,56 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 const bool oc = core::occupied(bits, D, okey);
                 F0 = uni(O[0]); F1 = uni(O[1]); F2 = uni(O[2]); Fkey = uni(okey);
                 Focc = uni((int)oc) != 0;
-#pragma unroll
-                for (int k = 0; k < S; ++k)
-                    if (k == f) { vs[k] = uni(vi); rem[k] = NN; }
                 if constexpr (MODE == MODE_COUNT) {
                     if (lane == 0) svis[f] = 0u;
                     wave_lds_fence();
                 }
+                // First step of every bin of the new vertex by the whole wave,
+                // whatever ray a lane is marching (about three rays in four end
+                // there: the leaf next to the origin, or out of the cube); the
+                // others are marked for the hand-out.
+                int npend = 0;
+#pragma unroll
+                for (int j = 0; j < BPL; ++j) {
+                    const int b = j * 64 + lane;
+                    const uint32_t w0 = lq[3 * b], w1 = lq[3 * b + 1], w2 = lq[3 * b + 2];
+                    const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
+                    core::MicroState ms;
+                    int pv = 0;
+                    core::micro_begin(ms, O, okey, oc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
+                                      a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, pv);
+                    const int r1 = core::micro_step(ms, D, bits64, 5, pv);
+                    if (r1 != core::STEP_CONTINUE) finish(ms, r1, f, b, vi, pv);
+                    const uint64_t pm = __ballot(r1 == core::STEP_CONTINUE);
+                    if (lane == 0) pmask[f * BPL + j] = pm;
+                    npend += (int)__popcll(pm);
+                }
+                wave_lds_fence();
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    if (k == f) { vs[k] = uni(vi); rem[k] = uni(npend); }
                 feed = f;
                 nxt = 0;
             }
-            const int nidle = (int)__popcll(idle), left = NN - nxt;
+            // the next bins of the feed slot's current mask go to the idle lanes
+            // in order, through the exchange buffer
+            const uint64_t avail = (uint64_t)uni((int64_t)pmask[feed * BPL + nxt]);
+            if (avail == 0ull) {
+                nxt = uni(nxt + 1);
+                continue;
+            }
+            const int nidle = (int)__popcll(idle), left = (int)__popcll(avail);
             const int take = nidle < left ? nidle : left;   // (integer min: the mixed-type min was FP64)
+            const int kr = lanes_below(avail);
+            const bool give = ((avail >> lane) & 1ull) && kr < take;
+            if (give) xch[kr] = (uint16_t)(nxt * 64 + lane);
+            const uint64_t given = __ballot(give);
+            wave_lds_fence();
             const int r = lanes_below(idle);
             const bool mine = ((idle >> lane) & 1ull) && r < take;
             if (mine) {
                 lslot = feed;
-                lbin = nxt + r;
+                lbin = xch[r];
                 const uint32_t O[3] = {F0, F1, F2};
                 const uint32_t w0 = lq[3 * lbin], w1 = lq[3 * lbin + 1], w2 = lq[3 * lbin + 2];
                 const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
@@ -481,7 +545,9 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                                   a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, vis);
             }
             idle &= ~__ballot(mine);
-            nxt = uni(nxt + take);
+            wave_lds_fence();   // the exchange buffer is read before it is written again
+            if (lane == 0) pmask[feed * BPL + nxt] = avail & ~given;
+            wave_lds_fence();
         }
         if (__ballot(lbin >= 0) == 0ull) {
             bool any = false, ready = false;
@@ -513,31 +579,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
         }
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
-            uint32_t *rec = recs + lslot * RW * NN;
-            const Hit h = res == core::STEP_HIT ? core::hit_of(st, D) : Hit{-1, 0u, 0u};
-            if constexpr (MODE == MODE_DEBUG) {
-                rec[2 * lbin] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
-                rec[2 * lbin + 1] = h.delta;
-            } else {
-                // cone footprint (Eq. 7) decided here: the record is the node it selects
-                uint32_t rv = 0u;
-                if (res == core::STEP_HIT) {
-                    const float dsel = ldir[3 * lbin + h.axis];
-                    const int k = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
-                    rv = (1u << (3 * (D - k))) | (h.key >> (3 * k));
-                }
-                rec[lbin] = rv;
-            }
-            if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[lslot], (uint32_t)vis);
-            if constexpr (MODE == MODE_DEBUG) {
-                if (a.dbg_visits) {
-                    int64_t vl = vs[0];
+            int64_t vl = vs[0];
 #pragma unroll
-                    for (int k = 1; k < S; ++k)
-                        if (lslot == k) vl = vs[k];
-                    a.dbg_visits[(size_t)vl * NN + lbin] = vis;
-                }
-            }
+            for (int k = 1; k < S; ++k)
+                if (lslot == k) vl = vs[k];
+            finish(st, res, lslot, lbin, vl, vis);
             lbin = -1;
         }
         if (__ballot(fin)) {
