@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this size before timing (counter calibration)")
-    ap.add_argument("--sections", default="binned,product,extract,learned,batching,precision",
+    ap.add_argument("--sections", default="tiny,stress,binned,product,extract,learned,batching,precision",
                     help="comma-separated extra sections after the headline march step "
                          "(binned, product, extract, learned, batching, precision; empty for none)")
     ap.add_argument("--only-march", action="store_true", help="same as --sections ''")
@@ -161,6 +161,12 @@ def main():
 
     gs_avg = float(np.mean(gs_ms))
     achieved = alg_bytes / (gs_avg * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(dev)
+    acc_avg = float(np.mean(acc_ms))
+    # svo_accumulate: per splat 36 B in + 8 (D - 4) B of occupancy lookups + 12 B
+    # normal + 16 B of atomics (112 B at depth 10); the bottom-up average reads
+    # the leaf accumulators and writes every node's exitance (~214 MB here)
+    acc_alg = 2_000_000 * (36 + 8 * (10 - 4) + 12 + 16) + acc_prop_bytes(st_levels(svo))
     counters = measured_counters(args.N, tile)
     traffic = None if counters is None else counters["bytes_per_launch"]
     out = {
@@ -185,6 +191,10 @@ def main():
         "breakdown_ms": {"svo_accumulate": float(np.mean(acc_ms)), "guide_sample": gs_avg,
                          "wall_per_step": wall / K * 1e3},
         "guide_samples_per_s": n / (gs_avg * 1e-3),
+        "accumulate_roofline": {"bound": "hbm", "kernels": "k_splat + k_prop_leaf + k_prop_inner",
+                                "alg_bytes_per_call": acc_alg, "achieved": acc_alg / (acc_avg * 1e-3) / 1e9,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": acc_alg / (acc_avg * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {
             "bound": "hbm", "kernel": "k_guide<16, SAMPLE>",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -192,6 +202,7 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "traffic_gbs": None if traffic is None else traffic / (gs_avg * 1e-3) / 1e9,
             "node_tests_per_bin": visits / (n * NN), "hit_fraction": hits / (n * NN),
+            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
             # the march is integer-ALU bound: VALU issue beside the logical HBM fraction
             "valu": None if counters is None else {
                 "achieved": counters["valu_wave_instrs_per_launch"] / (gs_avg * 1e-3),
@@ -205,9 +216,15 @@ def main():
         out["cpu_baseline"], orc, ref = cpu_baseline(room, splats, cam, args.N, args.cpu_sample, n, seed=K)
         out["parity"] = parity(d_out, p_out, ref, args.N)
     sections = set() if args.only_march else {x for x in args.sections.split(",") if x}
-    unknown = sections - {"binned", "product", "extract", "learned", "batching", "precision"}
+    unknown = sections - {"tiny", "stress", "binned", "product", "extract", "learned", "batching", "precision"}
     if unknown:
         raise SystemExit(f"unknown sections: {sorted(unknown)}")
+    if "tiny" in sections:
+        log("tiny-box section")
+        out["tiny"] = tiny_section(w, args)
+    if "stress" in sections:
+        log("stress-queue section")
+        out["stress"] = stress_section(w, svo, room, args)
     if "binned" in sections:
         log("binned section")
         out["binned"] = binned_section(w, svo, pos, n, args, gs_avg)
@@ -227,6 +244,108 @@ def main():
         log("precision section")
         out["precision"] = precision_section(w, room, sp, pos, cam, args, orc, tile)
     print(json.dumps(out))
+
+
+def copy_bandwidth(dev):
+    """HBM bandwidth of a plain streaming kernel measured in the same run:
+    torch's copy of 1 GiB (1 GiB read and 1 GiB written), HIP events."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = _timed(lambda: dst.copy_(src), 10, 3)
+    del src, dst
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def st_levels(svo):
+    return svo.level_sizes()
+
+
+def acc_prop_bytes(level_sizes):
+    """Bottom-up averaging: every leaf's two (sum, count) pairs read (16 B) and
+    its FP32 exitance pair written (8 B); every inner node reads its children's
+    pairs, its own normal and theirs (about 8 + 16 B per child) and writes its
+    pair (8 B)."""
+    leaves = level_sizes[-1]
+    inner = sum(level_sizes[:-1])
+    return leaves * (16 + 8) + sum(level_sizes[1:]) * (8 + 16) + inner * 8
+
+
+def tiny_section(w, args):
+    """The tiny Cornell box (depth 6, one exitance splat per leaf side, 4096
+    area-uniform vertices, N = 8): one step (accumulate + guide_sample) timed
+    on the GPU, and the oracle running the same step on all 4096 vertices on
+    the host cores, with the GPU's samples checked against it."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    dev = torch.device("cuda:0")
+    box = synth.cornell_box()
+    D, N = 6, 8
+    o = oracle.SVO(box, D)
+    xyz, em = o.leaf_info()
+    sp = synth.leaf_splats(xyz, o.normals(D), em, D, seed=2)
+    g = w.svo_build(box, D)
+    dsp = [torch.from_numpy(a).to(dev) for a in sp]
+    pos_h, _, _ = synth.area_points(box, 4096, 3)
+    pos = torch.from_numpy(pos_h).to(dev)
+    opts = w.make_opts(N=N)
+    d = torch.empty((3, 4096), device=dev)
+    p = torch.empty((4096,), device=dev)
+
+    def step():
+        w.svo_accumulate(g, *dsp)
+        w.guide_sample(g, pos, opts, seed=9, bounce=0, dir_out=d, pdf_out=p)
+    ms = _timed(step, args.steps, args.warmup)
+    t = time.perf_counter()
+    o.accumulate(*sp)
+    o.propagate()
+    ref = o.guide_sample(pos_h, N, seed=9, bounce=0)
+    t_orc = time.perf_counter() - t
+    dd = d.cpu().numpy().astype(np.float64)
+    pp = p.cpu().numpy().astype(np.float64)
+    uv = oracle.oct_encode_many(dd)
+    gb = np.minimum((uv * N).astype(np.int64), N - 1)
+    same = (gb[0] == ref["bin"][:, 0]) & (gb[1] == ref["bin"][:, 1])
+    band = (ref["margin"] < (4 * math.log2(N) + 3) * 2.0 ** -24).any(1)
+    rel = np.abs(pp[same] - ref["pdf"][same]) / ref["pdf"][same]
+    return {"workload": "Cornell box D=6 (%d leaves), 4096 area-uniform vertices, N=8, one splat per leaf side"
+                        % o.level_size(D),
+            "ms_per_step": ms, "samples_per_s": 4096 / (ms * 1e-3),
+            "oracle": {"seconds": t_orc, "samples_per_s": 4096 / t_orc, "cores": oracle.num_threads(),
+                       "sample": "all 4096 vertices, accumulate + propagate + guide_sample"},
+            "parity": {"same_bin": float(same.mean()), "differing_outside_scan_band": int((~same & ~band).sum()),
+                       "pdf_max_rel_err": float(rel.max())}}
+
+
+def stress_section(w, svo, room, args):
+    """The frame-scale room with the stress queue: 2,073,600 area-uniform
+    surface points in random order (no camera coherence), N = 16."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda:0")
+    rnd, _, _ = synth.area_points(room, 2_073_600, 14)
+    pos = torch.from_numpy(rnd).to(dev)
+    n = pos.shape[1]
+    opts = w.make_opts(N=16)
+    cnt = w.march_counts(svo, pos, opts).to(torch.int64).sum(0).cpu().numpy()
+    alg = n * (12 + 16) + 8 * int(cnt[0]) + int(cnt[1]) * (8 + 12)
+    d = torch.empty((3, n), device=dev)
+    p = torch.empty((n,), device=dev)
+    ms = _timed(lambda: w.guide_sample(svo, pos, opts, seed=2, bounce=1, dir_out=d, pdf_out=p), args.steps,
+                args.warmup)
+    assert torch.isfinite(p).all() and (p > 0).all()
+    return {"workload": "room D=10, 2073600 area-uniform vertices in random order, N=16",
+            "guide_sample_ms": ms, "samples_per_s": n / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "alg_bytes_per_launch": alg, "achieved": alg / (ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "node_tests_per_bin": int(cnt[0]) / (n * 256), "hit_fraction": int(cnt[1]) / (n * 256)}}
 
 
 def _timed(fn, K, warmup):
@@ -451,10 +570,21 @@ def batching_section(w, svo, room, cam, cnrm, args):
             w.guide_sample_binned(svo, q, w.bin_opts(N=bhalving[b], c_ray=512, l_min=5), 7, b,
                                   dir_out=G.dirs[b], pdf_out=G.pdfs[b])
     bh_ms = _timed(binned_halving, max(3, K // 4), 1)
+    # the same binned frame captured once in a HIP graph (the binned calls never
+    # wait for the device) and replayed
+    log("binned depth-halving as a graph")
+    binned_halving()   # scratch grown to these sizes before capture
+    torch.cuda.synchronize()
+    bg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(bg):
+        binned_halving()
+    bg_ms = _timed(bg.replay, max(3, K // 4), 1)
+    del bg
     depth_halving = {"per_vertex": {"N_per_bounce": halving, "graph_ms": h_ms,
                                     "samples_per_s": sum(sizes) / (h_ms * 1e-3)},
-                     "binned": {"N_per_bounce": bhalving, "c_ray": 512, "l_min": 5, "ms": bh_ms,
-                                "samples_per_s": sum(sizes) / (bh_ms * 1e-3)}}
+                     "binned": {"N_per_bounce": bhalving, "c_ray": 512, "l_min": 5, "eager_ms": bh_ms,
+                                "graph_ms": bg_ms, "samples_per_s": sum(sizes) / (bg_ms * 1e-3),
+                                "graph_speedup_vs_eager": bh_ms / bg_ms}}
     return {"bounces": len(sizes), "queue_sizes": sizes, "vertices": sum(sizes),
             "depth_halving": depth_halving,
             "budget_ns_per_vertex": args.budget_ns, "N_per_bounce": Ns,

@@ -483,9 +483,14 @@ wfpg_status wfpg_partition(const wfpg_svo *svo, const float *pos, int64_t n, int
 /* Binned guide_sample: pos DEVICE 3 x n; dir_out DEVICE 3 x n, pdf_out DEVICE
  * n (pdf of the sampled direction under the member's bin field, 1/sr; 0 and
  * a zero direction for a query without a bin); bin_out DEVICE n int32 (may
- * be NULL) as wfpg_partition. Synchronizes once (to size the per-bin fields)
- * and uses the SVO's binning scratch (calls on one SVO must be
- * stream-ordered). Errors: EINVAL for bad arguments, n >= 2^31. */
+ * be NULL) as wfpg_partition. Never waits for the device: the per-bin
+ * fields are sized by a bound on the bins a call can use (every bin is a node
+ * at a level up to l_min, or a deeper node holding at least c_ray queries:
+ * at most n / c_ray per level) and the kernels read the used count on the
+ * device, so the call can be captured in a HIP graph. It uses the SVO's
+ * binning scratch, which grows on first use: calls on one SVO must be
+ * stream-ordered, and a caller capturing a graph makes one call of the same
+ * n and N first. Errors: EINVAL for bad arguments, n >= 2^31. */
 wfpg_status guide_sample_binned(const wfpg_svo *svo, const float *pos, int64_t n, uint64_t seed,
                                 uint32_t bounce, const wfpg_bin_opts *opts, float *dir_out,
                                 float *pdf_out, int32_t *bin_out, void *hip_stream);

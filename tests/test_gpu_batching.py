@@ -167,3 +167,71 @@ def test_graph_eight_bounces_match_oracle(orc):
             assert chord.max() < bars.DIR_TOL, (rep, b, chord.max())
     assert g.stats()["errors"] == 0
     G.close()
+
+
+def test_binned_depth_halving_graph(orc):
+    """Alg. 1 with Alg. 2 and 3 per bounce: binned guiding with the field
+    resolution halved per depth (128, 64, 32, 16; c_ray = 256, l_min = 3)
+    over shrinking queues, captured once in a HIP graph and replayed (eager
+    work and synchronizations between replays). Every replay equals the eager
+    calls bit for bit, and every member's bin, pdf and direction match the
+    oracle's binned sampler (sequential-scan band, 2e-6 directions)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_2405_06997_amd as w
+    dev = torch.device("cuda:0")
+    room = synth.room(n_boxes=16)
+    D = 8
+    o = orc.SVO(room, D)
+    xyz, em = o.leaf_info()
+    sp = synth.leaf_splats(xyz, o.normals(D), em, D, seed=2)
+    assert o.accumulate(*sp) == 0
+    o.propagate()
+    g = w.svo_build(room, D)
+    w.svo_accumulate(g, *[torch.from_numpy(a).to(dev) for a in sp])
+    Ns = [128, 64, 32, 16]
+    sizes = [24000, 15000, 9000, 5000]
+    qs = [synth.area_points(room, n, 70 + b)[0] for b, n in enumerate(sizes)]
+    pos = [torch.from_numpy(q).to(dev) for q in qs]
+    opts = [w.bin_opts(N=N, c_ray=256, l_min=3) for N in Ns]
+    dirs = [torch.empty((3, n), device=dev) for n in sizes]
+    pdfs = [torch.empty((n,), device=dev) for n in sizes]
+
+    def frame():
+        for b in range(4):
+            w.guide_sample_binned(g, pos[b], opts[b], seed=808, bounce=b, dir_out=dirs[b], pdf_out=pdfs[b])
+
+    frame()   # eager: grows the binning scratch to these sizes before capture
+    torch.cuda.synchronize()
+    eager = [(d.clone(), p.clone()) for d, p in zip(dirs, pdfs)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        frame()
+    for rep in range(3):
+        for d, p in zip(dirs, pdfs):
+            d.fill_(7.0)
+            p.fill_(7.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        for b in range(4):
+            assert torch.equal(dirs[b], eager[b][0]) and torch.equal(pdfs[b], eager[b][1]), (rep, b)
+        w.guide_sample(g, pos[3][:, :100].contiguous(), w.make_opts(N=8), seed=1, bounce=0)   # eager work
+        torch.cuda.synchronize()
+    for b, N in enumerate(Ns):
+        r = o.binned_sample(qs[b], 256, 3, N, 808, b)
+        d = dirs[b].cpu().numpy().astype(np.float64)
+        p = pdfs[b].cpu().numpy().astype(np.float64)
+        uv = oracle.oct_encode_many(d)
+        gb = np.minimum((uv * N).astype(np.int64), N - 1)
+        same = (gb[0] == r["bin"][:, 0]) & (gb[1] == r["bin"][:, 1])
+        band = (r["margin"] < bars.scan_band_seq(N)).any(1)
+        assert (same | band).all(), (N, np.nonzero(~(same | band))[0][:10])
+        assert same.mean() > 0.999
+        rel = np.abs(p[same] - r["pdf"][same]) / r["pdf"][same]
+        bars.record(f"binned graph N={N} rel", rel.max())
+        assert rel.max() <= bars.PDF_RTOL
+        chord = np.linalg.norm(d[:, same] - r["dir"][:, same], axis=0)
+        assert chord.max() < bars.DIR_TOL, chord.max()
+    assert g.stats()["errors"] == 0
