@@ -236,7 +236,7 @@ def main():
         out["extract"] = extract_section(w, room, args)
     if "learned" in sections:
         log("learned section")
-        out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms)
+        out["learned"] = learned_section(w, svo, room, pos, cnrm, n, args, gs_avg, acc_ms, sp)
     if "batching" in sections:
         log("batching section")
         out["batching"] = batching_section(w, svo, room, cam, cnrm, args)
@@ -442,7 +442,7 @@ def extract_section(w, room, args):
             "alg_bytes": alg, "alg_gbs": alg / (ms * 1e-3) / 1e9, "includes": "splat + bottom-up propagation"}
 
 
-def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
+def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms, svo_splats_for_learned):
     """Hash-grid MLP trained on march pdfs of jittered frames of the same
     camera (as a progressive renderer sees them), then guide_sample in mode 1
     (network sample + march probes every 256th vertex + KL judge with the
@@ -469,7 +469,6 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
     loss = w.guide_train(svo, tp, tn, steps=steps, batch=batch)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    del tp, tn
 
     opts1 = w.make_opts(N=16, mode=1, kl_bound=0.05, probe_stride=256)
     d_out = torch.empty((3, n), device=dev)
@@ -500,6 +499,32 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
     tj = tj / tj.sum(1, keepdim=True)
     klj = torch.where(t > 0, t * (t.log() - tj.log()), torch.zeros_like(t)).sum(1).cpu().numpy()
     flops = 2 * (35 * 64 + 3 * 64 * 64 + 64 * 256)   # algorithmic MACs x 2 per vertex
+    # smoother target fields (Sec. 4): the blurred field with a larger initial
+    # value eps; a fresh model per field, trained and judged on that field
+    log("learned: blurred targets")
+    smooth = []
+    for eps in (0.01, 0.1, 0.3, 1.0):
+        g2 = w.svo_build(room, 10)
+        w.svo_accumulate(g2, *svo_splats_for_learned)
+        w.guide_train(g2, tp, tn, steps=steps, batch=batch, target_eps=eps, target_blur=1)
+        o0 = w.make_opts(N=16, eps=eps, blur=True)
+        t2 = w.guide_pdf(g2, sp_, o0).double()
+        t2 = t2 / t2.sum(1, keepdim=True)
+        q2 = w.nn_forward(g2, sp_, sn_).double()
+        k2 = torch.where(t2 > 0, t2 * (t2.log() - q2.log()), torch.zeros_like(t2)).sum(1).cpu().numpy()
+        o1 = w.make_opts(N=16, eps=eps, blur=True, mode=1, kl_bound=0.05, probe_stride=256)
+        fb = w.learned_stats(g2)["fallbacks"]
+        m1 = _timed(lambda: w.guide_sample(g2, pos, o1, seed=3, bounce=0, nrm=nrm, dir_out=d_out, pdf_out=p_out),
+                    K, args.warmup)
+        fb = w.learned_stats(g2)["fallbacks"] - fb
+        m0 = _timed(lambda: w.guide_sample(g2, pos, o0, seed=3, bounce=0, dir_out=d_out, pdf_out=p_out),
+                    K, args.warmup)
+        smooth.append({"eps": eps, "blur": True, "kl_mean": float(k2.mean()), "kl_median": float(np.median(k2)),
+                       "frac_vertices_kl_le_0.05": float((k2 <= 0.05).mean()),
+                       "judge_probe_kl": w.learned_stats(g2)["last_probe_kl"], "fallbacks": fb,
+                       "calls": K + args.warmup, "mode1_ms": m1, "march_ms": m0, "speedup_vs_march": m0 / m1})
+        del g2
+    del tp, tn
     return {
         "what": "hash-grid (16 x 2^19 x 2) + MLP 35-64-64-64-64-256, BF16 MFMA, trained on the GPU "
                 "on march pdfs; mode-1 guide_sample with KL judge (bound 0.05 nats, probe every "
@@ -518,6 +543,7 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms):
                                   "what": "KL(march pdf at the pixel centre || march pdf at a "
                                           "jittered point of the same pixel), same vertices"},
         "nn_forward_ms": fwd_ms,
+        "blurred_targets": smooth,
         "no_fallback_guide_sample_ms": nf_ms,
         "no_fallback_speedup_vs_march": march_ms / nf_ms,
         "mfma_flops_per_vertex": flops,
