@@ -363,8 +363,15 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     // through which the hand-out passes bins to idle lanes
     uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) +
                       (size_t)wave * S * BPL;
-    uint16_t *xch = reinterpret_cast<uint16_t *>(reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) +
-                                                 (size_t)nw * S * BPL) + (size_t)wave * 64;
+    uint64_t *pm_end = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) + (size_t)nw * S * BPL;
+    uint16_t *xch = reinterpret_cast<uint16_t *>(pm_end) + (size_t)wave * 64;
+    // per wave: the vertex of each slot and the fed vertex's origin (x, y, z,
+    // leaf key | occupied << 31)
+    int64_t *svert = reinterpret_cast<int64_t *>(reinterpret_cast<uint16_t *>(pm_end) + (size_t)nw * 64) +
+                     (size_t)wave * S;
+    uint32_t *sfeed = reinterpret_cast<uint32_t *>(reinterpret_cast<int64_t *>(reinterpret_cast<uint16_t *>(pm_end) +
+                                                                              (size_t)nw * 64) + (size_t)nw * S) +
+                      (size_t)wave * 4;
     // The per-vertex finalization reads its arguments from an LDS copy: held
     // in scalar registers across the march loop they overflowed the scalar
     // file and were spilled into vector lanes (two lane moves per use); read
@@ -408,13 +415,13 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     int64_t chunk_next = 0;
     int chunk_left = 0;
     bool exhausted = false;
-    int64_t vs[S];                       // vertex of each slot (-1: free)
-    int rem[S];                          // bins of the slot not yet finished
+    // bins of each slot not yet finished (-1: the slot is free); the slots'
+    // vertices and the fed vertex's origin live in LDS (scalar registers are
+    // the kernel's scarcest resource)
+    int rem[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) { vs[k] = -1; rem[k] = 0; }
+    for (int k = 0; k < S; ++k) rem[k] = -1;
     int feed = -1, nxt = BPL;            // slot being handed out and its mask of bins being handed out
-    uint32_t F0 = 0, F1 = 0, F2 = 0, Fkey = 0;   // origin and origin-leaf key of the fed vertex
-    bool Focc = false;
     // per-lane march state
     int lslot = 0, lbin = -1, vis = 0, iters = 0;
     core::MicroState st;
@@ -448,16 +455,17 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             int64_t vd = 0;
 #pragma unroll
             for (int k = 0; k < S; ++k)
-                if (done < 0 && vs[k] >= 0 && rem[k] == 0) { done = k; vd = vs[k]; }
+                if (done < 0 && rem[k] == 0) done = k;
             if (done < 0) break;
             wave_lds_fence();
+            vd = uni(svert[done]);
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
             finalize<N, MODE, BLUR>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * RW * NN,
                                     vd, ps, lane, vl);
             wave_lds_fence();
 #pragma unroll
             for (int k = 0; k < S; ++k)
-                if (k == done) vs[k] = -1;
+                if (k == done) rem[k] = -1;
         }
         // hand out bins to idle lanes
         uint64_t idle = __ballot(lbin < 0);
@@ -466,7 +474,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 int f = -1;
 #pragma unroll
                 for (int k = 0; k < S; ++k)
-                    if (f < 0 && vs[k] < 0) f = k;
+                    if (f < 0 && rem[k] < 0) f = k;
                 if (f < 0 || exhausted) break;
                 if (chunk_left == 0) {
                     int64_t b = 0;
@@ -484,8 +492,13 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D),
                                                     O[2] >> (WFPG_FINE - D));
                 const bool oc = core::occupied(bits, D, okey);
-                F0 = uni(O[0]); F1 = uni(O[1]); F2 = uni(O[2]); Fkey = uni(okey);
-                Focc = uni((int)oc) != 0;
+                if (lane == 0) {
+                    sfeed[0] = O[0];
+                    sfeed[1] = O[1];
+                    sfeed[2] = O[2];
+                    sfeed[3] = okey | (oc ? 0x80000000u : 0u);
+                    svert[f] = vi;
+                }
                 if constexpr (MODE == MODE_COUNT) {
                     if (lane == 0) svis[f] = 0u;
                     wave_lds_fence();
@@ -513,7 +526,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 wave_lds_fence();
 #pragma unroll
                 for (int k = 0; k < S; ++k)
-                    if (k == f) { vs[k] = uni(vi); rem[k] = uni(npend); }
+                    if (k == f) rem[k] = uni(npend);
                 feed = f;
                 nxt = 0;
             }
@@ -536,12 +549,13 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             if (mine) {
                 lslot = feed;
                 lbin = xch[r];
-                const uint32_t O[3] = {F0, F1, F2};
+                const uint32_t O[3] = {sfeed[0], sfeed[1], sfeed[2]};
+                const uint32_t Fk = sfeed[3];
                 const uint32_t w0 = lq[3 * lbin], w1 = lq[3 * lbin + 1], w2 = lq[3 * lbin + 2];
                 const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
                 vis = 0;
                 iters = 0;
-                core::micro_begin(st, O, Fkey, Focc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
+                core::micro_begin(st, O, Fk & 0x7fffffffu, (Fk >> 31) != 0u, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
                                   a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, vis);
             }
             idle &= ~__ballot(mine);
@@ -553,8 +567,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             bool any = false, ready = false;
 #pragma unroll
             for (int k = 0; k < S; ++k) {
-                any = any || vs[k] >= 0;
-                ready = ready || (vs[k] >= 0 && rem[k] == 0);
+                any = any || rem[k] >= 0;
+                ready = ready || rem[k] == 0;
             }
             if (!any) break;
             if (!ready) {
@@ -579,10 +593,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
         }
         const bool fin = lbin >= 0 && res != core::STEP_CONTINUE;
         if (fin) {
-            int64_t vl = vs[0];
-#pragma unroll
-            for (int k = 1; k < S; ++k)
-                if (lslot == k) vl = vs[k];
+            const int64_t vl = MODE == MODE_DEBUG ? svert[lslot] : 0;
             finish(st, res, lslot, lbin, vl, vis);
             lbin = -1;
         }

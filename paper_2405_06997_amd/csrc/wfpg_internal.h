@@ -124,7 +124,8 @@ inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPL
     const size_t S = (size_t)guide_slots(N), NN = (size_t)N * N;
     return NN * 3 * 4 * 2 +
            (size_t)tc.waves_per_block * (S * ((size_t)guide_rec_words(mode) * NN * 4 + 4) +   // records, counts
-                                         S * (NN / 64) * 8 + 64 * 2);                        // bin masks, exchange
+                                         S * (NN / 64) * 8 + 64 * 2 +                        // bin masks, exchange
+                                         S * 8 + 4 * 4);                                     // slot vertices, origin
 }
 // Dynamic LDS a guide workgroup may use on the current device (all modes but
 // debug): the device's per-workgroup LDS less kGuideStaticLds, a bound on the
