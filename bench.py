@@ -24,9 +24,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
-# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per 2 cycles per SIMD
-# (32 lanes per clock, the rate behind the 157.3 TFLOP/s FP32 vector peak), 2.4 GHz
-VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 2
+SIMDS = 256 * 4           # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
+
+# VALU issue ceiling of the guide kernel: its own mix of instruction forms,
+# each at its issue cost per wave64 instruction per SIMD: 2 cycles for the
+# one- and two-operand encodings (_e32; 32 lanes per clock, the rate behind
+# the 157.3 TFLOP/s FP32 vector figure) and 4 cycles for the three-operand
+# encoding and 64-bit forms (16 lanes per clock). The issue probe
+# (libwfpg_probe.so, four waves per SIMD on one CU), run live and reported
+# beside it, measures every form at or above these costs except v_bitop3_b32
+# (about 3 cycles; 24 of the 666 instructions below, counted at 4).
+# The mix is counted in the compiler listing (hipcc -S of guide.hip) of the
+# four unrolled steps of the pool loop of k_guide<16, SAMPLE, no blur> (666
+# VALU instructions) and describes the sources below only.
+PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
+               "bitop3", "lshl_e64"]
+GUIDE_STEP_MIX = {
+    "sources_sha256": "f1cd6fd58393be31a5a6a6f6156de75bfeb87b0fd973371ab42eb79dc711c149",
+    # class: (instructions in the listing, issue cycles, probe forms of the class)
+    "classes": {
+        "vop1/vop2/vopc (_e32)": (252, 2, ["add_e32", "xor_e32"]),
+        "v_cndmask_b32_e64": (160, 4, ["cndmask_e64"]),
+        "other three-operand 32-bit": (102, 4, ["bitop3", "lshl_e64"]),
+        "32-bit compares into an SGPR pair": (68, 4, ["cmp_e64"]),
+        "v_mad_u64_u32 / v_mad_i64_i32": (44, 4, ["mad_u64"]),
+        "64-bit compares": (24, 4, ["cmp64_e64"]),
+        "v_lshl_add_u64": (16, 4, ["lshl_add_u64"]),
+    },
+}
 
 # HBM bytes per launch of k_guide<16, SAMPLE> on this workload, from two
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) each scaled by what the same
@@ -34,27 +60,68 @@ VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 2
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "72bbcc71e6f9588f1f6b0cb287927cec04f4d10a19f373221ba9a8b66e46b2ae",
+    "sources_sha256": "f1cd6fd58393be31a5a6a6f6156de75bfeb87b0fd973371ab42eb79dc711c149",
     "N": 16,
     "tile": {"waves_per_block": 4, "blocks_per_cu": 6},
-    "bytes_per_launch": 5120221150,
-    "valu_wave_instrs_per_launch": 17557459930,
+    "bytes_per_launch": 4058847907,
+    "valu_wave_instrs_per_launch": 15068975948,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 
 
-def measured_counters(N, tile):
-    """The counter-derived figures (HBM bytes, VALU instructions per launch) if
-    they still describe the kernel that runs, else None."""
+def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2405_06997_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_counters(N, tile):
+    """The counter-derived figures (HBM bytes, VALU instructions per launch) if
+    they still describe the kernel that runs, else None."""
     m = MEASURED_TRAFFIC
-    if h.hexdigest() != m["sources_sha256"] or N != m["N"] or tile != m["tile"]:
+    if kernel_sources_sha256() != m["sources_sha256"] or N != m["N"] or tile != m["tile"]:
         return None
     return m
+
+
+def valu_issue_cycles(waves_per_simd=4, iters=20000):
+    """Cycles (at CLOCK_HZ) per wave64 instruction per SIMD of each probe form:
+    one workgroup, waves_per_simd waves on each SIMD of one CU, twelve
+    independent chains of that form per wave."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2405_06997_amd", "libwfpg_probe.so"))
+    lib.wfpg_probe_valu_issue.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    assert lib.wfpg_probe_valu_forms() == len(PROBE_FORMS)
+    out = {}
+    for op, name in enumerate(PROBE_FORMS):
+        ms, n = ctypes.c_float(), ctypes.c_double()
+        err = lib.wfpg_probe_valu_issue(op, waves_per_simd, iters, ctypes.byref(ms), ctypes.byref(n))
+        if err != 0:
+            raise RuntimeError("VALU issue probe failed (hipError %d)" % err)
+        out[name] = ms.value * 1e-3 * CLOCK_HZ / n.value
+    return out
+
+
+def valu_roofline(instrs_per_launch, launch_ms):
+    """The guide kernel's VALU issue rate against the ceiling of its own mix of
+    instruction forms (None when the mix no longer describes the sources)."""
+    if instrs_per_launch is None or kernel_sources_sha256() != GUIDE_STEP_MIX["sources_sha256"]:
+        return None
+    classes = list(GUIDE_STEP_MIX["classes"].values())
+    total = sum(n for n, _, _ in classes)
+    mix_cycles = sum(n * c for n, c, _ in classes) / total
+    cyc = valu_issue_cycles()
+    probe_mix = sum(n * sum(cyc[f] for f in forms) / len(forms) for n, _, forms in classes) / total
+    peak = SIMDS * CLOCK_HZ / mix_cycles
+    achieved = instrs_per_launch / (launch_ms * 1e-3)
+    return {"bound": "valu issue", "achieved": achieved, "peak": peak, "unit": "wave64 VALU instructions/s",
+            "frac": achieved / peak, "mix_cycles_per_instr": mix_cycles,
+            "kernel_cycles_per_instr": SIMDS * CLOCK_HZ / achieved,
+            "probe_cycles_per_instr": cyc, "probe_mix_cycles_per_instr": probe_mix}
 
 
 def parse():
@@ -203,11 +270,8 @@ def main():
             "traffic_gbs": None if traffic is None else traffic / (gs_avg * 1e-3) / 1e9,
             "node_tests_per_bin": visits / (n * NN), "hit_fraction": hits / (n * NN),
             "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-            # the march is integer-ALU bound: VALU issue beside the logical HBM fraction
-            "valu": None if counters is None else {
-                "achieved": counters["valu_wave_instrs_per_launch"] / (gs_avg * 1e-3),
-                "peak": VALU_PEAK_WAVE_INSTR_S, "unit": "wave64 VALU instructions/s",
-                "frac": counters["valu_wave_instrs_per_launch"] / (gs_avg * 1e-3) / VALU_PEAK_WAVE_INSTR_S},
+            # the march is bound by VALU issue: its rate beside the logical HBM fraction
+            "valu": valu_roofline(None if counters is None else counters["valu_wave_instrs_per_launch"], gs_avg),
         },
     }
     orc = None

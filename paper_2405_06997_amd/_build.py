@@ -1,4 +1,5 @@
-"""Build libwfpg.so (HIP, gfx950) in-tree with hipcc.
+"""Build libwfpg.so (HIP, gfx950) in-tree with hipcc, and beside it
+libwfpg_probe.so, the benchmark's VALU issue probe (no part of the library).
 
 Every source is compiled for gfx950 only, with FP contraction off (the
 kernels spell out their fused multiply-adds where they want them, so that
@@ -18,6 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libwfpg.so")
 SOURCES = ["api.hip", "build.hip", "accumulate.hip", "guide.hip", "tune.hip", "graph.hip", "nn.hip", "binning.hip"]
+PROBE_LIB = os.path.join(HERE, "libwfpg_probe.so")
+PROBE_SOURCE = "valu_issue_probe.hip"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -37,18 +40,23 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [PROBE_SOURCE]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], PROBE_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE_LIB}")
     return LIB
 
 
