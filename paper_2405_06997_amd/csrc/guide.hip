@@ -503,12 +503,36 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                     if (lane == 0) svis[f] = 0u;
                     wave_lds_fence();
                 }
+                // Without node-test counts, a vertex whose leaf is occupied
+                // takes its first steps from the occupancy of the leaf's six
+                // face neighbours (lane 2j + up tests the one along axis j),
+                // read once for all its bins; with an empty leaf every bin
+                // starts in the hand-out.
+                constexpr bool kNbrStep = MODE != MODE_DEBUG && MODE != MODE_COUNT;
+                const bool nbr_step = kNbrStep && uni((int)oc) != 0;
+                uint32_t nbm = 0u;
+                if (nbr_step) {
+                    bool on = false;
+                    if (lane < 6) {
+                        const int ax = lane >> 1;
+                        uint32_t c0 = O[0] >> (WFPG_FINE - D), c1 = O[1] >> (WFPG_FINE - D),
+                                 c2 = O[2] >> (WFPG_FINE - D);
+                        const uint32_t cj = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+                        const uint32_t nj = (lane & 1) ? cj + 1u : cj - 1u;   // wraps below 0
+                        c0 = ax == 0 ? nj : c0;
+                        c1 = ax == 1 ? nj : c1;
+                        c2 = ax == 2 ? nj : c2;
+                        on = nj < (1u << D) && core::occupied(bits, D, core::morton3(c0, c1, c2));
+                    }
+                    nbm = (uint32_t)__ballot(on);
+                }
+                const auto nbr = [&](int ax, bool up) { return ((nbm >> (2 * ax + (up ? 1 : 0))) & 1u) != 0u; };
                 // First step of every bin of the new vertex by the whole wave,
                 // whatever ray a lane is marching (about three rays in four end
                 // there: the leaf next to the origin, or out of the cube); the
                 // others are marked for the hand-out.
                 int npend = 0;
-#pragma unroll
+#pragma unroll 1
                 for (int j = 0; j < BPL; ++j) {
                     const int b = j * 64 + lane;
                     const uint32_t w0 = lq[3 * b], w1 = lq[3 * b + 1], w2 = lq[3 * b + 2];
@@ -517,7 +541,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                     int pv = 0;
                     core::micro_begin(ms, O, okey, oc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
                                       a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, pv);
-                    const int r1 = core::micro_step(ms, D, bits64, 5, pv);
+                    int r1;
+                    if constexpr (kNbrStep)   // an empty origin leaf: every bin goes to the hand-out
+                        r1 = nbr_step ? core::first_step(ms, D, nbr) : core::STEP_CONTINUE;
+                    else
+                        r1 = core::micro_step(ms, D, bits64, 5, pv);
                     if (r1 != core::STEP_CONTINUE) finish(ms, r1, f, b, vi, pv);
                     const uint64_t pm = __ballot(r1 == core::STEP_CONTINUE);
                     if (lane == 0) pmask[f * BPL + j] = pm;

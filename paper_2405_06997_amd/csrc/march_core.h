@@ -171,15 +171,18 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
 // node tests counted are those of the walk (levels >= count_from).
 // bits64(wi) returns 64-bit word wi of the concatenated bitmaps. On STEP_HIT
 // the hit is hit_of(s, D).
-template <class Bits64>
-WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_from, int &vis)
+// The first exit crossing of the cell s holds, through its upper face on
+// every axis: along axis e (lane masks m0, m1, m2), at parameter tn / td. The
+// cell entered has corner nlu along e (2^30 when the crossing leaves the cube)
+// and key akey. An axis the ray does not cross (|q| = 0) has lo + size - O >= 1,
+// which only ever meets its zero |q| in the comparisons.
+struct Exit {
+    uint32_t m0, m1, m2, le, nlu, akey, tn, td;
+    int e;
+};
+WFPG_HD Exit exit_crossing(const MicroState &s, uint32_t size)
 {
-    // PH_ADVANCE: the first exit crossing of the current cell, through its
-    // upper face on every axis. An axis the ray does not cross (|q| = 0) has
-    // lo + size - O >= 1, which only ever meets its zero |q| in the
-    // comparisons below.
-    const bool adv = s.phase == PH_ADVANCE;
-    const uint32_t size = 1u << (kFine - s.lvl);
+    Exit x;
     const uint32_t dl0 = s.lo0 + size - s.O0;
     const uint32_t dl1 = s.lo1 + size - s.O1;
     const uint32_t dl2 = s.lo2 + size - s.O2;
@@ -188,24 +191,38 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_fro
     const uint32_t C1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? ~0u : 0u;   // axis 1 before axis 0
     const uint32_t D01 = (dl1 & C1) | (dl0 & ~C1), Q01 = (s.aq1 & C1) | (s.aq0 & ~C1);
     const uint32_t C2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? ~0u : 0u;      // axis 2 before both
-    const uint32_t m0 = ~C1 & ~C2, m1 = C1 & ~C2, m2 = C2;
-    const int e = (int)((m1 & 1u) | (m2 & 2u));
-    const uint32_t le = (s.lo0 & m0) | (s.lo1 & m1) | (s.lo2 & m2);
+    x.m0 = ~C1 & ~C2;
+    x.m1 = C1 & ~C2;
+    x.m2 = C2;
+    x.e = (int)((x.m1 & 1u) | (x.m2 & 2u));
+    x.le = (s.lo0 & x.m0) | (s.lo1 & x.m1) | (s.lo2 & x.m2);
     // one cell up along the crossed axis (|q| > 0); leaving the cube reaches 2^30
-    const uint32_t nlu = le + size;
-    const bool miss = adv & (nlu >= (1u << kFine));
-    const uint32_t m = 0x09249249u << e;   // the key bits of axis e: add one to them
-    const uint32_t akey = ((((s.key | ~m) + 1u) & m)) | (s.key & ~m);
+    x.nlu = x.le + size;
+    const uint32_t m = 0x09249249u << x.e;   // the key bits of axis e: add one to them
+    x.akey = ((((s.key | ~m) + 1u) & m)) | (s.key & ~m);
+    x.tn = (dl2 & x.m2) | (D01 & ~x.m2);
+    x.td = (s.aq2 & x.m2) | (Q01 & ~x.m2);
+    return x;
+}
+
+template <class Bits64>
+WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_from, int &vis)
+{
+    // PH_ADVANCE: leave the current cell through its first exit crossing.
+    const bool adv = s.phase == PH_ADVANCE;
+    const uint32_t size = 1u << (kFine - s.lvl);
+    const Exit x = exit_crossing(s, size);
+    const bool miss = adv & (x.nlu >= (1u << kFine));
     // first level not shared with the cell left (le and nlu differ at level lvl, so ch >= 1)
-    const uint32_t ch = (le ^ nlu) >> (kFine - s.lvl);
+    const uint32_t ch = (x.le ^ x.nlu) >> (kFine - s.lvl);
     const int al = s.lvl - (31 - __builtin_clz(ch));
-    s.lo0 = adv & (m0 != 0u) ? nlu : s.lo0;
-    s.lo1 = adv & (m1 != 0u) ? nlu : s.lo1;
-    s.lo2 = adv & (m2 != 0u) ? nlu : s.lo2;
-    s.key = adv ? akey : s.key;
-    s.tn = adv ? ((dl2 & m2) | (D01 & ~m2)) : s.tn;
-    s.td = adv ? ((s.aq2 & m2) | (Q01 & ~m2)) : s.td;
-    s.ta = adv ? e : s.ta;
+    s.lo0 = adv & (x.m0 != 0u) ? x.nlu : s.lo0;
+    s.lo1 = adv & (x.m1 != 0u) ? x.nlu : s.lo1;
+    s.lo2 = adv & (x.m2 != 0u) ? x.nlu : s.lo2;
+    s.key = adv ? x.akey : s.key;
+    s.tn = adv ? x.tn : s.tn;
+    s.td = adv ? x.td : s.td;
+    s.ta = adv ? x.e : s.ta;
     const int l = adv ? al : s.l;
     const bool path = adv || s.phase == PH_PATH;
 
@@ -278,6 +295,28 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_fro
     s.l = T + 1;
     if (miss) return STEP_MISS;
     return full && at_cell && nl == D ? STEP_HIT : STEP_CONTINUE;
+}
+
+// The first step from an occupied origin leaf (the state micro_begin leaves),
+// for callers that need the march's result but not its node-test count: the
+// leaf's first exit crossing and the face neighbour it enters. nbr(j, up)
+// returns whether the neighbour leaf along axis j (up: towards larger
+// coordinates of the original frame) is occupied. STEP_MISS when the
+// crossing leaves the cube; STEP_HIT when the neighbour is occupied -- the
+// hit micro_step reaches from the same state, since the neighbour's
+// ancestors are occupied too and the leaf is entered by this crossing (on
+// STEP_HIT the hit is hit_of(s, D)); STEP_CONTINUE otherwise, with s no
+// longer a valid march state.
+template <class Nbr>
+WFPG_HD int first_step(MicroState &s, int D, const Nbr &nbr)
+{
+    const Exit x = exit_crossing(s, 1u << (kFine - D));
+    if (x.nlu >= (1u << kFine)) return STEP_MISS;
+    s.key = x.akey;
+    s.tn = x.tn;
+    s.td = x.td;
+    s.ta = x.e;
+    return nbr(x.e, ((s.mir >> x.e) & 1u) == 0u) ? STEP_HIT : STEP_CONTINUE;
 }
 
 // The hit of a march whose last step returned STEP_HIT: the crossing axis, the

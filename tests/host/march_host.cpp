@@ -84,3 +84,47 @@ extern "C" int host_footprint_levels(uint32_t delta, float dabs, int D, float om
 {
     return footprint_levels(delta, dabs, D, omega);
 }
+
+// The first step from an occupied origin leaf taken from the occupancy of the
+// leaf's face neighbours (first_step), per (point, direction) pair: out =
+// {result, axis, key, delta} with result 1 hit, 2 miss, 0 continue (axis, key
+// and delta then those of the crossing into the empty neighbour), -1 when the
+// origin leaf is empty (no first step taken).
+extern "C" void host_first_step_dirs(const uint64_t *bits, int D, const float *pos, int64_t n, const float *dirs,
+                                     int nd, int64_t *out)
+{
+    const uint32_t *bits32 = reinterpret_cast<const uint32_t *>(bits);
+    auto load = [&](int, uint32_t wi) -> uint32_t { return bits32[wi]; };
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t O[3];
+        for (int k = 0; k < 3; ++k) O[k] = quantize_pos(pos[k * n + i]);
+        const uint32_t c[3] = {O[0] >> (kFine - D), O[1] >> (kFine - D), O[2] >> (kFine - D)};
+        const uint32_t ok = morton3(c[0], c[1], c[2]);
+        const bool occ = occupied(load, D, ok);
+        auto nbr = [&](int ax, bool up) {
+            uint32_t cc[3] = {c[0], c[1], c[2]};
+            cc[ax] = up ? cc[ax] + 1u : cc[ax] - 1u;
+            return cc[ax] < (1u << D) && occupied(load, D, morton3(cc[0], cc[1], cc[2]));
+        };
+        for (int b = 0; b < nd; ++b) {
+            int64_t *o = out + (i * nd + b) * 4;
+            if (!occ) {
+                o[0] = -1; o[1] = -1; o[2] = -1; o[3] = -1;
+                continue;
+            }
+            const float *d = dirs + 3 * b;
+            uint32_t aq[3];
+            int sg[3];
+            for (int k = 0; k < 3; ++k) split_dir(quantize_dir(d[k]), aq[k], sg[k]);
+            MicroState s;
+            int vis = 0;
+            micro_begin(s, O, ok, true, aq[0], aq[1], aq[2], sg[0], sg[1], sg[2], D, 0, vis);
+            const int r = first_step(s, D, nbr);
+            const Hit h = hit_of(s, D);
+            o[0] = r == STEP_HIT ? 1 : (r == STEP_MISS ? 2 : 0);
+            o[1] = r == STEP_MISS ? -1 : h.axis;
+            o[2] = r == STEP_MISS ? -1 : (int64_t)h.key;
+            o[3] = r == STEP_MISS ? -1 : (int64_t)h.delta;
+        }
+    }
+}

@@ -25,6 +25,9 @@ def host_lib(tmp_path_factory):
     L.host_footprint_levels.argtypes = [C.c_uint32, C.c_float, C.c_int, C.c_float]
     L.host_march_dirs.restype = None
     L.host_march_dirs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]
+    L.host_first_step_dirs.restype = None
+    L.host_first_step_dirs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                       C.c_void_p]
     L.host_debug_march.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_int64,
                                                        C.c_void_p, C.c_int, C.c_float,
                                                        C.c_void_p, C.c_void_p]
@@ -160,6 +163,51 @@ def test_host_core_special_directions(orc, host_lib):
                 hits += 1
                 assert (got[1], got[2], got[3]) == (w["axis"], w["key"], w["delta"]), (i, b, got, w)
     assert hits > 1000
+
+
+def test_host_first_step_from_neighbours(orc, host_lib):
+    """The first step of a ray from an occupied origin leaf taken from the
+    occupancy of the leaf's six face neighbours (the kernels' shortcut when
+    no node-test count is kept): a hit is the oracle's hit (same leaf, axis
+    and |B - O|), a miss the oracle's miss, and a ray sent on is one the
+    oracle does not end in the empty neighbour it entered. Camera-queue and
+    area points of the room at depth 8 and points on the planes of many
+    levels, with axis, diagonal and random directions."""
+    import itertools
+    room = synth.room()
+    D = 8
+    o = orc.SVO(room, D)
+    dirs = [np.array(v, float) / np.linalg.norm(v) for v in itertools.product([-1, 0, 1], repeat=3) if any(v)]
+    rng = np.random.default_rng(19)
+    r = rng.normal(size=(40, 3))
+    r[np.arange(20), rng.integers(0, 3, 20)] = 0.0
+    dirs += list(r / np.linalg.norm(r, axis=1, keepdims=True))
+    dirs = np.ascontiguousarray(np.array(dirs, np.float32))
+    cam, _, _ = synth.camera_queue(room)
+    area, _, _ = synth.area_points(room, 60, 23)
+    # area points snapped to leaf corners: on the planes of every level below
+    snap = np.clip(np.round(area[:, :30] * 2 ** D) / 2 ** D, 0, 1)
+    pos = np.concatenate([cam[:, rng.choice(cam.shape[1], 60, replace=False)], area, snap], 1)
+    pos = np.ascontiguousarray(pos.astype(np.float32))
+    bits, _, _, _ = bitmaps_from_oracle(o, D)
+    out = np.zeros((pos.shape[1], len(dirs), 4), np.int64)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    host_lib.host_first_step_dirs(p(bits), D, p(pos), pos.shape[1], p(dirs), len(dirs), p(out))
+    seen = {0: 0, 1: 0, 2: 0}
+    for i in range(pos.shape[1]):
+        for b in range(len(dirs)):
+            got = out[i, b]
+            if got[0] < 0:
+                continue
+            seen[int(got[0])] += 1
+            w = o.march_one(pos[:, i], dirs[b])
+            if got[0] == 1:
+                assert w["hit"] and (got[1], got[2], got[3]) == (w["axis"], w["key"], w["delta"]), (i, b, got, w)
+            elif got[0] == 2:
+                assert not w["hit"], (i, b, got, w)
+            else:
+                assert not (w["hit"] and w["key"] == got[2]), (i, b, got, w)
+    assert seen[1] > 2000 and seen[0] > 500 and seen[2] > 0, seen
 
 
 def test_host_footprint_levels_at_thresholds(host_lib):
