@@ -615,7 +615,29 @@ def learned_section(w, svo, room, pos, cnrm, n, args, march_ms, acc_ms, svo_spla
         "no_fallback_guide_sample_ms": nf_ms,
         "no_fallback_speedup_vs_march": march_ms / nf_ms,
         "mfma_flops_per_vertex": flops,
+        "inference_roofline": inference_roofline(n, flops, fwd_ms),
     }
+
+
+def inference_roofline(n, flops, fwd_ms):
+    """The network forward (nn_forward: the 256 probabilities of every vertex
+    written out) against the dense BF16 matrix-core peak and against a
+    library GEMM measured in the same run (8192^3 BF16 torch.matmul), and its
+    bytes (24 in; 16 levels x 8 corners x 2 BF16 features gathered, 512; 1024
+    out) against HBM."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.randn(8192, 8192, device=dev).to(torch.bfloat16).contiguous()
+    b = torch.randn(8192, 8192, device=dev).to(torch.bfloat16).contiguous()
+    gms = _timed(lambda: torch.matmul(a, b), 5, 2)
+    del a, b
+    gemm = 2.0 * 8192 ** 3 / (gms * 1e-3) / 1e12
+    achieved = flops * n / (fwd_ms * 1e-3) / 1e12
+    nbytes = n * (24 + 512 + 1024)
+    return {"bound": "mfma", "kernel": "k_nn_infer (nn_forward)", "achieved": achieved, "peak": 2500.0,
+            "unit": "TFLOP/s", "frac": achieved / 2500.0, "gemm_tflops": gemm, "frac_of_gemm": achieved / gemm,
+            "bytes": {"bound": "hbm", "per_vertex": 24 + 512 + 1024, "achieved_gbs": nbytes / (fwd_ms * 1e-3) / 1e9,
+                      "peak": HBM_PEAK_GBS, "frac": nbytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def batching_section(w, svo, room, cam, cnrm, args):
