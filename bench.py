@@ -260,7 +260,7 @@ def main():
             "tile": tile,
         },
         "breakdown_ms": {"svo_accumulate": float(np.mean(acc_ms)), "guide_sample": gs_avg,
-                         "wall_per_step": wall / K * 1e3},
+                         "guide_sample_median": float(np.median(gs_ms)), "wall_per_step": wall / K * 1e3},
         "guide_samples_per_s": n / (gs_avg * 1e-3),
         "accumulate_roofline": {"bound": "hbm", "kernels": "k_splat + k_prop_leaf + k_prop_inner",
                                 "alg_bytes_per_call": acc_alg, "achieved": acc_alg / (acc_avg * 1e-3) / 1e9,
