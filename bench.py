@@ -41,7 +41,7 @@ CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "e57ad9ef99d63a4f7fc57d44b8ac42bfdd8a5143bd93ed07d3becfe206e098b3",
+    "sources_sha256": "44b92711d2de8f6e89bd45bc78471c1e002ceb160d3c5b572f008ec7b763004c",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
         "vop1/vop2/vopc (_e32)": (472, 2, ["add_e32", "xor_e32"]),
@@ -60,7 +60,7 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "e57ad9ef99d63a4f7fc57d44b8ac42bfdd8a5143bd93ed07d3becfe206e098b3",
+    "sources_sha256": "44b92711d2de8f6e89bd45bc78471c1e002ceb160d3c5b572f008ec7b763004c",
     "N": 16,
     "tile": {"waves_per_block": 4, "blocks_per_cu": 6},
     "bytes_per_launch": 4854690736,

@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 }
                 const auto nbr = [&](int ax, bool up) { return ((nbm >> (2 * ax + (up ? 1 : 0))) & 1u) != 0u; };
                 // First step of every bin of the new vertex by the whole wave,
-                // whatever ray a lane is marching (about three rays in four end
+                // whatever ray a lane is marching (about four rays in five end
                 // there: the leaf next to the origin, or out of the cube); the
                 // others are marked for the hand-out.
                 int npend = 0;
