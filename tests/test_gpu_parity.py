@@ -204,6 +204,25 @@ def test_guide_pdf_c1(c1, w, torch_dev):
         _pdf_compare(c1["o"], c1["g"], w, torch_dev, c1["pos"][:, :1024], N, name="guide_pdf C1")
 
 
+def test_guide_pdf_off_surface_and_on_planes(orc, c1, w, torch_dev):
+    """Vertices the first step of the guide kernel treats apart: points in
+    empty space (an empty origin leaf: every bin marched in full), points on
+    leaf corners (on the planes of every level, crossings at t = 0 into a
+    face neighbour) and points on the cube's faces (first crossing out of the
+    cube), against the oracle's guide_pdf."""
+    rng = np.random.default_rng(31)
+    D = 6
+    free = rng.random((3, 192))
+    corner = np.round(rng.random((3, 192)) * 2 ** D) / 2 ** D
+    face = rng.random((3, 96))
+    face[rng.integers(0, 3, 96), np.arange(96)] = rng.integers(0, 2, 96)
+    pos = np.ascontiguousarray(np.concatenate([free, corner, face], 1).astype(np.float32))
+    for N in (8, 16):
+        _pdf_compare(c1["o"], c1["g"], w, torch_dev, pos, N, name="guide_pdf off-surface C1")
+    _sample_compare(orc, c1["o"], c1["g"], w, torch_dev, pos, 16, seed=77, bounce=3,
+                    name="guide_sample off-surface C1")
+
+
 @pytest.mark.parametrize("N", [16, 32])
 def test_guide_pdf_c2(c2, w, torch_dev, N):
     """The frame-scale room at depth 10 with N = 16 (the benchmark's field)
