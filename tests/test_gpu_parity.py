@@ -223,6 +223,28 @@ def test_guide_pdf_off_surface_and_on_planes(orc, c1, w, torch_dev):
                     name="guide_sample off-surface C1")
 
 
+@pytest.mark.parametrize("D", [1, 2, 3, 4, 8])
+def test_guide_shallow_and_other_depths(orc, w, torch_dev, D):
+    """guide_pdf and guide_sample on SVOs of other depths than the two
+    configurations (depth 1 has no level-2 bitmap word; the first steps and
+    the three-level window work on shallow trees too) against the oracle,
+    for surface vertices and points anywhere in the cube."""
+    rs = synth.room(n_boxes=8)
+    o = orc.SVO(rs, D)
+    xyz, em = o.leaf_info()
+    sp = synth.leaf_splats(xyz, o.normals(D), em, D, seed=40 + D)
+    assert o.accumulate(*sp) == 0
+    o.propagate()
+    g = w.svo_build(rs, D)
+    w.svo_accumulate(g, *to_dev(torch_dev, *sp))
+    area, _, _ = synth.area_points(rs, 256, 50 + D)
+    free = np.random.default_rng(60 + D).random((3, 128))
+    pos = np.ascontiguousarray(np.concatenate([area, free], 1).astype(np.float32))
+    for N in (8, 16):
+        _pdf_compare(o, g, w, torch_dev, pos, N, name=f"guide_pdf D={D}")
+    _sample_compare(orc, o, g, w, torch_dev, pos, 16, seed=70 + D, bounce=1, name=f"guide_sample D={D}")
+
+
 @pytest.mark.parametrize("N", [16, 32])
 def test_guide_pdf_c2(c2, w, torch_dev, N):
     """The frame-scale room at depth 10 with N = 16 (the benchmark's field)
