@@ -29,9 +29,13 @@ Key key_of(const wfpg_svo *svo, int N)
 
 TileConfig default_tile(int N, int depth)
 {
+    // the tuner's usual picks on the frame-scale room: 24 waves per CU (six
+    // per SIMD, what the guide kernel's registers allow); at N = 16 in two
+    // blocks, whose two copies of the direction tables leave the LDS for
+    // five vertex slots per wave
     TileConfig t;
-    t.waves_per_block = 4;   // the tuner's usual pick for the frame-scale room at N = 16
-    t.blocks_per_cu = N == 32 ? 4 : 6;
+    t.waves_per_block = N == 16 ? 12 : 4;
+    t.blocks_per_cu = N == 16 ? 2 : (N == 32 ? 4 : 6);
     return legalize_tile(t, N, depth);
 }
 
@@ -129,8 +133,8 @@ wfpg_status wfpg_autotune(wfpg_svo *svo, const float *pos, int64_t n, int32_t N,
         a.err = svo->d_err;
         a.dir_out = d_dir;
         a.pdf_out = d_pdf;
-        const int waves[] = {1, 2, 4, 8, 16};
-        const int bpcu[] = {1, 2, 4, 8, 16};
+        const int waves[] = {1, 2, 3, 4, 6, 8, 12, 16};
+        const int bpcu[] = {1, 2, 3, 4, 6, 8, 12, 16};
         std::vector<TileConfig> cand;
         for (int w : waves)
             for (int b : bpcu) {

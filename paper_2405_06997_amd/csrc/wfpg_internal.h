@@ -112,8 +112,11 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
                         const TileConfig &tc, hipStream_t s);
 
 // LDS bytes of one guide block: bin directions and the per-wave hit records.
-// Query vertices a wave keeps in flight (hit records of each in LDS).
-__host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : 4; }
+// Query vertices a wave keeps in flight (hit records of each in LDS). A slot
+// stays taken until the last ray of its vertex ends, so with few slots a wave
+// runs out of bins to hand out while its slots drain; as many as the LDS holds
+// at six waves per SIMD (1 KiB of records per slot at N = 16, 256 B at N = 8).
+__host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : (N == 16 ? 5 : 8); }
 
 // 32-bit words of one bin's hit record: the debug mode keeps the raw
 // traversal record, every other mode the footprint node only.
