@@ -102,7 +102,7 @@ constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
 // of every bin from the hit records in `rec`, then the row / marginal CDFs
 // and the mode's output for vertex i. Returns the number of hit bins of this
 // lane (for the count mode).
-template <int N, int MODE, bool BLUR>
+template <int N, int MODE, bool BLUR, bool R24>
 __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, const float *ldir,
                                          uint32_t *rec, int64_t i, int64_t ps, int lane,
                                          int vis_lane)
@@ -133,6 +133,11 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
                 lf = D - k;
                 node = key >> (3 * k);
             }
+        } else if constexpr (R24) {           // footprint node's index + 1 (0: miss), 16 + 8 bits
+            const uint32_t r = (uint32_t)reinterpret_cast<const uint16_t *>(rec)[b] |
+                               ((uint32_t)reinterpret_cast<const uint8_t *>(rec)[2 * NN + b] << 16);
+            hit = r != 0u;
+            node = r - 1u;
         } else {                              // footprint node: 1 << 3*lf | key (0: miss)
             const uint32_t r = rec[b];
             hit = r != 0u;
@@ -142,10 +147,15 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
             }
         }
         if (hit) {
-            const uint32_t wi = woff(lf) + (node >> 6);
-            const uint64_t w = sv.bits[wi];
-            const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
-            const int64_t g = (int64_t)sv.rank[wi] + __popcll(msk);
+            int64_t g;
+            if constexpr (R24) {
+                g = (int64_t)node;
+            } else {
+                const uint32_t wi = woff(lf) + (node >> 6);
+                const uint64_t w = sv.bits[wi];
+                const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
+                g = (int64_t)sv.rank[wi] + __popcll(msk);
+            }
             const float4 Nn = sv.nrm[g];
             const int side = core::dot3(Nn.x, Nn.y, Nn.z, dx, dy, dz) < 0.f ? 0 : 1;
             if (fmt == WFPG_FP32) {
@@ -343,12 +353,14 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 // unrolled constants.
 // BLUR: the field is blurred before its CDF (a variant of its own: the blur's
 // registers would lower the occupancy of the unblurred kernel).
-template <int N, int MODE, bool BLUR>
+template <int N, int MODE, bool BLUR, bool R24>
 __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
 {
     constexpr int NN = N * N;
     constexpr int BPL = NN / 64;
-    constexpr int S = guide_slots(N);
+    constexpr int S = guide_slots(N, R24);
+    static_assert(!R24 || (N == 16 && !BLUR && (MODE == MODE_SAMPLE || MODE == MODE_PDF || MODE == MODE_EVAL)),
+                  "3-byte records: N = 16, sample / pdf / eval, no blur");
     extern __shared__ uint64_t smem[];
     if (a.gate && *a.gate == 0) return;   // uniform: every thread reads the same flag
     const int lane = threadIdx.x & 63;
@@ -356,16 +368,17 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     const int D = sv.depth;
     float *ldir = reinterpret_cast<float *>(smem);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
-    constexpr int RW = guide_rec_words(MODE);
+    constexpr int RW = guide_slot_words(N, MODE, R24) / NN;   // (unused with R24)
+    constexpr int SW = guide_slot_words(N, MODE, R24);         // 32-bit words of one slot's records
     const int nw = blockDim.x / 64;
-    uint32_t *recs = lq + 3 * NN + (size_t)wave * S * RW * NN;
-    uint32_t *svis = lq + 3 * NN + (size_t)nw * S * RW * NN + (size_t)wave * S;
+    uint32_t *recs = lq + 3 * NN + (size_t)wave * S * SW;
+    uint32_t *svis = lq + 3 * NN + (size_t)nw * S * SW + (size_t)wave * S;
     // per wave: the bins each slot still has to march, one 64-bit mask per
     // 64 bins (bit l of mask j: bin 64 j + l), and a 64-entry exchange buffer
     // through which the hand-out passes bins to idle lanes
-    uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) +
+    uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 1)) +
                       (size_t)wave * S * BPL;
-    uint64_t *pm_end = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (RW * NN + 1)) + (size_t)nw * S * BPL;
+    uint64_t *pm_end = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 1)) + (size_t)nw * S * BPL;
     uint16_t *xch = reinterpret_cast<uint16_t *>(pm_end) + (size_t)wave * 64;
     // per wave: the vertex of each slot and the fed vertex's origin (x, y, z,
     // leaf key | occupied << 31)
@@ -431,7 +444,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     // the record of a finished march (res: STEP_HIT or STEP_MISS) of bin b
     // of slot k whose vertex is v, with its node-test count pv
     auto finish = [&](const core::MicroState &ms, int res, int k, int b, int64_t v, int pv) {
-        uint32_t *rec = recs + k * RW * NN;
+        uint32_t *rec = recs + k * SW;
         const Hit h = res == core::STEP_HIT ? core::hit_of(ms, D) : Hit{-1, 0u, 0u};
         if constexpr (MODE == MODE_DEBUG) {
             rec[2 * b] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
@@ -444,8 +457,20 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                 const float dsel = ldir[3 * b + h.axis];
                 const int kk = core::footprint_levels(h.delta, fabsf(dsel), D, a.omega);
                 rv = (1u << (3 * (D - kk))) | (h.key >> (3 * kk));
+                if constexpr (R24) {   // the node's index + 1
+                    const uint32_t node = h.key >> (3 * kk);
+                    const uint32_t wi = woff(D - kk) + (node >> 6);
+                    const uint64_t w = gbits64[wi];
+                    const uint64_t msk = (node & 63) ? (w & ((1ull << (node & 63)) - 1)) : 0ull;
+                    rv = __builtin_launder(&s_sv)->rank[wi] + (uint32_t)__popcll(msk) + 1u;
+                }
             }
-            rec[b] = rv;
+            if constexpr (R24) {
+                reinterpret_cast<uint16_t *>(rec)[b] = (uint16_t)rv;
+                reinterpret_cast<uint8_t *>(rec)[2 * NN + b] = (uint8_t)(rv >> 16);
+            } else {
+                rec[b] = rv;
+            }
         }
         if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[k], (uint32_t)pv);
     };
@@ -462,7 +487,7 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             wave_lds_fence();
             vd = uni(svert[done]);
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
-            finalize<N, MODE, BLUR>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * RW * NN,
+            finalize<N, MODE, BLUR, R24>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * SW,
                                     vd, ps, lane, vl);
             wave_lds_fence();
 #pragma unroll
@@ -646,33 +671,40 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     GuideArgs a = a0;
     if (!a.queue_ctr)
         a.queue_ctr = svo->d_ctr + (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
+    const bool blur = a.blur != 0 && mode != MODE_DEBUG && mode != MODE_COUNT;
+    const bool r24 = guide_use_r24(N, mode, blur, svo->total_nodes);
     TileConfig t = tc;   // debug records are twice as large: shrink the workgroup if needed
-    while (t.waves_per_block > 1 && guide_lds_bytes(N, t, mode) > guide_max_lds()) --t.waves_per_block;
+    while (t.waves_per_block > 1 && guide_lds_bytes(N, t, mode, r24) > guide_max_lds()) --t.waves_per_block;
     const int W = t.waves_per_block;
     const int64_t want = a.n_dev ? INT64_MAX : ((a.n + kChunk - 1) / kChunk + W - 1) / W;
     const int64_t cap = (int64_t)device_cu_count() * t.blocks_per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    const size_t lds = guide_lds_bytes(N, t, mode);
+    const size_t lds = guide_lds_bytes(N, t, mode, r24);
     if (lds > guide_max_lds()) return hipErrorInvalidValue;
     const dim3 blk(64 * W);
     const wfpg::SvoView v = svo->view();
-    const bool blur = a.blur != 0 && mode != MODE_DEBUG && mode != MODE_COUNT;
     const void *fn = nullptr;
 #define WFPG_PICK(M)                                                                      \
-    fn = blur ? (const void *)&k_guide<N, M, true> : (const void *)&k_guide<N, M, false>
+    fn = blur ? (const void *)&k_guide<N, M, true, false> : (const void *)&k_guide<N, M, false, false>
+#define WFPG_PICK24(M)                                                                    \
+    if constexpr (N == 16) {                                                              \
+        if (r24) fn = (const void *)&k_guide<N, M, false, true>;                          \
+    }
     switch (mode) {
-    case MODE_SAMPLE: WFPG_PICK(MODE_SAMPLE); break;
-    case MODE_PDF: WFPG_PICK(MODE_PDF); break;
-    case MODE_EVAL: WFPG_PICK(MODE_EVAL); break;
+    case MODE_SAMPLE: WFPG_PICK(MODE_SAMPLE); WFPG_PICK24(MODE_SAMPLE); break;
+    case MODE_PDF: WFPG_PICK(MODE_PDF); WFPG_PICK24(MODE_PDF); break;
+    case MODE_EVAL: WFPG_PICK(MODE_EVAL); WFPG_PICK24(MODE_EVAL); break;
     case MODE_PRODUCT: WFPG_PICK(MODE_PRODUCT); break;
     case MODE_PEVAL: WFPG_PICK(MODE_PEVAL); break;
-    case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT, false>; break;
-    default: fn = (const void *)&k_guide<N, MODE_DEBUG, false>; break;
+    case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT, false, false>; break;
+    default: fn = (const void *)&k_guide<N, MODE_DEBUG, false, false>; break;
     }
 #undef WFPG_PICK
+#undef WFPG_PICK24
     if (lds > 64 * 1024) {   // opt in to the device's whole LDS once per kernel
-        static std::atomic<bool> opted[2 * MODE_COUNT_OF_MODES];
-        const int m = (mode < 0 || mode >= MODE_COUNT_OF_MODES ? MODE_DEBUG : mode) * 2 + (blur ? 1 : 0);
+        static std::atomic<bool> opted[4 * MODE_COUNT_OF_MODES];
+        const int m = ((mode < 0 || mode >= MODE_COUNT_OF_MODES ? MODE_DEBUG : mode) * 2 + (blur ? 1 : 0)) * 2 +
+                      (r24 ? 1 : 0);
         if (!opted[m].load()) {
             const hipError_t e =
                 hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)guide_max_lds());

@@ -115,20 +115,40 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
 // Query vertices a wave keeps in flight (hit records of each in LDS). A slot
 // stays taken until the last ray of its vertex ends, so with few slots a wave
 // runs out of bins to hand out while its slots drain; as many as the LDS holds
-// at six waves per SIMD (1 KiB of records per slot at N = 16, 256 B at N = 8).
-__host__ __device__ constexpr int guide_slots(int N) { return N >= 32 ? 2 : (N == 16 ? 5 : 8); }
+// at six waves per SIMD (1 KiB of records per slot at N = 16, 256 B at N = 8;
+// 768 B at N = 16 with 3-byte records).
+__host__ __device__ constexpr int guide_slots(int N, bool r24 = false)
+{
+    return N >= 32 ? 2 : (N == 16 ? (r24 ? 7 : 5) : 8);
+}
 
 // 32-bit words of one bin's hit record: the debug mode keeps the raw
 // traversal record, every other mode the footprint node only.
 __host__ __device__ constexpr int guide_rec_words(int mode) { return mode == MODE_DEBUG ? 2 : 1; }
 
-inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE)
+// 32-bit words of one slot's records: with r24 a record is the footprint
+// node's index + 1 (0: miss) in 3 bytes, a 16-bit and an 8-bit array of NN.
+__host__ __device__ constexpr int guide_slot_words(int N, int mode, bool r24)
 {
-    const size_t S = (size_t)guide_slots(N), NN = (size_t)N * N;
+    return r24 ? 3 * N * N / 4 : guide_rec_words(mode) * N * N;
+}
+
+// 3-byte records: at N = 16 in the modes whose finalization keeps nothing
+// else in the slot (sample, pdf, eval without blur), for SVOs whose node
+// indices + 1 fit 24 bits.
+inline bool guide_use_r24(int N, int mode, bool blur, int64_t total_nodes)
+{
+    return N == 16 && !blur && (mode == MODE_SAMPLE || mode == MODE_PDF || mode == MODE_EVAL) &&
+           total_nodes < (int64_t)0xffffff;
+}
+
+inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE, bool r24 = false)
+{
+    const size_t S = (size_t)guide_slots(N, r24), NN = (size_t)N * N;
     return NN * 3 * 4 * 2 +
-           (size_t)tc.waves_per_block * (S * ((size_t)guide_rec_words(mode) * NN * 4 + 4) +   // records, counts
-                                         S * (NN / 64) * 8 + 64 * 2 +                        // bin masks, exchange
-                                         S * 8 + 4 * 4);                                     // slot vertices, origin
+           (size_t)tc.waves_per_block * (S * ((size_t)guide_slot_words(N, mode, r24) * 4 + 4) +   // records, counts
+                                         S * (NN / 64) * 8 + 64 * 2 +                            // bin masks, exchange
+                                         S * 8 + 4 * 4);                                         // slot vertices, origin
 }
 // Dynamic LDS a guide workgroup may use on the current device (all modes but
 // debug): the device's per-workgroup LDS less kGuideStaticLds, a bound on the

@@ -245,6 +245,27 @@ def test_guide_shallow_and_other_depths(orc, w, torch_dev, D):
     _sample_compare(orc, o, g, w, torch_dev, pos, 16, seed=70 + D, bounce=1, name=f"guide_sample D={D}")
 
 
+def test_guide_large_svo_four_byte_records(orc, w, torch_dev):
+    """A room with 400 boxes at depth 10: 22 M nodes, more than 3-byte hit
+    records can index, so N = 16 keeps 4-byte records (and five vertex
+    slots); guide_pdf and guide_sample against the oracle."""
+    rs = synth.room(n_boxes=400)
+    o = orc.SVO(rs, 10)
+    assert sum(o.level_sizes()) >= 0xffffff
+    sp = synth.room_splats(rs, 1_000_000, 17)
+    o.accumulate(*sp)
+    o.propagate()
+    g = w.svo_build(rs, 10)
+    w.svo_accumulate(g, *to_dev(torch_dev, *sp))
+    assert g.stats()["nodes"] == sum(o.level_sizes())
+    _, _, cnt = o.leaf_accum()
+    C = int(max(1, cnt.max()))
+    pos, _, _ = synth.area_points(rs, 192, 18)
+    _pdf_compare(o, g, w, torch_dev, pos, 16, C, name="guide_pdf 22M-node room")
+    _sample_compare(orc, o, g, w, torch_dev, pos, 16, seed=19, bounce=0, C=C, name="guide_sample 22M-node room")
+    del o, g
+
+
 @pytest.mark.parametrize("N", [16, 32])
 def test_guide_pdf_c2(c2, w, torch_dev, N):
     """The frame-scale room at depth 10 with N = 16 (the benchmark's field)
