@@ -353,8 +353,11 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 // unrolled constants.
 // BLUR: the field is blurred before its CDF (a variant of its own: the blur's
 // registers would lower the occupancy of the unblurred kernel).
+// At N = 16 the register allocation is held to six waves per SIMD (80 VGPRs;
+// a few bytes of spills): left free it takes one register more and five.
 template <int N, int MODE, bool BLUR, bool R24>
-__global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(N == 16 ? 6 : 1)))
+k_guide(SvoView sv, GuideArgs a)
 {
     constexpr int NN = N * N;
     constexpr int BPL = NN / 64;
@@ -373,12 +376,14 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     const int nw = blockDim.x / 64;
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * SW;
     uint32_t *svis = lq + 3 * NN + (size_t)nw * S * SW + (size_t)wave * S;
+    // per wave: the bins each slot has not finished yet (-1: the slot is free)
+    int *srem = reinterpret_cast<int *>(lq + 3 * NN + (size_t)nw * S * SW + (size_t)nw * S) + (size_t)wave * S;
     // per wave: the bins each slot still has to march, one 64-bit mask per
     // 64 bins (bit l of mask j: bin 64 j + l), and a 64-entry exchange buffer
     // through which the hand-out passes bins to idle lanes
-    uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 1)) +
+    uint64_t *pmask = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 2)) +
                       (size_t)wave * S * BPL;
-    uint64_t *pm_end = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 1)) + (size_t)nw * S * BPL;
+    uint64_t *pm_end = reinterpret_cast<uint64_t *>(lq + 3 * NN + (size_t)nw * S * (SW + 2)) + (size_t)nw * S * BPL;
     uint16_t *xch = reinterpret_cast<uint16_t *>(pm_end) + (size_t)wave * 64;
     // per wave: the vertex of each slot and the fed vertex's origin (x, y, z,
     // leaf key | occupied << 31)
@@ -430,12 +435,11 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     int64_t chunk_next = 0;
     int chunk_left = 0;
     bool exhausted = false;
-    // bins of each slot not yet finished (-1: the slot is free); the slots'
-    // vertices and the fed vertex's origin live in LDS (scalar registers are
-    // the kernel's scarcest resource)
-    int rem[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) rem[k] = -1;
+    // the bins each slot has not finished, the slots' vertices and the fed
+    // vertex's origin live in LDS (scalar registers are the kernel's scarcest
+    // resource); a finishing lane takes its bin off its slot's count
+    if (lane < S) srem[lane] = -1;
+    wave_lds_fence();
     int feed = -1, nxt = BPL;            // slot being handed out and its mask of bins being handed out
     // per-lane march state
     int lslot = 0, lbin = -1, vis = 0, iters = 0;
@@ -478,31 +482,25 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
     while (true) {
         // finalize every slot whose bins are all finished
         while (true) {
-            int done = -1;
             int64_t vd = 0;
-#pragma unroll
-            for (int k = 0; k < S; ++k)
-                if (done < 0 && rem[k] == 0) done = k;
-            if (done < 0) break;
-            wave_lds_fence();
+            const uint64_t zr = __ballot(lane < S && srem[lane] == 0);
+            if (zr == 0ull) break;
+            const int done = uni((int)__builtin_ctzll(zr));
             vd = uni(svert[done]);
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
             finalize<N, MODE, BLUR, R24>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * SW,
                                     vd, ps, lane, vl);
             wave_lds_fence();
-#pragma unroll
-            for (int k = 0; k < S; ++k)
-                if (k == done) rem[k] = -1;
+            if (lane == 0) srem[done] = -1;
+            wave_lds_fence();
         }
         // hand out bins to idle lanes
         uint64_t idle = __ballot(lbin < 0);
         while (idle) {
             if (feed < 0 || nxt >= BPL) {
-                int f = -1;
-#pragma unroll
-                for (int k = 0; k < S; ++k)
-                    if (f < 0 && rem[k] < 0) f = k;
-                if (f < 0 || exhausted) break;
+                const uint64_t fr = __ballot(lane < S && srem[lane] < 0);
+                if (fr == 0ull || exhausted) break;
+                const int f = uni((int)__builtin_ctzll(fr));
                 if (chunk_left == 0) {
                     int64_t b = 0;
                     if (lane == 0) b = (int64_t)atomicAdd(a.queue_ctr, (unsigned long long)kChunk);
@@ -578,10 +576,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
                     if (lane == 0) pmask[f * BPL + j] = pm;
                     npend += (int)__popcll(pm);
                 }
+                if (lane == 0) srem[f] = npend;
                 wave_lds_fence();
-#pragma unroll
-                for (int k = 0; k < S; ++k)
-                    if (k == f) rem[k] = uni(npend);
                 feed = f;
                 nxt = 0;
             }
@@ -619,12 +615,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             wave_lds_fence();
         }
         if (__ballot(lbin >= 0) == 0ull) {
-            bool any = false, ready = false;
-#pragma unroll
-            for (int k = 0; k < S; ++k) {
-                any = any || rem[k] >= 0;
-                ready = ready || rem[k] == 0;
-            }
+            const int rk = lane < S ? srem[lane] : -1;
+            const bool any = __ballot(rk >= 0) != 0ull, ready = __ballot(rk == 0) != 0ull;
             if (!any) break;
             if (!ready) {
                 atomicOr(a.err, 2);   // no progress possible (never expected)
@@ -652,10 +644,8 @@ __global__ void __launch_bounds__(1024) k_guide(SvoView sv, GuideArgs a)
             finish(st, res, lslot, lbin, vl, vis);
             lbin = -1;
         }
-        if (__ballot(fin)) {
-#pragma unroll
-            for (int k = 0; k < S; ++k) rem[k] = uni(rem[k] - __popcll(__ballot(fin && lslot == k)));
-        }
+        if (fin) atomicSub(&srem[lslot], 1);
+        wave_lds_fence();
     }
 }
 

@@ -146,7 +146,7 @@ inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPL
 {
     const size_t S = (size_t)guide_slots(N, r24), NN = (size_t)N * N;
     return NN * 3 * 4 * 2 +
-           (size_t)tc.waves_per_block * (S * ((size_t)guide_slot_words(N, mode, r24) * 4 + 4) +   // records, counts
+           (size_t)tc.waves_per_block * (S * ((size_t)guide_slot_words(N, mode, r24) * 4 + 8) +   // records, counts
                                          S * (NN / 64) * 8 + 64 * 2 +                            // bin masks, exchange
                                          S * 8 + 4 * 4);                                         // slot vertices, origin
 }
