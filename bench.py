@@ -41,7 +41,7 @@ CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "01ea9fa0ad5d37f8682591adc2170248fc0cc2954603bf86dd6b6633c1e30086",
+    "sources_sha256": "b56b18fede07f8d5651cd744325f392ec04a6df19f9f283e43ef5c469a49b702",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
         "vop1/vop2/vopc (_e32)": (461, 2, ["add_e32", "xor_e32"]),
@@ -60,7 +60,7 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "01ea9fa0ad5d37f8682591adc2170248fc0cc2954603bf86dd6b6633c1e30086",
+    "sources_sha256": "b56b18fede07f8d5651cd744325f392ec04a6df19f9f283e43ef5c469a49b702",
     "N": 16,
     "tile": {"waves_per_block": 12, "blocks_per_cu": 2},
     "bytes_per_launch": 5248890525,

@@ -337,19 +337,22 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 }
 
 // LDS layout of a block: [N*N*3 bin directions]
-// [N*N*3 quantized directions |q| | sign << 31][per wave: kSlots vertex
-// slots x N*N hit records][per wave: kSlots node-test counters (count
-// mode)]. A hit record is the node the cone footprint selects, as
-// 1 << 3*level | key (0 for a miss); the debug mode keeps the raw traversal
-// record {key | axis << 30, |B - O|} instead.
+// [N*N*3 quantized directions |q| | sign << 31][per wave: S vertex slots x
+// N*N hit records][per wave: S node-test counters (count mode)][per wave: S
+// unfinished-bin counts][per wave: S x N*N/64 pending-bin masks][per wave:
+// 64-entry exchange][per wave: S slot vertices][per wave: the fed vertex's
+// origin]. A hit record is the node the cone footprint selects, as
+// 1 << 3*level | key (0 for a miss), or with R24 that node's index + 1 in a
+// 16-bit and an 8-bit array; the debug mode keeps the raw traversal record
+// {key | axis << 30, |B - O|} instead.
 //
-// A wave keeps up to kSlots query vertices in flight. Idle lanes take the
-// next unmarched bin of the vertex being fed; when it has no bins left a
-// free slot is opened for the next vertex of the queue (taken from a device
-// counter, kChunk at a time), so lanes rarely wait for another vertex's
-// longest rays. A slot whose bins are all finished is finalized by the whole
-// wave (values, CDF, sample) and freed. Slot bookkeeping is wave-uniform and
-// lives in scalar registers; the arrays below are only ever indexed by
+// A wave keeps up to S = guide_slots(N, R24) query vertices in flight. Idle
+// lanes take the next unmarched bin of the vertex being fed; when it has no
+// bins left a free slot is opened for the next vertex of the queue (taken
+// from a device counter, kChunk at a time), so lanes rarely wait for another
+// vertex's longest rays. A slot whose bins are all finished is finalized by
+// the whole wave (values, CDF, sample) and freed. Slot bookkeeping is
+// wave-uniform; the per-slot arrays in registers are only ever indexed by
 // unrolled constants.
 // BLUR: the field is blurred before its CDF (a variant of its own: the blur's
 // registers would lower the occupancy of the unblurred kernel).
