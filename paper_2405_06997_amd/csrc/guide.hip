@@ -450,9 +450,8 @@ k_guide(SvoView sv, GuideArgs a)
 
     // the record of a finished march (res: STEP_HIT or STEP_MISS) of bin b
     // of slot k whose vertex is v, with its node-test count pv
-    auto finish = [&](const core::MicroState &ms, int res, int k, int b, int64_t v, int pv) {
+    auto finish_hit = [&](int res, const Hit &h, int k, int b, int64_t v, int pv) {
         uint32_t *rec = recs + k * SW;
-        const Hit h = res == core::STEP_HIT ? core::hit_of(ms, D) : Hit{-1, 0u, 0u};
         if constexpr (MODE == MODE_DEBUG) {
             rec[2 * b] = res == core::STEP_HIT ? (h.key | ((uint32_t)h.axis << 30)) : kMissRec;
             rec[2 * b + 1] = h.delta;
@@ -480,6 +479,9 @@ k_guide(SvoView sv, GuideArgs a)
             }
         }
         if constexpr (MODE == MODE_COUNT) atomicAdd(&svis[k], (uint32_t)pv);
+    };
+    auto finish = [&](const core::MicroState &ms, int res, int k, int b, int64_t v, int pv) {
+        finish_hit(res, res == core::STEP_HIT ? core::hit_of(ms, D) : Hit{-1, 0u, 0u}, k, b, v, pv);
     };
 
     while (true) {
@@ -531,16 +533,22 @@ k_guide(SvoView sv, GuideArgs a)
                     if (lane == 0) svis[f] = 0u;
                     wave_lds_fence();
                 }
-                // Without node-test counts, a vertex whose leaf is occupied
-                // takes its first steps from the occupancy of the leaf's six
-                // face neighbours (lane 2j + up tests the one along axis j),
-                // read once for all its bins; with an empty leaf every bin
-                // starts in the hand-out.
+                // First step of every bin of the new vertex by the whole wave,
+                // whatever ray a lane is marching (about four rays in five end
+                // there: they enter an occupied face neighbour of the origin's
+                // leaf, or leave the cube); the others are marked for the
+                // hand-out. Without node-test counts, a vertex whose leaf is
+                // occupied takes it from the leaf's six face neighbours (lane
+                // 2j + up reads the one along axis j: its key, whether it lies
+                // in the cube, whether it is occupied), read once for all its
+                // bins, and the exit crossing of each bin, with no march state;
+                // with an empty leaf every bin starts in the hand-out.
                 constexpr bool kNbrStep = MODE != MODE_DEBUG && MODE != MODE_COUNT;
-                const bool nbr_step = kNbrStep && uni((int)oc) != 0;
-                uint32_t nbm = 0u;
-                if (nbr_step) {
-                    bool on = false;
+                int npend = 0;
+                if constexpr (kNbrStep) {
+                    const bool nbr_step = uni((int)oc) != 0;
+                    uint32_t nkey = 0u;
+                    bool nin = false, non = false;
                     if (lane < 6) {
                         const int ax = lane >> 1;
                         uint32_t c0 = O[0] >> (WFPG_FINE - D), c1 = O[1] >> (WFPG_FINE - D),
@@ -550,34 +558,55 @@ k_guide(SvoView sv, GuideArgs a)
                         c0 = ax == 0 ? nj : c0;
                         c1 = ax == 1 ? nj : c1;
                         c2 = ax == 2 ? nj : c2;
-                        on = nj < (1u << D) && core::occupied(bits, D, core::morton3(c0, c1, c2));
+                        nin = nj < (1u << D);
+                        nkey = core::morton3(c0, c1, c2);
+                        non = nin && core::occupied(bits, D, nkey);
                     }
-                    nbm = (uint32_t)__ballot(on);
-                }
-                const auto nbr = [&](int ax, bool up) { return ((nbm >> (2 * ax + (up ? 1 : 0))) & 1u) != 0u; };
-                // First step of every bin of the new vertex by the whole wave,
-                // whatever ray a lane is marching (about four rays in five end
-                // there: the leaf next to the origin, or out of the cube); the
-                // others are marked for the hand-out.
-                int npend = 0;
+                    const uint32_t inm = (uint32_t)__ballot(nin), onm = (uint32_t)__ballot(non);
+                    core::FirstLeaf fl = core::first_leaf(O, D);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {   // the same on every lane
+                        fl.up[k] = uni(fl.up[k]);
+                        fl.dn[k] = uni(fl.dn[k]);
+                    }
 #pragma unroll 1
-                for (int j = 0; j < BPL; ++j) {
-                    const int b = j * 64 + lane;
-                    const uint32_t w0 = lq[3 * b], w1 = lq[3 * b + 1], w2 = lq[3 * b + 2];
-                    const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
-                    core::MicroState ms;
-                    int pv = 0;
-                    core::micro_begin(ms, O, okey, oc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
-                                      a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, pv);
-                    int r1;
-                    if constexpr (kNbrStep)   // an empty origin leaf: every bin goes to the hand-out
-                        r1 = nbr_step ? core::first_step(ms, D, nbr) : core::STEP_CONTINUE;
-                    else
-                        r1 = core::micro_step(ms, D, bits64, 5, pv);
-                    if (r1 != core::STEP_CONTINUE) finish(ms, r1, f, b, vi, pv);
-                    const uint64_t pm = __ballot(r1 == core::STEP_CONTINUE);
-                    if (lane == 0) pmask[f * BPL + j] = pm;
-                    npend += (int)__popcll(pm);
+                    for (int j = 0; j < BPL; ++j) {
+                        const int b = j * 64 + lane;
+                        const uint32_t w0 = lq[3 * b], w1 = lq[3 * b + 1], w2 = lq[3 * b + 2];
+                        const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
+                        int e;
+                        bool up;
+                        uint32_t delta;
+                        core::first_exit(fl, a0, a1, a2, a0 && (w0 >> 31), a1 && (w1 >> 31), a2 && (w2 >> 31), e, up,
+                                         delta);
+                        const int idx = 2 * e + (up ? 1 : 0);
+                        const uint32_t hkey = (uint32_t)__shfl((int)nkey, idx);
+                        const int r1 = !nbr_step ? core::STEP_CONTINUE
+                                                 : (((inm >> idx) & 1u) == 0u ? core::STEP_MISS
+                                                                              : (((onm >> idx) & 1u) != 0u
+                                                                                     ? core::STEP_HIT
+                                                                                     : core::STEP_CONTINUE));
+                        if (r1 != core::STEP_CONTINUE) finish_hit(r1, Hit{e, hkey, delta}, f, b, vi, 0);
+                        const uint64_t pm = __ballot(r1 == core::STEP_CONTINUE);
+                        if (lane == 0) pmask[f * BPL + j] = pm;
+                        npend += (int)__popcll(pm);
+                    }
+                } else {
+#pragma unroll 1
+                    for (int j = 0; j < BPL; ++j) {
+                        const int b = j * 64 + lane;
+                        const uint32_t w0 = lq[3 * b], w1 = lq[3 * b + 1], w2 = lq[3 * b + 2];
+                        const uint32_t a0 = w0 & 0x7fffffffu, a1 = w1 & 0x7fffffffu, a2 = w2 & 0x7fffffffu;
+                        core::MicroState ms;
+                        int pv = 0;
+                        core::micro_begin(ms, O, okey, oc, a0, a1, a2, a0 ? ((w0 >> 31) ? -1 : 1) : 0,
+                                          a1 ? ((w1 >> 31) ? -1 : 1) : 0, a2 ? ((w2 >> 31) ? -1 : 1) : 0, D, 5, pv);
+                        const int r1 = core::micro_step(ms, D, bits64, 5, pv);
+                        if (r1 != core::STEP_CONTINUE) finish(ms, r1, f, b, vi, pv);
+                        const uint64_t pm = __ballot(r1 == core::STEP_CONTINUE);
+                        if (lane == 0) pmask[f * BPL + j] = pm;
+                        npend += (int)__popcll(pm);
+                    }
                 }
                 if (lane == 0) srem[f] = npend;
                 wave_lds_fence();

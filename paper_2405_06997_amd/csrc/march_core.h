@@ -319,6 +319,41 @@ WFPG_HD int first_step(MicroState &s, int D, const Nbr &nbr)
     return nbr(x.e, ((s.mir >> x.e) & 1u) == 0u) ? STEP_HIT : STEP_CONTINUE;
 }
 
+// The same first step from per-origin and per-direction quantities, with no
+// march state: first_leaf gives, per origin, the distance from O to the
+// leaf's upper face (up) and lower face (dn) on each axis (2^-30 units);
+// first_exit, per direction (|q| and q < 0 per axis), the exit axis e,
+// whether the crossing goes towards larger coordinates, and |B - O| along e
+// -- the values first_step computes in its mirrored frame (the lower face of
+// a mirrored axis is its upper face there), by the same comparisons.
+struct FirstLeaf {
+    uint32_t up[3], dn[3];
+};
+WFPG_HD FirstLeaf first_leaf(const uint32_t O[3], int D)
+{
+    const uint32_t leaf = 1u << (kFine - D), mk = ~(leaf - 1u);
+    FirstLeaf f;
+    WFPG_UNROLL
+    for (int j = 0; j < 3; ++j) {
+        f.up[j] = (O[j] & mk) + leaf - O[j];
+        f.dn[j] = O[j] - (O[j] & mk);
+    }
+    return f;
+}
+WFPG_HD void first_exit(const FirstLeaf &f, uint32_t aq0, uint32_t aq1, uint32_t aq2, bool n0, bool n1, bool n2,
+                        int &e, bool &up, uint32_t &delta)
+{
+    const uint32_t dl0 = n0 ? f.dn[0] : f.up[0];
+    const uint32_t dl1 = n1 ? f.dn[1] : f.up[1];
+    const uint32_t dl2 = n2 ? f.dn[2] : f.up[2];
+    const bool c1 = (uint64_t)dl1 * aq0 < (uint64_t)dl0 * aq1;   // axis 1 before axis 0
+    const uint32_t d01 = c1 ? dl1 : dl0, q01 = c1 ? aq1 : aq0;
+    const bool c2 = (uint64_t)dl2 * q01 < (uint64_t)d01 * aq2;   // axis 2 before both
+    e = c2 ? 2 : (c1 ? 1 : 0);
+    delta = c2 ? dl2 : d01;
+    up = !(c2 ? n2 : (c1 ? n1 : n0));
+}
+
 // The hit of a march whose last step returned STEP_HIT: the crossing axis, the
 // leaf key in the original frame, and |B - O| of the crossing.
 WFPG_HD Hit hit_of(const MicroState &s, int D)

@@ -89,7 +89,8 @@ extern "C" int host_footprint_levels(uint32_t delta, float dabs, int D, float om
 // leaf's face neighbours (first_step), per (point, direction) pair: out =
 // {result, axis, key, delta} with result 1 hit, 2 miss, 0 continue (axis, key
 // and delta then those of the crossing into the empty neighbour), -1 when the
-// origin leaf is empty (no first step taken).
+// origin leaf is empty (no first step taken), -2 when the same step taken with
+// no march state (first_leaf, first_exit) disagrees.
 extern "C" void host_first_step_dirs(const uint64_t *bits, int D, const float *pos, int64_t n, const float *dirs,
                                      int nd, int64_t *out)
 {
@@ -125,6 +126,17 @@ extern "C" void host_first_step_dirs(const uint64_t *bits, int D, const float *p
             o[1] = r == STEP_MISS ? -1 : h.axis;
             o[2] = r == STEP_MISS ? -1 : (int64_t)h.key;
             o[3] = r == STEP_MISS ? -1 : (int64_t)h.delta;
+            // the same step with no march state (first_leaf, first_exit) must agree
+            int e;
+            bool up;
+            uint32_t delta;
+            first_exit(first_leaf(O, D), aq[0], aq[1], aq[2], sg[0] < 0, sg[1] < 0, sg[2] < 0, e, up, delta);
+            uint32_t cc[3] = {c[0], c[1], c[2]};
+            cc[e] = up ? cc[e] + 1u : cc[e] - 1u;
+            const bool inside = cc[e] < (1u << D);
+            const uint32_t nk = morton3(cc[0], cc[1], cc[2]);
+            const int r2 = !inside ? STEP_MISS : (occupied(load, D, nk) ? STEP_HIT : STEP_CONTINUE);
+            if (r2 != r || (r != STEP_MISS && (e != h.axis || nk != h.key || delta != h.delta))) o[0] = -2;
         }
     }
 }
