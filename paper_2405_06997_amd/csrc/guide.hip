@@ -508,7 +508,7 @@ k_guide(SvoView sv, GuideArgs a)
                 const int f = uni((int)__builtin_ctzll(fr));
                 if (chunk_left == 0) {
                     int64_t b = 0;
-                    if (lane == 0) b = (int64_t)atomicAdd(a.queue_ctr, (unsigned long long)kChunk);
+                    if (lane == 0) b = (int64_t)atomicAdd(__builtin_launder(&s_a)->queue_ctr, (unsigned long long)kChunk);
                     b = uni(shfl64(b, 0));
                     if (b >= n) { exhausted = true; break; }
                     chunk_next = b;
@@ -518,7 +518,7 @@ k_guide(SvoView sv, GuideArgs a)
                 --chunk_left;
                 uint32_t O[3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(a.pos[k * ps + vi]);
+                for (int k = 0; k < 3; ++k) O[k] = core::quantize_pos(__builtin_launder(&s_a)->pos[k * ps + vi]);
                 const uint32_t okey = core::morton3(O[0] >> (WFPG_FINE - D), O[1] >> (WFPG_FINE - D),
                                                     O[2] >> (WFPG_FINE - D));
                 const bool oc = core::occupied(bits, D, okey);
@@ -651,7 +651,7 @@ k_guide(SvoView sv, GuideArgs a)
             const bool any = __ballot(rk >= 0) != 0ull, ready = __ballot(rk == 0) != 0ull;
             if (!any) break;
             if (!ready) {
-                atomicOr(a.err, 2);   // no progress possible (never expected)
+                atomicOr(__builtin_launder(&s_a)->err, 2);   // no progress possible (never expected)
                 break;
             }
             continue;
@@ -666,7 +666,7 @@ k_guide(SvoView sv, GuideArgs a)
                 if (res != core::STEP_CONTINUE) break;
             }
             if (res == core::STEP_CONTINUE && (iters += kMicro) >= core::kMaxTests) {
-                atomicOr(a.err, 1);
+                atomicOr(__builtin_launder(&s_a)->err, 1);
                 res = core::STEP_MISS;
             }
         }
