@@ -34,20 +34,20 @@ CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 # encoding and 64-bit forms (16 lanes per clock). The issue probe
 # (libwfpg_probe.so, four waves per SIMD on one CU), run live and reported
 # beside it, measures every form at or above these costs except v_bitop3_b32
-# (about 3 cycles; 48 of the 1,291 instructions below, counted at 4).
+# (about 3 cycles; 48 of the 1,275 instructions below, counted at 4).
 # The mix is counted in the compiler listing (hipcc -S of guide.hip) of the
-# eight unrolled steps of the pool loop of k_guide<16, SAMPLE, no blur> (1,291
+# eight unrolled steps of the pool loop of k_guide<16, SAMPLE, no blur> (1,275
 # VALU instructions) and describes the sources below only.
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "fe9dfff582fd6164cc0ade1289ed467631f6ac2c0793463ef41ea3091fd05037",
+    "sources_sha256": "a8b953d18c8ef594b8d7c4cc4bc8be0f0c534335fc261ff7b52e48dedfad6587",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
-        "vop1/vop2/vopc (_e32)": (461, 2, ["add_e32", "xor_e32"]),
+        "vop1/vop2/vopc (_e32)": (460, 2, ["add_e32", "xor_e32"]),
         "v_cndmask_b32_e64": (320, 4, ["cndmask_e64"]),
-        "other three-operand 32-bit": (210, 4, ["bitop3", "lshl_e64"]),
-        "32-bit compares into an SGPR pair": (132, 4, ["cmp_e64"]),
+        "other three-operand 32-bit": (196, 4, ["bitop3", "lshl_e64"]),
+        "32-bit compares into an SGPR pair": (131, 4, ["cmp_e64"]),
         "v_mad_u64_u32 / v_mad_i64_i32": (88, 4, ["mad_u64"]),
         "64-bit compares": (48, 4, ["cmp64_e64"]),
         "v_lshl_add_u64": (32, 4, ["lshl_add_u64"]),
@@ -60,11 +60,11 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "fe9dfff582fd6164cc0ade1289ed467631f6ac2c0793463ef41ea3091fd05037",
+    "sources_sha256": "a8b953d18c8ef594b8d7c4cc4bc8be0f0c534335fc261ff7b52e48dedfad6587",
     "N": 16,
     "tile": {"waves_per_block": 12, "blocks_per_cu": 2},
-    "bytes_per_launch": 5235339553,
-    "valu_wave_instrs_per_launch": 12371991006,
+    "bytes_per_launch": 5032544823,
+    "valu_wave_instrs_per_launch": 12454616603,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 
