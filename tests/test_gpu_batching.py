@@ -69,14 +69,26 @@ def test_autotune_and_tiles(env):
     torch, dev, w, room, g, sp = env
     pos = torch.from_numpy(synth.area_points(room, 20000, 3)[0]).to(dev)
     ref_d, ref_p = w.guide_sample(g, pos, w.make_opts(N=16), seed=1, bounce=0)
+    pos2k = pos[:, :2000].contiguous()
+    pos4k = pos[:, :4000].contiguous()
+    ref_pdf = w.guide_pdf(g, pos2k, w.make_opts(N=16))
+    ref_other = {N: w.guide_sample(g, pos4k, w.make_opts(N=N), seed=1, bounce=0) for N in (8, 32)}
     best = w.autotune(g, pos, 16, reps=1)
     assert best["ms"] > 0
     assert w.get_tile(g, 16)["waves_per_block"] == best["waves_per_block"]
-    # results do not depend on the launch shape
-    for tile in [(1, 2), (6, 16), (4, 8), (2, 4), (16, 2)]:
+    # results do not depend on the launch shape (odd wave counts too: the
+    # per-wave LDS arrays stay aligned whatever the slot count)
+    for tile in [(1, 2), (6, 16), (4, 8), (2, 4), (16, 2), (3, 8), (5, 4), (7, 3)]:
         w.set_tile(g, 16, *tile)
         d, p = w.guide_sample(g, pos, w.make_opts(N=16), seed=1, bounce=0)
         assert torch.equal(d, ref_d) and torch.equal(p, ref_p)
+        pp = w.guide_pdf(g, pos2k, w.make_opts(N=16))
+        assert torch.equal(pp, ref_pdf)
+    for tile in [(3, 8), (5, 4)]:   # N = 8 (eight slots) and N = 32 (two)
+        for N in (8, 32):
+            w.set_tile(g, N, *tile)
+            d, p = w.guide_sample(g, pos4k, w.make_opts(N=N), seed=1, bounce=0)
+            assert torch.equal(d, ref_other[N][0]) and torch.equal(p, ref_other[N][1])
     for bad in [(0, 2), (17, 2), (4, 0), (4, 65)]:
         with pytest.raises(w.WfpgError):
             w.set_tile(g, 16, *bad)
