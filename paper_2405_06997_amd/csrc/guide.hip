@@ -374,8 +374,7 @@ k_guide(SvoView sv, GuideArgs a)
     const int D = sv.depth;
     float *ldir = reinterpret_cast<float *>(smem);
     uint32_t *lq = reinterpret_cast<uint32_t *>(ldir + 3 * NN);
-    constexpr int RW = guide_slot_words(N, MODE, R24) / NN;   // (unused with R24)
-    constexpr int SW = guide_slot_words(N, MODE, R24);         // 32-bit words of one slot's records
+    constexpr int SW = guide_slot_words(N, MODE, R24);   // 32-bit words of one slot's records
     const int nw = blockDim.x / 64;
     uint32_t *recs = lq + 3 * NN + (size_t)wave * S * SW;
     uint32_t *svis = lq + 3 * NN + (size_t)nw * S * SW + (size_t)wave * S;

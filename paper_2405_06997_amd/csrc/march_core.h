@@ -306,7 +306,8 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_fro
 // hit micro_step reaches from the same state, since the neighbour's
 // ancestors are occupied too and the leaf is entered by this crossing (on
 // STEP_HIT the hit is hit_of(s, D)); STEP_CONTINUE otherwise, with s no
-// longer a valid march state.
+// longer a valid march state. The kernels take the state-free form below;
+// this one, built on the march state, is its reference in the host tests.
 template <class Nbr>
 WFPG_HD int first_step(MicroState &s, int D, const Nbr &nbr)
 {
