@@ -41,7 +41,7 @@ CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "5955df5f21d4583b3e943184edcfcceb72b55d4c9f237b53b120adc0b76730ca",
+    "sources_sha256": "ba5c97bc444e128dab8848a8e95f2f08e5cc5662f6005482fc8857c24b718e82",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
         "vop1/vop2/vopc (_e32)": (460, 2, ["add_e32", "xor_e32"]),
@@ -60,7 +60,7 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "5955df5f21d4583b3e943184edcfcceb72b55d4c9f237b53b120adc0b76730ca",
+    "sources_sha256": "ba5c97bc444e128dab8848a8e95f2f08e5cc5662f6005482fc8857c24b718e82",
     "N": 16,
     "tile": {"waves_per_block": 12, "blocks_per_cu": 2},
     "bytes_per_launch": 5032544823,

@@ -104,7 +104,7 @@ constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
 // lane (for the count mode).
 template <int N, int MODE, bool BLUR, bool R24>
 __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, const float *ldir,
-                                         uint32_t *rec, int64_t i, int64_t ps, int lane,
+                                         uint32_t *rec, float *field, int64_t i, int64_t ps, int lane,
                                          int vis_lane)
 {
     constexpr int NN = N * N;
@@ -190,8 +190,8 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
         }
         return;
     }
-    if constexpr (BLUR) {   // the slot's records are consumed: its LDS holds the field
-        float *lv = reinterpret_cast<float *>(rec);
+    if constexpr (BLUR) {   // the slot's records are consumed: its LDS (or the field buffer) holds the field
+        float *lv = R24 ? field : reinterpret_cast<float *>(rec);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) lv[j * 64 + lane] = L[j];
         wave_lds_fence();
@@ -205,7 +205,7 @@ __device__ __forceinline__ void finalize(const SvoView &sv, const GuideArgs &a, 
     if constexpr (MODE == MODE_PRODUCT || MODE == MODE_PEVAL) {
         // the slot's records are consumed: its LDS holds the field for the two levels
         constexpr int SB = N / prod::kCells;
-        float *lv = reinterpret_cast<float *>(rec);
+        float *lv = R24 ? field : reinterpret_cast<float *>(rec);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) lv[j * 64 + lane] = L[j];
         wave_lds_fence();
@@ -364,9 +364,10 @@ k_guide(SvoView sv, GuideArgs a)
 {
     constexpr int NN = N * N;
     constexpr int BPL = NN / 64;
-    constexpr int S = guide_slots(N, R24);
-    static_assert(!R24 || (N == 16 && !BLUR && (MODE == MODE_SAMPLE || MODE == MODE_PDF || MODE == MODE_EVAL)),
-                  "3-byte records: N = 16, sample / pdf / eval, no blur");
+    constexpr bool FIELD = guide_field_buffer(MODE, BLUR, R24);
+    constexpr int S = guide_slots(N, R24, FIELD);
+    static_assert(!R24 || (N == 16 && MODE != MODE_DEBUG && MODE != MODE_COUNT),
+                  "3-byte records: N = 16, not the debug or counting modes");
     extern __shared__ uint64_t smem[];
     if (a.gate && *a.gate == 0) return;   // uniform: every thread reads the same flag
     const int lane = threadIdx.x & 63;
@@ -391,9 +392,11 @@ k_guide(SvoView sv, GuideArgs a)
     // leaf key | occupied << 31)
     int64_t *svert = reinterpret_cast<int64_t *>(reinterpret_cast<uint16_t *>(pm_end) + (size_t)nw * 64) +
                      (size_t)wave * S;
-    uint32_t *sfeed = reinterpret_cast<uint32_t *>(reinterpret_cast<int64_t *>(reinterpret_cast<uint16_t *>(pm_end) +
-                                                                              (size_t)nw * 64) + (size_t)nw * S) +
-                      (size_t)wave * 4;
+    uint32_t *sfeed_all = reinterpret_cast<uint32_t *>(reinterpret_cast<int64_t *>(reinterpret_cast<uint16_t *>(pm_end) +
+                                                                                  (size_t)nw * 64) + (size_t)nw * S);
+    uint32_t *sfeed = sfeed_all + (size_t)wave * 4;
+    // per wave (blur and product modes with 3-byte records): the field buffer
+    float *sfield = FIELD ? reinterpret_cast<float *>(sfeed_all + (size_t)nw * 4) + (size_t)wave * NN : nullptr;
     // The per-vertex finalization reads its arguments from an LDS copy: held
     // in scalar registers across the march loop they overflowed the scalar
     // file and were spilled into vector lanes (two lane moves per use); read
@@ -492,7 +495,7 @@ k_guide(SvoView sv, GuideArgs a)
             const int done = uni((int)__builtin_ctzll(zr));
             vd = uni(svert[done]);
             const int vl = MODE == MODE_COUNT && lane == 0 ? (int)svis[done] : 0;
-            finalize<N, MODE, BLUR, R24>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * SW,
+            finalize<N, MODE, BLUR, R24>(*__builtin_launder(&s_sv), *__builtin_launder(&s_a), ldir, recs + done * SW, sfield,
                                     vd, ps, lane, vl);
             wave_lds_fence();
             if (lane == 0) srem[done] = -1;
@@ -693,14 +696,14 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     if (!a.queue_ctr)
         a.queue_ctr = svo->d_ctr + (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
     const bool blur = a.blur != 0 && mode != MODE_DEBUG && mode != MODE_COUNT;
-    const bool r24 = guide_use_r24(N, mode, blur, svo->total_nodes);
+    const bool r24 = guide_use_r24(N, mode, svo->total_nodes);
     TileConfig t = tc;   // debug records are twice as large: shrink the workgroup if needed
-    while (t.waves_per_block > 1 && guide_lds_bytes(N, t, mode, r24) > guide_max_lds()) --t.waves_per_block;
+    while (t.waves_per_block > 1 && guide_lds_bytes(N, t, mode, r24, blur) > guide_max_lds()) --t.waves_per_block;
     const int W = t.waves_per_block;
     const int64_t want = a.n_dev ? INT64_MAX : ((a.n + kChunk - 1) / kChunk + W - 1) / W;
     const int64_t cap = (int64_t)device_cu_count() * t.blocks_per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
-    const size_t lds = guide_lds_bytes(N, t, mode, r24);
+    const size_t lds = guide_lds_bytes(N, t, mode, r24, blur);
     if (lds > guide_max_lds()) return hipErrorInvalidValue;
     const dim3 blk(64 * W);
     const wfpg::SvoView v = svo->view();
@@ -709,14 +712,15 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
     fn = blur ? (const void *)&k_guide<N, M, true, false> : (const void *)&k_guide<N, M, false, false>
 #define WFPG_PICK24(M)                                                                    \
     if constexpr (N == 16) {                                                              \
-        if (r24) fn = (const void *)&k_guide<N, M, false, true>;                          \
+        if (r24)                                                                          \
+            fn = blur ? (const void *)&k_guide<N, M, true, true> : (const void *)&k_guide<N, M, false, true>; \
     }
     switch (mode) {
     case MODE_SAMPLE: WFPG_PICK(MODE_SAMPLE); WFPG_PICK24(MODE_SAMPLE); break;
     case MODE_PDF: WFPG_PICK(MODE_PDF); WFPG_PICK24(MODE_PDF); break;
     case MODE_EVAL: WFPG_PICK(MODE_EVAL); WFPG_PICK24(MODE_EVAL); break;
-    case MODE_PRODUCT: WFPG_PICK(MODE_PRODUCT); break;
-    case MODE_PEVAL: WFPG_PICK(MODE_PEVAL); break;
+    case MODE_PRODUCT: WFPG_PICK(MODE_PRODUCT); WFPG_PICK24(MODE_PRODUCT); break;
+    case MODE_PEVAL: WFPG_PICK(MODE_PEVAL); WFPG_PICK24(MODE_PEVAL); break;
     case MODE_COUNT: fn = (const void *)&k_guide<N, MODE_COUNT, false, false>; break;
     default: fn = (const void *)&k_guide<N, MODE_DEBUG, false, false>; break;
     }

@@ -116,10 +116,19 @@ hipError_t launch_guide(const struct ::wfpg_svo *svo, int N, int mode, const Gui
 // stays taken until the last ray of its vertex ends, so with few slots a wave
 // runs out of bins to hand out while its slots drain; as many as the LDS holds
 // at six waves per SIMD (1 KiB of records per slot at N = 16, 256 B at N = 8;
-// 768 B at N = 16 with 3-byte records).
-__host__ __device__ constexpr int guide_slots(int N, bool r24 = false)
+// 768 B at N = 16 with 3-byte records, one slot fewer where the wave also
+// holds a field buffer).
+__host__ __device__ constexpr int guide_slots(int N, bool r24 = false, bool field = false)
 {
-    return N >= 32 ? 2 : (N == 16 ? (r24 ? 7 : 5) : 8);
+    return N >= 32 ? 2 : (N == 16 ? (r24 ? (field ? 6 : 7) : 5) : 8);
+}
+
+// With 3-byte records a slot cannot hold the field the blur and the product
+// modes build in the finalization (N*N floats): those take a per-wave field
+// buffer of their own (32-bit words).
+__host__ __device__ constexpr bool guide_field_buffer(int mode, bool blur, bool r24)
+{
+    return r24 && (blur || mode == MODE_PRODUCT || mode == MODE_PEVAL);
 }
 
 // 32-bit words of one bin's hit record: the debug mode keeps the raw
@@ -133,22 +142,23 @@ __host__ __device__ constexpr int guide_slot_words(int N, int mode, bool r24)
     return r24 ? 3 * N * N / 4 : guide_rec_words(mode) * N * N;
 }
 
-// 3-byte records: at N = 16 in the modes whose finalization keeps nothing
-// else in the slot (sample, pdf, eval without blur), for SVOs whose node
-// indices + 1 fit 24 bits.
-inline bool guide_use_r24(int N, int mode, bool blur, int64_t total_nodes)
+// 3-byte records: at N = 16 in every mode but debug and counting, for SVOs
+// whose node indices + 1 fit 24 bits.
+inline bool guide_use_r24(int N, int mode, int64_t total_nodes)
 {
-    return N == 16 && !blur && (mode == MODE_SAMPLE || mode == MODE_PDF || mode == MODE_EVAL) &&
-           total_nodes < (int64_t)0xffffff;
+    return N == 16 && mode != MODE_DEBUG && mode != MODE_COUNT && total_nodes < (int64_t)0xffffff;
 }
 
-inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE, bool r24 = false)
+inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPLE, bool r24 = false,
+                              bool blur = false)
 {
-    const size_t S = (size_t)guide_slots(N, r24), NN = (size_t)N * N;
+    const bool field = guide_field_buffer(mode, blur, r24);
+    const size_t S = (size_t)guide_slots(N, r24, field), NN = (size_t)N * N;
     return NN * 3 * 4 * 2 +
            (size_t)tc.waves_per_block * (S * ((size_t)guide_slot_words(N, mode, r24) * 4 + 8) +   // records, counts
                                          S * (NN / 64) * 8 + 64 * 2 +                            // bin masks, exchange
-                                         S * 8 + 4 * 4);                                         // slot vertices, origin
+                                         S * 8 + 4 * 4 +                                         // slot vertices, origin
+                                         (field ? NN * 4 : 0));                                  // field buffer
 }
 // Dynamic LDS a guide workgroup may use on the current device (all modes but
 // debug): the device's per-workgroup LDS less kGuideStaticLds, a bound on the

@@ -248,7 +248,9 @@ def test_guide_shallow_and_other_depths(orc, w, torch_dev, D):
 def test_guide_large_svo_four_byte_records(orc, w, torch_dev):
     """A room with 400 boxes at depth 10: 22 M nodes, more than 3-byte hit
     records can index, so N = 16 keeps 4-byte records (and five vertex
-    slots); guide_pdf and guide_sample against the oracle."""
+    slots); guide_pdf and guide_sample against the oracle, and the modes whose
+    finalization builds the field in the slot's record memory: guide_pdf
+    with the blur and the product sampler."""
     rs = synth.room(n_boxes=400)
     o = orc.SVO(rs, 10)
     assert sum(o.level_sizes()) >= 0xffffff
@@ -263,6 +265,24 @@ def test_guide_large_svo_four_byte_records(orc, w, torch_dev):
     pos, _, _ = synth.area_points(rs, 192, 18)
     _pdf_compare(o, g, w, torch_dev, pos, 16, C, name="guide_pdf 22M-node room")
     _sample_compare(orc, o, g, w, torch_dev, pos, 16, seed=19, bounce=0, C=C, name="guide_sample 22M-node room")
+    (dpos,) = to_dev(torch_dev, pos)
+    got = w.guide_pdf(g, dpos, w.make_opts(N=16, blur=True)).cpu().numpy().astype(np.float64)
+    L = o.field_aa(pos, 16, blur=True)
+    want = L / L.sum(1, keepdims=True) * 256 / (4 * math.pi)
+    rel = np.abs(got - want) / want
+    bars.record("guide_pdf blur 22M-node room N=16 rel", rel.max(), bars.pdf_bound(16, C))
+    assert rel.max() <= bars.PDF_RTOL, rel.max()
+    nrm = np.random.default_rng(20).normal(size=pos.shape)
+    nrm = (nrm / np.linalg.norm(nrm, axis=0)).astype(np.float32)
+    (dnrm,) = to_dev(torch_dev, nrm)
+    d, p = w.guide_sample_product(g, dpos, w.make_opts(N=16), 21, 1, nrm=dnrm)
+    r = o.product_sample(pos, 16, 21, 1, nrm=nrm)
+    d, p = d.cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64)
+    gb = np.minimum((orc.oct_encode_many(d) * 16).astype(np.int64), 15)
+    same = (gb[0] == r["bin"][:, 0]) & (gb[1] == r["bin"][:, 1])
+    band = (r["margin"] < bars.scan_band_seq(16)).any(1)
+    assert (same | band).all() and same.mean() > 0.99
+    np.testing.assert_allclose(p[same], r["pdf"][same], rtol=bars.PDF_RTOL)
     del o, g
 
 
