@@ -28,29 +28,28 @@ SIMDS = 256 * 4           # 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 
 # VALU issue ceiling of the guide kernel: its own mix of instruction forms,
-# each at its issue cost per wave64 instruction per SIMD: 2 cycles for the
-# one- and two-operand encodings (_e32; 32 lanes per clock, the rate behind
-# the 157.3 TFLOP/s FP32 vector figure) and 4 cycles for the three-operand
-# encoding and 64-bit forms (16 lanes per clock). The issue probe
-# (libwfpg_probe.so, four waves per SIMD on one CU), run live and reported
-# beside it, measures every form at or above these costs except v_bitop3_b32
-# (about 3 cycles; 48 of the 1,275 instructions below, counted at 4).
-# The mix is counted in the compiler listing (hipcc -S of guide.hip) of the
-# eight unrolled steps of the pool loop of k_guide<16, SAMPLE, no blur> (1,275
-# VALU instructions) and describes the sources below only.
+# each at its issue cost per wave64 instruction per SIMD. The issue probe
+# (libwfpg_probe.so, one CU, four waves per SIMD, run live and reported
+# beside the ceiling) splits the forms into two rates whatever their
+# encoding: 32-bit adds and subtracts, logic ops, right shifts, moves and
+# v_bitop3_b32 issue every 2 cycles (32 lanes per clock, the rate behind the
+# 157.3 TFLOP/s FP32 vector figure; the probe reads 2.5-3), and selects on
+# lane masks, compares, left shifts, min/max, 24-bit products, bit-field ops
+# and 64-bit forms every 4 cycles (the probe reads 4.5-5). The mix is counted
+# in the compiler listing (hipcc -S of guide.hip) of the eight unrolled steps
+# of the pool loop of k_guide<16, SAMPLE, no blur, 3-byte records> (1,305 VALU
+# instructions) and describes the sources below only.
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "ba5c97bc444e128dab8848a8e95f2f08e5cc5662f6005482fc8857c24b718e82",
+    "sources_sha256": "bb48df3cb4f6e0e9843c199e2d504a769543d8201409ecf589cc95543632b1bf",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
-        "vop1/vop2/vopc (_e32)": (460, 2, ["add_e32", "xor_e32"]),
-        "v_cndmask_b32_e64": (320, 4, ["cndmask_e64"]),
-        "other three-operand 32-bit": (196, 4, ["bitop3", "lshl_e64"]),
-        "32-bit compares into an SGPR pair": (131, 4, ["cmp_e64"]),
+        "32-bit add / sub / logic / right shift / move / bitop3": (1049, 2, ["add_e32", "xor_e32", "bitop3"]),
+        "other 32-bit (selects, compares, left shifts, min/max, 24-bit products)":
+            (160, 4, ["cndmask_e64", "cmp_e64", "lshl_e64"]),
         "v_mad_u64_u32 / v_mad_i64_i32": (88, 4, ["mad_u64"]),
-        "64-bit compares": (48, 4, ["cmp64_e64"]),
-        "v_lshl_add_u64": (32, 4, ["lshl_add_u64"]),
+        "64-bit adds and compares": (8, 4, ["lshl_add_u64", "cmp64_e64"]),
     },
 }
 
@@ -60,11 +59,11 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "ba5c97bc444e128dab8848a8e95f2f08e5cc5662f6005482fc8857c24b718e82",
+    "sources_sha256": "bb48df3cb4f6e0e9843c199e2d504a769543d8201409ecf589cc95543632b1bf",
     "N": 16,
     "tile": {"waves_per_block": 12, "blocks_per_cu": 2},
-    "bytes_per_launch": 5032544823,
-    "valu_wave_instrs_per_launch": 12454616603,
+    "bytes_per_launch": 5101257051,
+    "valu_wave_instrs_per_launch": 12749626983,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 

@@ -93,6 +93,40 @@ WFPG_HD void split_dir(int q, uint32_t &aq, int &sg)
     sg = (q > 0) - (q < 0);
 }
 
+// Lane conditions of the march step held as 32-bit masks (all ones or zero)
+// in ordinary registers, made from the sign of a difference, and combined and
+// selected with one three-input bitwise operation each: on gfx950 an add, a
+// logic op, a right shift and v_bitop3_b32 issue at twice the rate of a
+// select on a condition register, a compare, a left shift or a min/max.
+// bop3<F>(a, b, c): bit i of the result is bit (a_i << 2 | b_i << 1 | c_i)
+// of the truth table F (the host build evaluates the table).
+template <unsigned F>
+WFPG_HD uint32_t bop3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, F);
+#else
+    uint32_t r = 0;
+    for (unsigned i = 0; i < 8; ++i)
+        if ((F >> i) & 1u) r |= ((i & 4u) ? a : ~a) & ((i & 2u) ? b : ~b) & ((i & 1u) ? c : ~c);
+    return r;
+#endif
+}
+// A value the compiler may not reason about: an empty statement that keeps
+// it in a vector register, so that a sign mask stays a shift (not a compare
+// and a select) and a sum keeps the grouping it is written in.
+template <class T>
+WFPG_HD T opaque(T x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __asm__("" : "+v"(x));
+#endif
+    return x;
+}
+WFPG_HD uint32_t msel(uint32_t m, uint32_t a, uint32_t b) { return bop3<0xCA>(m, a, b); }   // m ? a : b
+WFPG_HD uint32_t neg_mask(int32_t x) { return (uint32_t)(opaque(x) >> 31); }               // x < 0
+WFPG_HD uint32_t neg_mask64(int64_t x) { return neg_mask((int32_t)(uint32_t)((uint64_t)x >> 32)); }
+
 // The traversal is a machine that performs exactly one occupancy test per
 // call, so that the lanes of a wave, each on its own ray, advance in lockstep
 // one test at a time instead of waiting for the longest ancestor walk or
@@ -172,12 +206,13 @@ WFPG_HD void micro_begin(MicroState &s, const uint32_t O[3], uint32_t origin_key
 // bits64(wi) returns 64-bit word wi of the concatenated bitmaps. On STEP_HIT
 // the hit is hit_of(s, D).
 // The first exit crossing of the cell s holds, through its upper face on
-// every axis: along axis e (lane masks m0, m1, m2), at parameter tn / td. The
-// cell entered has corner nlu along e (2^30 when the crossing leaves the cube)
-// and key akey. An axis the ray does not cross (|q| = 0) has lo + size - O >= 1,
-// which only ever meets its zero |q| in the comparisons.
+// every axis: along axis e (c1: axis 1 before axis 0, c2: axis 2 before
+// both, as masks), at parameter tn / td. The cell entered has corner nlu
+// along e (2^30 when the crossing leaves the cube) and key akey. An axis the
+// ray does not cross (|q| = 0) has lo + size - O >= 1, which only ever meets
+// its zero |q| in the comparisons.
 struct Exit {
-    uint32_t m0, m1, m2, le, nlu, akey, tn, td;
+    uint32_t c1, c2, le, nlu, akey, tn, td;
     int e;
 };
 WFPG_HD Exit exit_crossing(const MicroState &s, uint32_t size)
@@ -186,78 +221,87 @@ WFPG_HD Exit exit_crossing(const MicroState &s, uint32_t size)
     const uint32_t dl0 = s.lo0 + size - s.O0;
     const uint32_t dl1 = s.lo1 + size - s.O1;
     const uint32_t dl2 = s.lo2 + size - s.O2;
-    // axis choice as lane masks (selects between the three axes' registers
-    // compiled to a stack array indexed by the axis)
-    const uint32_t C1 = (uint64_t)dl1 * s.aq0 < (uint64_t)dl0 * s.aq1 ? ~0u : 0u;   // axis 1 before axis 0
-    const uint32_t D01 = (dl1 & C1) | (dl0 & ~C1), Q01 = (s.aq1 & C1) | (s.aq0 & ~C1);
-    const uint32_t C2 = (uint64_t)dl2 * Q01 < (uint64_t)D01 * s.aq2 ? ~0u : 0u;      // axis 2 before both
-    x.m0 = ~C1 & ~C2;
-    x.m1 = C1 & ~C2;
-    x.m2 = C2;
-    x.e = (int)((x.m1 & 1u) | (x.m2 & 2u));
-    x.le = (s.lo0 & x.m0) | (s.lo1 & x.m1) | (s.lo2 & x.m2);
+    // axis 1 before axis 0 iff dl1 |q0| - dl0 |q1| < 0 (dl <= 2^30, |q| <= 2^23:
+    // the difference is exact in 64 bits)
+    x.c1 = neg_mask64((int64_t)((uint64_t)dl1 * s.aq0) + (int64_t)(int32_t)dl0 * (int64_t)(0 - (int32_t)s.aq1));
+    const uint32_t D01 = msel(x.c1, dl1, dl0), Q01 = msel(x.c1, s.aq1, s.aq0);
+    x.c2 = neg_mask64((int64_t)((uint64_t)dl2 * Q01) + (int64_t)(int32_t)D01 * (int64_t)(0 - (int32_t)s.aq2));
+    x.e = (int)(bop3<0x58>(x.c2, x.c1, 1u) & 3u);   // c2 ? 2 : (c1 ? 1 : 0)
+    x.le = msel(x.c2, s.lo2, msel(x.c1, s.lo1, s.lo0));
     // one cell up along the crossed axis (|q| > 0); leaving the cube reaches 2^30
     x.nlu = x.le + size;
-    const uint32_t m = 0x09249249u << x.e;   // the key bits of axis e: add one to them
-    x.akey = ((((s.key | ~m) + 1u) & m)) | (s.key & ~m);
-    x.tn = (dl2 & x.m2) | (D01 & ~x.m2);
-    x.td = (s.aq2 & x.m2) | (Q01 & ~x.m2);
+    const uint32_t m = 0x24924924u >> (2 - x.e);   // the key bits of axis e: add one to them
+    x.akey = msel(m, bop3<0xF3>(s.key, m, m) + 1u, s.key);   // (key | ~m) + 1 on those bits
+    x.tn = msel(x.c2, dl2, D01);
+    x.td = msel(x.c2, s.aq2, Q01);
     return x;
 }
 
 template <class Bits64>
 WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_from, int &vis)
 {
-    // PH_ADVANCE: leave the current cell through its first exit crossing.
-    const bool adv = s.phase == PH_ADVANCE;
-    const uint32_t size = 1u << (kFine - s.lvl);
-    const Exit x = exit_crossing(s, size);
-    const bool miss = adv & (x.nlu >= (1u << kFine));
-    // first level not shared with the cell left (le and nlu differ at level lvl, so ch >= 1)
-    const uint32_t ch = (x.le ^ x.nlu) >> (kFine - s.lvl);
-    const int al = s.lvl - (31 - __builtin_clz(ch));
-    s.lo0 = adv & (x.m0 != 0u) ? x.nlu : s.lo0;
-    s.lo1 = adv & (x.m1 != 0u) ? x.nlu : s.lo1;
-    s.lo2 = adv & (x.m2 != 0u) ? x.nlu : s.lo2;
-    s.key = adv ? x.akey : s.key;
-    s.tn = adv ? x.tn : s.tn;
-    s.td = adv ? x.td : s.td;
-    s.ta = adv ? x.e : s.ta;
-    const int l = adv ? al : s.l;
-    const bool path = adv || s.phase == PH_PATH;
-
-    // PH_DESCEND candidate: the child the ray is in just after the current
-    // crossing tn/td. Along axis j the mid-plane M counts as crossed iff its
+    const uint32_t advm = neg_mask(s.phase - PH_PATH);    // PH_ADVANCE
+    const uint32_t pathm = neg_mask(s.phase - PH_DESCEND);  // PH_ADVANCE or PH_PATH
+    const uint32_t size = (1u << kFine) >> s.lvl;
+    // PH_DESCEND candidate (taken from the state before the advance below,
+    // which leaves a descending lane's state as it is, so that the two are
+    // independent): the child the ray is in just after the current crossing
+    // tn/td. Along axis j the mid-plane M counts as crossed iff its
     // parameter is smaller, or equal with j not above ta: with d = M - O,
     // iff d td < tn |q_j| + k (k = 1 when j is not above ta), i.e. iff
-    // P = tn |q_j| + k - d td > 0, one signed 32 x 32 + 64 product-add
-    // (td < 2^24); a plane behind the origin (d < 0) gives P > 0. A point on
-    // the plane (d = 0) of an axis that is not mirrored is in the upper half
-    // (the half-open cells of the original frame); that decides only where
-    // tn |q_j| = 0 (at the origin, or with no motion along j, where O >= M
-    // is the whole rule), and there k = 1 gives it.
+    // P = tn |q_j| + k - d td > 0, iff tn |q_j| + (k - 1) - d td >= 0: one
+    // 32 x 32 + 64 product-add and one signed one (td < 2^24), the sign of the
+    // sum giving the mask of the lower half; a plane behind the origin (d < 0)
+    // gives P > 0. A point on the plane (d = 0) of an axis that is not
+    // mirrored is in the upper half (the half-open cells of the original
+    // frame); that decides only where tn |q_j| = 0 (at the origin, or with no
+    // motion along j, where O >= M is the whole rule), and there k = 1 gives it.
     const uint32_t half = size >> 1;
     const int32_t nd0 = (int32_t)(s.O0 - s.lo0 - half);   // -d
     const int32_t nd1 = (int32_t)(s.O1 - s.lo1 - half);
     const int32_t nd2 = (int32_t)(s.O2 - s.lo2 - half);
     const int64_t td = (int64_t)(int32_t)s.td;
     // k_j as bits: bit j of K (j not above ta: the low ta + 1 bits; an axis
-    // without motion; a non-mirrored axis while tn = 0)
-    const uint32_t K = ((1u << (s.ta + 1)) - 1u) | (s.mir >> 3) | (s.tn == 0u ? ~s.mir & 7u : 0u);
-    const uint32_t k0 = K & 1u, k1 = (K >> 1) & 1u, k2 = (K >> 2) & 1u;
-    const bool u0 = (int64_t)nd0 * td + (int64_t)((uint64_t)s.tn * s.aq0 + k0) > 0;
-    const bool u1 = (int64_t)nd1 * td + (int64_t)((uint64_t)s.tn * s.aq1 + k1) > 0;
-    const bool u2 = (int64_t)nd2 * td + (int64_t)((uint64_t)s.tn * s.aq2 + k2) > 0;
-    const uint32_t dk = (s.key << 3) | (u0 ? 1u : 0u) | (u1 ? 2u : 0u) | (u2 ? 4u : 0u);
+    // without motion; a non-mirrored axis while tn = 0, tn <= 2^30)
+    const uint32_t K = bop3<0xFE>(7u >> (2 - s.ta), s.mir >> 3, bop3<0x20>(neg_mask((int32_t)s.tn - 1), s.mir, 7u));
+    // -d td + (k_j - 1) (k_j - 1 is 0 or -1), then + tn |q_j|: the mask of
+    // the lower half (the plane not crossed) on each axis
+    auto lower = [&](int32_t nd, uint32_t kbit, uint32_t aq) {
+        const int64_t a = opaque((int64_t)nd * td + (int64_t)(int32_t)neg_mask((int32_t)kbit - 1));
+        return neg_mask64((int64_t)((uint64_t)s.tn * aq + (uint64_t)a));
+    };
+    const uint32_t lo0m = lower(nd0, K & 1u, s.aq0);
+    const uint32_t lo1m = lower(nd1, K & 2u, s.aq1);
+    const uint32_t lo2m = lower(nd2, K & 4u, s.aq2);
+    // the child key: bit j set where the plane is crossed
+    const uint32_t dk = (s.key << 3) | (bop3<0xB1>(bop3<0x1B>(lo0m, lo1m, 1u), lo2m, 3u) & 7u);
+
+    // PH_ADVANCE: leave the current cell through its first exit crossing.
+    const Exit x = exit_crossing(s, size);
+    const uint32_t missm = advm & neg_mask((int32_t)((1u << kFine) - 1u - x.nlu));   // nlu < 2^31
+    // first level not shared with the cell left: le and nlu differ first in
+    // bit 30 - al (at level lvl or above, so al <= lvl)
+    const int cz = __builtin_clz(x.le ^ x.nlu);   // al = cz - 1
+    s.lo0 = msel(bop3<0x10>(advm, x.c1, x.c2), x.nlu, s.lo0);   // adv & ~c1 & ~c2
+    s.lo1 = msel(bop3<0x40>(advm, x.c1, x.c2), x.nlu, s.lo1);   // adv & c1 & ~c2
+    s.lo2 = msel(advm & x.c2, x.nlu, s.lo2);
+    s.key = msel(advm, x.akey, s.key);
+    s.tn = msel(advm, x.tn, s.tn);
+    s.td = msel(advm, x.td, s.td);
+    s.ta = (int)msel(advm, (uint32_t)x.e, (uint32_t)s.ta);
+    const int l = (int)msel(advm, (uint32_t)(cz - 1), (uint32_t)s.l);
 
     // The levels tested: the window [ws, T] of the path (ancestors of the
-    // entered cell at level lvl, l <= lvl), or the child's level. A lane that
-    // left the cube tests the root instead (its stepped key is out of range).
-    // Levels are < 16: masked so that the products by 3 stay 24-bit ones.
-    const int Tp = l + 2 < s.lvl ? l + 2 : s.lvl;
-    const int T = (miss ? 0 : (path ? Tp : s.lvl + 1)) & 15;
-    const int ws = miss ? 0 : (path ? l : T);
-    const uint32_t tk = miss ? 0u : (path ? s.key >> ((3 * ((s.lvl - Tp) & 15)) & 31) : dk);
+    // entered cell at level lvl, l <= lvl, T = min(l + 2, lvl) = lvl - dsh),
+    // or the child's level. A lane that left the cube tests the root instead
+    // (its stepped key is out of range).
+    const int dp = (int)msel(advm, (uint32_t)(s.lvl - 1 - cz), (uint32_t)(s.lvl - 2 - s.l));
+    const uint32_t dsh = (uint32_t)(dp > 0 ? dp : 0) & 15u;   // levels are < 16
+    const int Tp = s.lvl - (int)dsh;
+    const int T = (int)bop3<0x20>(msel(pathm, (uint32_t)Tp, (uint32_t)(s.lvl + 1)), missm, 15u);   // & ~miss & 15
+    const uint32_t pnm = bop3<0x30>(pathm, missm, missm);   // path & ~miss
+    const int ws = (int)msel(pnm, (uint32_t)l, (uint32_t)T);   // ws <= T
+    const uint32_t tk = msel(pnm, s.key >> ((3 * dsh) & 31), bop3<0x30>(dk, missm, missm));
     // the word of level wl = max(T, 2) holding the cell (original frame;
     // level D itself on SVOs of depth 1), read as two 32-bit halves
     const int w2 = D < 2 ? D : 2;
@@ -265,36 +309,43 @@ WFPG_HD int micro_step(MicroState &s, int D, const Bits64 &bits64, int count_fro
     const uint32_t ko = (tk ^ (s.flip >> (kFine - 3 * T))) << (3 * ((wl - T) & 3));
     const uint64_t W = bits64(woff(wl) + (ko >> 6));
     const uint32_t wlo = (uint32_t)W, whi = (uint32_t)(W >> 32);
-    const uint32_t wh = (ko & 32u) ? whi : wlo;                   // the half holding the cell
-    const bool o0 = (wlo | whi) != 0u;                            // level wl - 2
-    const bool o1 = ((wh >> (ko & 0x18u)) & 0xffu) != 0u;         // level wl - 1
-    const bool o2 = ((wh >> (ko & 31u)) & 1u) != 0u;              // level wl
-    // the first empty level of the window (-1: all occupied)
-    const bool f0 = wl - 2 >= ws && !o0;
-    const bool f1 = wl - 1 >= ws && wl - 1 <= T && !o1;
-    const bool f2 = wl <= T && !o2;
-    const int ee = f0 ? wl - 2 : (f1 ? wl - 1 : (f2 ? wl : -1));
+    const uint32_t wh = msel(((ko >> 5) & 1u) - 1u, wlo, whi);   // the half holding the cell
+    // occupancy of levels wl - 2 (the word), wl - 1 (its byte) and wl (its
+    // bit) as 0 / 1; each implies the one before, so the first empty level of
+    // the three is wl - 2 + o0 + o1 + o2 (wl + 1: none)
+    const uint32_t ow = wlo | whi;
+    const uint32_t o0 = ((0u - ow) | ow) >> 31;
+    const uint32_t o1 = ((opaque(wh >> (ko & 0x18u)) & 0xffu) + 0xffu) >> 8;
+    const uint32_t o2 = opaque(wh >> (ko & 31u)) & 1u;
+    // the first empty level of the window [ws, T] (-1: all occupied)
+    const int fe = wl - 2 + (int)(o0 + o1 + o2);
+    const int c = fe > ws ? fe : ws;
+    const uint32_t fullm = neg_mask(T - fe);   // T < c, as ws <= T
+    const int ee = (int)((uint32_t)c | fullm);
     const int last = ee >= 0 ? ee : T;
     const int from = ws > count_from ? ws : count_from;
-    vis += (!miss && last >= from) ? last - from + 1 : 0;
+    vis += (missm == 0u && last >= from) ? last - from + 1 : 0;
 
     // The new cell: on the path the ancestor at the first empty level (the
     // entered cell itself when the window is all occupied); in a descent the
     // child. Its corner: the old corner cut to its level, with the child's
     // half added on each axis for a child.
-    const bool full = ee < 0;
-    const int nl = path ? (full ? s.lvl : ee) : s.lvl + 1;
-    const uint32_t MK = ~((1u << (kFine - nl)) - 1u);
-    s.lo0 = (s.lo0 & MK) | (!path & u0 ? half : 0u);
-    s.lo1 = (s.lo1 & MK) | (!path & u1 ? half : 0u);
-    s.lo2 = (s.lo2 & MK) | (!path & u2 ? half : 0u);
-    s.key = path ? s.key >> ((3 * ((s.lvl - nl) & 15)) & 31) : dk;
-    const bool at_cell = !path || T == s.lvl;   // the window reached the cell itself
+    const int nl = (int)msel(pathm, msel(fullm, (uint32_t)s.lvl, (uint32_t)c), (uint32_t)(s.lvl + 1));
+    const uint32_t MK = 0u - ((1u << kFine) >> nl);
+    s.lo0 = bop3<0xEA>(s.lo0, MK, bop3<0x10>(half, pathm, lo0m));   // (lo & MK) | (half & ~path & ~lower)
+    s.lo1 = bop3<0xEA>(s.lo1, MK, bop3<0x10>(half, pathm, lo1m));
+    s.lo2 = bop3<0xEA>(s.lo2, MK, bop3<0x10>(half, pathm, lo2m));
+    s.key = msel(pathm, s.key >> ((3 * ((s.lvl - nl) & 15)) & 31), dk);
+    // the window did not reach the cell itself (path lanes only; a descent has T = lvl + 1)
+    const uint32_t shortm = neg_mask(T - s.lvl);
+    const int lvl0 = s.lvl;
     s.lvl = nl;
-    s.phase = !full ? PH_ADVANCE : (at_cell ? PH_DESCEND : PH_PATH);
+    s.phase = (int)(bop3<0x90>(fullm, shortm, 1u) & 3u);   // full ? (short ? PH_PATH : PH_DESCEND) : PH_ADVANCE
     s.l = T + 1;
-    if (miss) return STEP_MISS;
-    return full && at_cell && nl == D ? STEP_HIT : STEP_CONTINUE;
+    // STEP_MISS, else STEP_HIT where the full window reached the leaf (the
+    // new level of a full window is lvl on the path, lvl + 1 in a descent)
+    const uint32_t hitm = bop3<0x10>(fullm, shortm, neg_mask((int)msel(pathm, (uint32_t)lvl0, (uint32_t)(lvl0 + 1)) - D));
+    return (int)(bop3<0x58>(missm, hitm, 1u) & 3u);   // miss ? 2 : (hit ? 1 : 0)
 }
 
 // The first step from an occupied origin leaf (the state micro_begin leaves),
