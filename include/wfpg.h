@@ -243,14 +243,14 @@ wfpg_status guide_sample(const wfpg_svo *svo, const float *pos, const float *nrm
  * allocating library routine; the caller passes inputs and outputs as for
  * guide_sample and gets the same results bit for bit (same kernels).
  *
- * Its scratch is one static device array of 16,640 bytes per GPU, held
+ * Its scratch is one static device array of 17,408 bytes per GPU, held
  * until the process ends: the bin-direction tables of N = 8, 16 and 32 and
- * the vertex-queue counter. The first call on a device, with that device
+ * the vertex-queue counters. The first call on a device, with that device
  * current, looks the array up and uploads the tables synchronously (make
  * that first call before capturing a graph); later calls only enqueue a
  * counter reset (a kernel, not a memset) and the guide kernel on the stream.
  * Every call on a GPU shares that array: calls that overlap on one GPU
- * (concurrent streams) race on the counter and must be ordered by the
+ * (concurrent streams) race on the counters and must be ordered by the
  * caller.
  * Errors: as guide_sample; EINVAL for N beyond the tables (not 8, 16 or
  * 32); EUNSUPPORTED for mode 1 (the learned form keeps working buffers).

@@ -238,7 +238,8 @@ wfpg_status svo_build(const wfpg_rect *rects, int64_t n_rects, int32_t depth, in
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_rank, svo->total_words * sizeof(uint32_t)));
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_dropped, 2 * sizeof(unsigned long long)));
     if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_err, sizeof(int32_t)));
-    if (e == hipSuccess) e = NOTE(hipMalloc((void **)&svo->d_ctr, kCounterPool * sizeof(unsigned long long)));
+    if (e == hipSuccess)
+        e = NOTE(hipMalloc((void **)&svo->d_ctr, (size_t)kCounterPool * kQueueRanges * kQueueStride * sizeof(unsigned long long)));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_bits, 0, svo->total_words * sizeof(uint64_t), s));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_dropped, 0, 2 * sizeof(unsigned long long), s));
     if (e == hipSuccess) e = NOTE(hipMemsetAsync(svo->d_err, 0, sizeof(int32_t), s));
@@ -516,8 +517,8 @@ namespace {
 constexpr size_t kNaTabFloats[3] = {8 * 8 * 3, 16 * 16 * 3, 32 * 32 * 3};
 constexpr size_t kNaTabOff[3] = {0, 8 * 8 * 3, 8 * 8 * 3 + 16 * 16 * 3};   // floats
 constexpr size_t kNaCounterOff = 16384;                                  // bytes (tables: 16128)
-constexpr size_t kNaScratchBytes = kNaCounterOff + 256;
-static_assert((kNaTabOff[2] + kNaTabFloats[2]) * sizeof(float) <= kNaCounterOff, "tables overlap the counter");
+constexpr size_t kNaScratchBytes = kNaCounterOff + kQueueRanges * kQueueStride * 8;
+static_assert((kNaTabOff[2] + kNaTabFloats[2]) * sizeof(float) <= kNaCounterOff, "tables overlap the counters");
 
 static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
 
@@ -564,7 +565,7 @@ extern "C" wfpg_status guide_sample_noalloc(const wfpg_svo *svo, const float *po
     GuideArgs a = base_args(svo, opts, false);
     const int k = opts->N == 8 ? 0 : (opts->N == 16 ? 1 : 2);
     a.dirtab = reinterpret_cast<const float *>(sp) + kNaTabOff[k];
-    a.queue_ctr = reinterpret_cast<unsigned long long *>(sp + kNaCounterOff);   // reset by the launch
+    a.queue_ctr = reinterpret_cast<unsigned long long *>(sp + kNaCounterOff);   // the counters, reset by the launch
     a.pos = pos;
     a.n = n;
     a.seed = seed;

@@ -17,7 +17,7 @@ using namespace wfpg;
 struct wfpg_bounce_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    unsigned long long *d_ctr = nullptr;   // one queue counter per bounce
+    unsigned long long *d_ctr = nullptr;   // the queue counters of each bounce
 };
 
 namespace {
@@ -52,7 +52,7 @@ wfpg_status wfpg_graph_create(const wfpg_svo *svo, int32_t n_bounces, const floa
     if (!g) return WFPG_ENOMEM;
     hipStream_t user = (hipStream_t)hip_stream;
     hipStream_t cs = nullptr;
-    hipError_t e = hipMalloc((void **)&g->d_ctr, n_bounces * sizeof(unsigned long long));
+    hipError_t e = hipMalloc((void **)&g->d_ctr, (size_t)n_bounces * kQueueRanges * kQueueStride * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamSynchronize(user);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -74,7 +74,7 @@ wfpg_status wfpg_graph_create(const wfpg_svo *svo, int32_t n_bounces, const floa
             a.pdf_out = pdf_out[b];
             a.dirtab = device_dirtab(N[b]);
             a.err = svo->d_err;
-            a.queue_ctr = g->d_ctr + b;
+            a.queue_ctr = g->d_ctr + (size_t)kQueueRanges * kQueueStride * b;
             e = launch_guide(svo, N[b], MODE_SAMPLE, a, choose_tile(svo, N[b]), cs);
         }
         hipGraph_t graph = nullptr;

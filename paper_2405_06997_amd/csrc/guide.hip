@@ -96,7 +96,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 constexpr int kMicro = 8;
 
 constexpr uint32_t kMissRec = 0xffffffffu;
-constexpr int kChunk = 8;   // vertices taken from the queue counter at a time
+constexpr int kChunk = 8;   // vertices taken from a queue counter at a time
 
 // Per-vertex finalization (wave-wide): footprint level, node, side and value
 // of every bin from the hit records in `rec`, then the row / marginal CDFs
@@ -349,7 +349,8 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 // A wave keeps up to S = guide_slots(N, R24) query vertices in flight. Idle
 // lanes take the next unmarched bin of the vertex being fed; when it has no
 // bins left a free slot is opened for the next vertex of the queue (taken
-// from a device counter, kChunk at a time), so lanes rarely wait for another
+// kChunk at a time from the counter of one of kQueueRanges contiguous ranges
+// of the queue, the workgroup's XCD's first), so lanes rarely wait for another
 // vertex's longest rays. A slot whose bins are all finished is finalized by
 // the whole wave (values, CDF, sample) and freed. Slot bookkeeping is
 // wave-uniform; the per-slot arrays in registers are only ever indexed by
@@ -440,6 +441,9 @@ k_guide(SvoView sv, GuideArgs a)
     int64_t chunk_next = 0;
     int chunk_left = 0;
     bool exhausted = false;
+    // the queue range taken from (this workgroup's XCD's first) and how many
+    // ranges were found exhausted
+    int xr = (int)(blockIdx.x % (unsigned)kQueueRanges), xdone = 0;
     // the bins each slot has not finished, the slots' vertices and the fed
     // vertex's origin live in LDS (scalar registers are the kernel's scarcest
     // resource); a finishing lane takes its bin off its slot's count
@@ -509,12 +513,19 @@ k_guide(SvoView sv, GuideArgs a)
                 if (fr == 0ull || exhausted) break;
                 const int f = uni((int)__builtin_ctzll(fr));
                 if (chunk_left == 0) {
-                    int64_t b = 0;
-                    if (lane == 0) b = (int64_t)atomicAdd(__builtin_launder(&s_a)->queue_ctr, (unsigned long long)kChunk);
-                    b = uni(shfl64(b, 0));
-                    if (b >= n) { exhausted = true; break; }
+                    int64_t b = 0, hi = 0;
+                    for (;;) {   // the next chunk of range xr, else of the next range
+                        const int64_t lo = n * xr / kQueueRanges;
+                        hi = n * (xr + 1) / kQueueRanges;
+                        if (lane == 0)
+                            b = (int64_t)atomicAdd(__builtin_launder(&s_a)->queue_ctr + xr * kQueueStride, (unsigned long long)kChunk);
+                        b = uni(shfl64(b, 0)) + lo;
+                        if (b < hi || ++xdone == kQueueRanges) break;
+                        xr = (xr + 1) % kQueueRanges;
+                    }
+                    if (b >= hi) { exhausted = true; break; }
                     chunk_next = b;
-                    chunk_left = uni((int)min((int64_t)kChunk, n - b));
+                    chunk_left = uni((int)min((int64_t)kChunk, hi - b));
                 }
                 const int64_t vi = chunk_next++;
                 --chunk_left;
@@ -685,7 +696,7 @@ k_guide(SvoView sv, GuideArgs a)
 
 __global__ void k_reset_counter(unsigned long long *ctr)
 {
-    *ctr = 0ull;
+    if (threadIdx.x < kQueueRanges) ctr[threadIdx.x * kQueueStride] = 0ull;
 }
 
 template <int N>
@@ -694,7 +705,7 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
 {
     GuideArgs a = a0;
     if (!a.queue_ctr)
-        a.queue_ctr = svo->d_ctr + (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
+        a.queue_ctr = svo->d_ctr + (size_t)kQueueRanges * kQueueStride * (svo->ctr_next.fetch_add(1u) % (unsigned)kCounterPool);
     const bool blur = a.blur != 0 && mode != MODE_DEBUG && mode != MODE_COUNT;
     const bool r24 = guide_use_r24(N, mode, svo->total_nodes);
     TileConfig t = tc;   // debug records are twice as large: shrink the workgroup if needed
@@ -737,7 +748,7 @@ hipError_t launch_n(const wfpg_svo *svo, int mode, const GuideArgs &a0, const Ti
             opted[m].store(true);
         }
     }
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.queue_ctr);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, a.queue_ctr);
     void *args[] = {(void *)&v, (void *)&a};
     const hipError_t e = hipLaunchKernel(fn, dim3(grid), blk, args, lds, s);
     if (e != hipSuccess) return e;

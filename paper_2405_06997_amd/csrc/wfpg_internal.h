@@ -93,7 +93,7 @@ struct GuideArgs {
     int32_t *dbg_visits;
     const float *dirtab;      // N*N*3 FP32 bin centres
     int32_t *err;             // device error flags
-    unsigned long long *queue_ctr;   // vertex queue counter (reset before each launch)
+    unsigned long long *queue_ctr;   // kQueueRanges vertex-queue counters (reset before each launch)
     const int32_t *gate;             // optional: the kernel does nothing unless *gate != 0
     const float *nrm_in;      // product modes: SoA normals (Lambertian table) or NULL
     const float *bsdf_in;     // product modes: n x 64 BSDF tables or NULL
@@ -166,6 +166,18 @@ inline size_t guide_lds_bytes(int N, const TileConfig &tc, int mode = MODE_SAMPL
 constexpr size_t kGuideStaticLds = 1024;
 size_t guide_max_lds();
 constexpr int kCounterPool = 64;   // concurrent guide launches per SVO with distinct counters
+// The guide kernel splits its vertex queue into this many contiguous ranges,
+// one per XCD (workgroups are dispatched to the XCDs round robin, so
+// workgroup b runs on XCD b mod 8), each with its own counter: the vertices
+// one XCD works on at a time are neighbours in the queue (neighbouring
+// pixels of a camera queue), whose rays read the same occupancy words, so
+// its L2 and its CUs' L1s see a narrow front of the queue instead of a
+// slice of every XCD's. A workgroup takes from its own range first, then
+// from the others in turn; results do not depend on the order. The counters
+// sit kQueueStride words apart, each on its own 128-byte line (sharing one
+// line, the XCDs' atomics on it contended).
+constexpr int kQueueRanges = 8;
+constexpr int kQueueStride = 16;
 
 // Tile chosen for (device, N, depth, format): the autotuned one if present.
 TileConfig choose_tile(const struct ::wfpg_svo *svo, int N);
