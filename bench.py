@@ -42,7 +42,7 @@ CLOCK_HZ = 2.4e9          # peak engine clock (cancels in the VALU fraction)
 PROBE_FORMS = ["add_e32", "xor_e32", "cndmask_e64", "cmp_e64", "cmp64_e64", "mad_u64", "lshl_add_u64",
                "bitop3", "lshl_e64"]
 GUIDE_STEP_MIX = {
-    "sources_sha256": "46294a5ecf292879086c93e7f654483b3f3dc98607708a42b9955316c81b65cc",
+    "sources_sha256": "c6379962211547571b1be6b9d62057aaa8ddce3e8209bdac25d3bb9e11a2c879",
     # class: (instructions in the listing, issue cycles, probe forms of the class)
     "classes": {
         "32-bit add / sub / logic / right shift / move / bitop3": (1049, 2, ["add_e32", "xor_e32", "bitop3"]),
@@ -59,11 +59,11 @@ GUIDE_STEP_MIX = {
 # profiles/k_guide_sample_room_d10_n16_counters.md. It describes the kernel
 # sources it was taken on and the default tile, and is reported only for them.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "46294a5ecf292879086c93e7f654483b3f3dc98607708a42b9955316c81b65cc",
+    "sources_sha256": "c6379962211547571b1be6b9d62057aaa8ddce3e8209bdac25d3bb9e11a2c879",
     "N": 16,
     "tile": {"waves_per_block": 12, "blocks_per_cu": 2},
-    "bytes_per_launch": 2000081495,
-    "valu_wave_instrs_per_launch": 12723991324,
+    "bytes_per_launch": 1570617035,
+    "valu_wave_instrs_per_launch": 12664715492,
 }
 KERNEL_SOURCES = ["guide.hip", "march_core.h", "wfpg_internal.h", "product_core.h", "antialias_core.h"]
 

@@ -96,7 +96,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 constexpr int kMicro = 8;
 
 constexpr uint32_t kMissRec = 0xffffffffu;
-constexpr int kChunk = 8;   // vertices taken from a queue counter at a time
+constexpr int kChunk = 4;   // vertices taken from a queue counter at a time (8 and 16 were slower)
 
 // Per-vertex finalization (wave-wide): footprint level, node, side and value
 // of every bin from the hit records in `rec`, then the row / marginal CDFs
